@@ -1,0 +1,146 @@
+"""CPU oracle for the threshold sampler - TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path never does.
+
+``oracle.c`` (built to ``liboracle.so`` by ``__graft_entry__.build()``) is a
+single sequential loop in the paper's counter form (section 3.2 for sampling,
+3.3 for sample contents, 3.4 for the leak rule and score, 3.5 for copy volume,
+2.1 for the Python/native time split).  This module only marshals arguments.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, EOVERFLOW, ENOMEM = 0, 1, 6, 7
+OPT_PRIME_T, OPT_RESOLVE_AT_END = 1, 2
+
+HIST_NAMES = (
+    "py_bytes", "nat_bytes", "growth_n", "shrink_n", "growth_bytes", "shrink_bytes",
+    "leak_mallocs", "leak_frees", "copy_sampled", "copy_exact", "py_time_us", "nat_time_us",
+)
+
+SAMPLE_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("F", "<i8"), ("py", "<i8"), ("nat", "<i8")])
+TRACKED_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("ptr", "<u4"), ("freed", "<u4")])
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("threshold", ctypes.c_int64),
+        ("copy_threshold", ctypes.c_int64),
+        ("num_lines", ctypes.c_uint32),
+        ("quantum_us", ctypes.c_uint32),
+        ("options", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("num_lines", ctypes.c_uint32),
+        ("threshold_used", ctypes.c_int64),
+        ("n_samples", ctypes.c_uint64),
+        ("n_tracked", ctypes.c_uint64),
+        ("final_F", ctypes.c_int64),
+        ("peak_F", ctypes.c_int64),
+        ("peak_sampled_F", ctypes.c_int64),
+        ("samples", ctypes.c_void_p),
+        ("tracked", ctypes.c_void_p),
+        ("hist", ctypes.c_void_p),
+        ("samples_cap", ctypes.c_uint64),
+        ("tracked_cap", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.oracle_run.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(_Params),
+                                 ctypes.POINTER(ctypes.POINTER(_Result))]
+        L.oracle_run.restype = ctypes.c_int
+        L.oracle_free.argtypes = [ctypes.POINTER(_Result)]
+        L.oracle_free.restype = None
+        L.oracle_prime_at_least.argtypes = [ctypes.c_int64]
+        L.oracle_prime_at_least.restype = ctypes.c_int64
+        p64 = ctypes.POINTER(ctypes.c_int64)
+        p8 = ctypes.POINTER(ctypes.c_uint8)
+        L.oracle_leak_scores.argtypes = [p64, p64, ctypes.c_uint32, p64, p64, p64, p64, p8, p8]
+        L.oracle_leak_scores.restype = None
+        _lib = L
+    return _lib
+
+
+def prime_at_least(t: int) -> int:
+    return int(lib().oracle_prime_at_least(t))
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def leak_scores(mallocs, frees):
+    """Exact reduced rationals (Laplace and as-printed) and 95 % gates per line."""
+    m = np.ascontiguousarray(mallocs, dtype=np.int64)
+    f = np.ascontiguousarray(frees, dtype=np.int64)
+    n = m.shape[0]
+    out = {k: np.empty(n, np.int64) for k in ("lap_num", "lap_den", "lit_num", "lit_den")}
+    out["lap_gate"] = np.empty(n, np.uint8)
+    out["lit_gate"] = np.empty(n, np.uint8)
+    lib().oracle_leak_scores(_ptr(m, ctypes.c_int64), _ptr(f, ctypes.c_int64), n,
+                             _ptr(out["lap_num"], ctypes.c_int64), _ptr(out["lap_den"], ctypes.c_int64),
+                             _ptr(out["lit_num"], ctypes.c_int64), _ptr(out["lit_den"], ctypes.c_int64),
+                             _ptr(out["lap_gate"], ctypes.c_uint8), _ptr(out["lit_gate"], ctypes.c_uint8))
+    return out
+
+
+def run(events, threshold, num_lines, copy_threshold=None, quantum_us=10_000, options=0):
+    """Run the sequential sampler over a 24-byte-record event array.
+
+    Returns a dict: status, samples (SAMPLE_DTYPE), tracked (TRACKED_DTYPE), the
+    twelve per-line int64 arrays, final_F, peak_F, peak_sampled_F,
+    threshold_used, K, H and the leak rationals/gates.
+    """
+    ev = np.ascontiguousarray(events)
+    if ev.dtype.itemsize != 24:
+        raise ValueError("events must be 24-byte records")
+    p = _Params(int(threshold), int(copy_threshold if copy_threshold is not None else threshold),
+                int(num_lines), int(quantum_us), int(options), 0)
+    rp = ctypes.POINTER(_Result)()
+    lib().oracle_run(ev.ctypes.data if ev.size else None, ev.shape[0], ctypes.byref(p), ctypes.byref(rp))
+    try:
+        r = rp.contents
+        out = {"status": int(r.status), "threshold_used": int(r.threshold_used)}
+        if r.status != OK:
+            return out
+        K, H, L = int(r.n_samples), int(r.n_tracked), int(r.num_lines)
+        out["K"], out["H"] = K, H
+        out["samples"] = (np.ctypeslib.as_array(ctypes.cast(r.samples, ctypes.POINTER(ctypes.c_uint8)),
+                                                shape=(K * SAMPLE_DTYPE.itemsize,)).view(SAMPLE_DTYPE).copy()
+                          if K else np.zeros(0, SAMPLE_DTYPE))
+        out["tracked"] = (np.ctypeslib.as_array(ctypes.cast(r.tracked, ctypes.POINTER(ctypes.c_uint8)),
+                                                shape=(H * TRACKED_DTYPE.itemsize,)).view(TRACKED_DTYPE).copy()
+                          if H else np.zeros(0, TRACKED_DTYPE))
+        hist = np.ctypeslib.as_array(ctypes.cast(r.hist, ctypes.POINTER(ctypes.c_int64)),
+                                     shape=(len(HIST_NAMES) * L,)).copy().reshape(len(HIST_NAMES), L)
+        for k, name in enumerate(HIST_NAMES):
+            out[name] = hist[k]
+        out["final_F"] = int(r.final_F)
+        out["peak_F"] = int(r.peak_F)
+        out["peak_sampled_F"] = int(r.peak_sampled_F)
+        out.update(leak_scores(out["leak_mallocs"], out["leak_frees"]))
+        return out
+    finally:
+        lib().oracle_free(rp)

@@ -1,0 +1,407 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle is checked against things other than itself: hand-worked
+fixtures (tests/golden, each citing the paper passage whose rule it applies),
+brute-force enumeration of every candidate sample set on tiny traces, closed
+forms, a second independent formulation (first-crossing search + chain
+iteration, and the leak rule restated as one window compare per tracked
+object), and invariants that hold at any size.
+"""
+import glob
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import tracegen as tg
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------ helpers --
+
+def events_from_rows(rows):
+    return tg.make_events([tuple(r) for r in rows])
+
+
+def run_case(params, rows):
+    ev = events_from_rows(rows)
+    p = dict(params)
+    return oracle.run(ev, threshold=p["threshold"], num_lines=p["num_lines"],
+                      copy_threshold=p.get("copy_threshold"), quantum_us=p.get("quantum_us", 10_000),
+                      options=p.get("options", 0))
+
+
+def check_expect(r, exp, num_lines):
+    assert r["status"] == oracle.OK
+    s = r["samples"]
+    got = [[int(x["event_idx"]), int(x["line"]), int(x["F"]), int(x["py"]), int(x["nat"])] for x in s]
+    assert got == exp["samples"]
+    for key in ("final_F", "peak_F", "peak_sampled_F"):
+        if key in exp:
+            assert r[key] == exp[key], key
+    if "lines" in exp:
+        for name in oracle.HIST_NAMES:
+            want = np.zeros(num_lines, np.int64)
+            for line, v in exp["lines"].get(name, {}).items():
+                want[int(line)] = v
+            np.testing.assert_array_equal(r[name], want, err_msg=name)
+    if "tracked" in exp:
+        t = r["tracked"]
+        got_t = [[int(x["event_idx"]), int(x["line"]), int(x["ptr"]), int(x["freed"])] for x in t]
+        assert got_t == exp["tracked"]
+    if "leak" in exp:
+        for line in range(num_lines):
+            if str(line) in exp["leak"]:
+                e = exp["leak"][str(line)]
+                assert [r["lap_num"][line], r["lap_den"][line]] == e["laplace"]
+                assert [r["lit_num"][line], r["lit_den"][line]] == e["literal"]
+            else:
+                assert r["lap_den"][line] == 0 and r["lit_den"][line] == 0
+
+
+# ---------------------------------------------------- golden fixtures --
+
+def _golden_cases():
+    out = []
+    for path in sorted(glob.glob(os.path.join(GOLDEN, "W*.json"))):
+        d = json.load(open(path))
+        if "cases" in d:
+            for k, c in enumerate(d["cases"]):
+                out.append(pytest.param(c["params"], c["events"], c["expect"], id=f"{d['id']}.{k}"))
+        else:
+            out.append(pytest.param(d["params"], d["events"], d["expect"], id=d["id"]))
+    return out
+
+
+@pytest.mark.parametrize("params,rows,expect", _golden_cases())
+def test_golden(params, rows, expect):
+    r = run_case(params, rows)
+    check_expect(r, expect, params["num_lines"])
+
+
+def test_w4_peak_only_view_misses_first_object():
+    """Section 6.3: a peak-only profile would show only the second object;
+    the threshold sampler attributes the 4 GB to both allocation lines."""
+    d = json.load(open(os.path.join(GOLDEN, "W4.json")))
+    r = run_case(d["params"], d["events"])
+    assert r["growth_bytes"][0] == 1 << 32 and r["growth_bytes"][2] == (1 << 32) + 8
+    # neither site passes the 95 % report gate with a single observation
+    assert not r["lap_gate"].any() and not r["lit_gate"].any()
+
+
+def test_w9_threshold_is_prime_above_10mb():
+    d = json.load(open(os.path.join(GOLDEN, "W9.json")))
+    r = run_case(d["params"], d["events"])
+    t = r["threshold_used"]
+    assert t >= 10 * tg.MiB and all(t % k for k in range(2, int(t ** 0.5) + 1))
+    assert all(any(v % k == 0 for k in range(2, int(v ** 0.5) + 1)) for v in range(10 * tg.MiB, t))
+
+
+# -------------------------------------------------------- brute force --
+
+def footprint(ev):
+    kind = (ev["flags"] >> 1) & 3
+    d = np.where(kind == 0, ev["delta"], 0).astype(np.int64)
+    return np.concatenate([[0], np.cumsum(d)])
+
+
+def satisfies_definition(F, T, nodes):
+    """Every consecutive pair (from the virtual node 0) is a first crossing
+    and nothing crosses after the last sample."""
+    prev = 0
+    for s in nodes:
+        if abs(int(F[s]) - int(F[prev])) < T:
+            return False
+        for j in range(prev + 1, s):
+            if abs(int(F[j]) - int(F[prev])) >= T:
+                return False
+        prev = s
+    for j in range(prev + 1, len(F)):
+        if abs(int(F[j]) - int(F[prev])) >= T:
+            return False
+    return True
+
+
+def brute_force_samples(ev, T):
+    F = footprint(ev)
+    n = len(ev)
+    hits = []
+    for mask in range(1 << n):
+        nodes = [i + 1 for i in range(n) if mask >> i & 1]
+        if satisfies_definition(F, T, nodes):
+            hits.append([x - 1 for x in nodes])
+    return hits
+
+
+def random_tiny_trace(rng, n, with_other_kinds):
+    rows = []
+    for i in range(n):
+        kind = 0
+        if with_other_kinds and rng.random() < 0.2:
+            kind = 1 if rng.random() < 0.5 else 2
+        d = int(rng.integers(-3, 4)) if kind == 0 else int(rng.integers(0, 4))
+        rows.append((d, i + 1, int(rng.integers(0, 3)), int(rng.integers(0, 2)), kind))
+    return events_from_rows(rows)
+
+
+def test_brute_force_exhaustive_small_alphabet():
+    """All traces of 4 memory events with deltas in {+-1,+-2,+-3}, T in 1..5:
+    exactly one index set satisfies the definition and it is the oracle's."""
+    alphabet = [-3, -2, -1, 1, 2, 3]
+    for T in range(1, 6):
+        for ds in itertools.product(alphabet, repeat=4):
+            ev = events_from_rows([(d, i + 1, 0, 0, 0) for i, d in enumerate(ds)])
+            hits = brute_force_samples(ev, T)
+            assert len(hits) == 1, (ds, T, hits)
+            r = oracle.run(ev, threshold=T, num_lines=1)
+            assert list(r["samples"]["event_idx"]) == hits[0], (ds, T)
+
+
+def test_brute_force_random_up_to_12():
+    rng = np.random.default_rng(1234)
+    for trial in range(150):
+        n = int(rng.integers(1, 13))
+        T = int(rng.integers(1, 7))
+        ev = random_tiny_trace(rng, n, with_other_kinds=bool(trial % 2))
+        hits = brute_force_samples(ev, T)
+        assert len(hits) == 1
+        r = oracle.run(ev, threshold=T, num_lines=3)
+        assert list(r["samples"]["event_idx"]) == hits[0]
+
+
+# ------------------------------------------------------- closed forms --
+
+def test_threshold_one_samples_every_nonzero_memory_event():
+    rng = np.random.default_rng(7)
+    ev = random_tiny_trace(rng, 400, with_other_kinds=True)
+    ev["delta"][::7] = np.where((ev["flags"][::7] >> 1) == 0, 0, ev["delta"][::7])
+    r = oracle.run(ev, threshold=1, num_lines=3)
+    kind = (ev["flags"] >> 1) & 3
+    want = np.flatnonzero((kind == 0) & (ev["delta"] != 0))
+    np.testing.assert_array_equal(r["samples"]["event_idx"], want)
+
+
+def test_threshold_above_total_variation_never_samples():
+    ev, _ = tg.config1(seed=11, n=5000)
+    kind = (ev["flags"] >> 1) & 3
+    tv = int(np.abs(np.where(kind == 0, ev["delta"], 0)).sum())
+    r = oracle.run(ev, threshold=tv + 1, num_lines=64)
+    assert r["K"] == 0 and r["H"] == 0
+
+
+@pytest.mark.parametrize("T", [1, 3, 10, 64])
+def test_monotone_unit_steps(T):
+    n = 1000
+    ev = events_from_rows([(1, i + 1, 0, 0, 0) for i in range(n)])
+    r = oracle.run(ev, threshold=T, num_lines=1)
+    assert r["K"] == n // T
+    np.testing.assert_array_equal(r["samples"]["event_idx"], np.arange(1, n // T + 1) * T - 1)
+    np.testing.assert_array_equal(r["samples"]["F"], np.arange(1, n // T + 1) * T)
+    # every sample is a new maximum, so every one is tracked and none freed
+    assert r["H"] == n // T and r["leak_frees"][0] == 0
+
+
+def test_leak_gates_and_printed_formula():
+    m = np.array([18, 19, 38, 39, 4, 0, 1, 5], np.int64)
+    f = np.array([0, 0, 1, 1, 4, 0, 1, 2], np.int64)
+    s = oracle.leak_scores(m, f)
+    # Laplace gate: likelihood (m-f+1)/(m+2) > 0.95
+    assert list(s["lap_gate"]) == [0, 1, 0, 1, 0, 0, 0, 0]
+    assert (s["lap_num"][0], s["lap_den"][0]) == (19, 20)
+    assert (s["lap_num"][1], s["lap_den"][1]) == (20, 21)
+    # the printed formula goes negative when every tracked object was freed
+    assert (s["lit_num"][4], s["lit_den"][4]) == (-3, 2)
+    assert (s["lap_num"][4], s["lap_den"][4]) == (1, 6)
+    assert s["lap_den"][5] == 0 and s["lit_den"][5] == 0
+    # exact: num/den equals the real-valued formulas
+    for i in (0, 1, 2, 3, 6, 7):
+        assert abs(s["lap_num"][i] / s["lap_den"][i] - (1 - (f[i] + 1) / (m[i] + 2))) < 1e-12
+        assert abs(s["lit_num"][i] / s["lit_den"][i] - (1 - (f[i] + 1) / (m[i] - f[i] + 2))) < 1e-12
+
+
+# ------------------------------------------------ second formulation --
+
+def chain_by_search(F, T):
+    """Samples by iterating 'first later node whose footprint differs from the
+    reference by at least T' from the virtual node 0."""
+    out = []
+    r = 0
+    n = len(F) - 1
+    while True:
+        nxt = None
+        start = r + 1
+        step = 256
+        while start <= n:
+            seg = F[start:start + step]
+            hit = np.flatnonzero(np.abs(seg - F[r]) >= T)
+            if hit.size:
+                nxt = start + int(hit[0])
+                break
+            start += step
+            step *= 2
+        if nxt is None:
+            return out
+        out.append(nxt)
+        r = nxt
+
+
+def restated_profile(ev, T, num_lines):
+    """Per-line attribution and leak counts recomputed from the sample chain
+    with prefix sums and one window compare per tracked object."""
+    kind = (ev["flags"] >> 1) & 3
+    mem = kind == 0
+    d = np.where(mem, ev["delta"], 0).astype(np.int64)
+    pyd = np.where(mem & ((ev["flags"] & 1) == 0), ev["delta"], 0).astype(np.int64)
+    F = np.concatenate([[0], np.cumsum(d)])
+    P = np.concatenate([[0], np.cumsum(pyd)])
+    nodes = chain_by_search(F, T)
+    lines = ev["line"]
+    out = {name: np.zeros(num_lines, np.int64) for name in oracle.HIST_NAMES}
+    prev = 0
+    hwm = 0
+    tracked = []
+    samples = []
+    for s in nodes:
+        ln = int(lines[s - 1])
+        py = int(P[s] - P[prev])
+        nat = int(F[s] - F[prev]) - py
+        samples.append((s - 1, ln, int(F[s]), py, nat))
+        out["py_bytes"][ln] += py
+        out["nat_bytes"][ln] += nat
+        delta = int(F[s] - F[prev])
+        if delta > 0:
+            out["growth_n"][ln] += 1
+            out["growth_bytes"][ln] += delta
+            if F[s] > hwm:
+                tracked.append((s - 1, ln, int(ev["ptr"][s - 1])))
+                out["leak_mallocs"][ln] += 1
+                hwm = int(F[s])
+        else:
+            out["shrink_n"][ln] += 1
+            out["shrink_bytes"][ln] += -delta
+        prev = s
+    frees = np.flatnonzero(mem & (ev["delta"] < 0))
+    freed = []
+    for h, (idx, ln, ptr) in enumerate(tracked):
+        end = tracked[h + 1][0] if h + 1 < len(tracked) else len(ev)
+        lo, hi = np.searchsorted(frees, idx, "right"), np.searchsorted(frees, end, "left")
+        hit = bool((ev["ptr"][frees[lo:hi]] == ptr).any())
+        freed.append(hit)
+        if h + 1 < len(tracked) and hit:
+            out["leak_frees"][ln] += 1
+    return samples, out, tracked, freed
+
+
+@pytest.mark.parametrize("seed,T,gen", [(1, tg.MiB, "c1"), (2, 256 * tg.KiB, "c1"), (3, 10 * tg.MiB, "c1"),
+                                        (4, 10 * tg.MiB, "c2")])
+def test_second_formulation_agrees(seed, T, gen):
+    if gen == "c1":
+        ev = tg.mix(seed, 100_000, num_lines=64)
+        L = 64
+    else:
+        ev = tg.lifetime(seed, 200_000, num_lines=500)
+        L = 500
+    r = oracle.run(ev, threshold=T, num_lines=L)
+    samples, prof, tracked, freed = restated_profile(ev, T, L)
+    got = [tuple(int(v) for v in row) for row in r["samples"][["event_idx", "line", "F", "py", "nat"]].tolist()]
+    assert got == samples
+    for name in ("py_bytes", "nat_bytes", "growth_n", "shrink_n", "growth_bytes", "shrink_bytes",
+                 "leak_mallocs", "leak_frees"):
+        np.testing.assert_array_equal(r[name], prof[name], err_msg=name)
+    assert [tuple(int(v) for v in x) for x in r["tracked"][["event_idx", "line", "ptr"]].tolist()] == tracked
+    assert [bool(x) for x in r["tracked"]["freed"]] == freed
+
+
+# --------------------------------------------------------- invariants --
+
+def check_invariants(ev, r, T, Tc, q):
+    kind = (ev["flags"] >> 1) & 3
+    mem = kind == 0
+    d = np.where(mem, ev["delta"], 0).astype(np.int64)
+    F = np.concatenate([[0], np.cumsum(d)])
+    s = r["samples"]
+    K = r["K"]
+    # telescoping: per-line sampled bytes sum to the footprint at the last sample
+    last = int(s["F"][-1]) if K else 0
+    assert int(r["py_bytes"].sum() + r["nat_bytes"].sum()) == last
+    np.testing.assert_array_equal(s["py"] + s["nat"], np.diff(np.concatenate([[0], s["F"]])))
+    np.testing.assert_array_equal(s["F"], F[s["event_idx"].astype(np.int64) + 1])
+    assert int(r["growth_n"].sum() + r["shrink_n"].sum()) == K
+    # each step is at least T and at most T - 1 + |trigger delta|
+    steps = np.abs(np.diff(np.concatenate([[0], s["F"]])))
+    trig = np.abs(ev["delta"][s["event_idx"]])
+    assert (steps >= T).all() and (steps <= T - 1 + trig).all()
+    # threshold sampling never takes more samples than deterministic rate-based sampling
+    tv = int(np.abs(d).sum())
+    assert K <= tv // T
+    # corrected lower bound on the number of samples
+    assert abs(int(F[-1])) <= (K + 1) * (T - 1) + int(trig.sum())
+    # leak counts
+    assert int(r["leak_mallocs"].sum()) == r["H"]
+    assert int(r["leak_frees"].sum()) <= max(r["H"] - 1, 0)
+    assert (r["leak_frees"] <= r["leak_mallocs"]).all()
+    # copy and timer totals
+    C = int(np.where(kind == 1, ev["delta"], 0).sum())
+    assert int(r["copy_exact"].sum()) == C
+    assert int(r["copy_sampled"].sum()) == (C // Tc) * Tc
+    nt = int((kind == 2).sum())
+    assert int(r["py_time_us"].sum()) == q * nt
+    assert int(r["nat_time_us"].sum()) == int(np.where(kind == 2, ev["delta"], 0).sum())
+    assert r["final_F"] == int(F[-1]) and r["peak_F"] == max(0, int(F.max()))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("T", [256 * tg.KiB, tg.MiB, 10 * tg.MiB])
+def test_invariants_config1_mix(seed, T):
+    ev, _ = tg.config1(seed=seed)
+    r = oracle.run(ev, threshold=T, num_lines=64)
+    check_invariants(ev, r, T, T, 10_000)
+
+
+def test_invariants_with_copy_and_timer():
+    ev = tg.mix(9, 200_000, num_lines=1000, zipf_s=1.05, copy_frac=0.10, timer_frac=0.01)
+    T, Tc = 4 * tg.MiB, 3 * tg.MiB + 7
+    r = oracle.run(ev, threshold=T, copy_threshold=Tc, num_lines=1000, quantum_us=10_000)
+    check_invariants(ev, r, T, Tc, 10_000)
+    kind = (ev["flags"] >> 1) & 3
+    # copy samples, per event, from the cumulative copy count
+    c = np.cumsum(np.where(kind == 1, ev["delta"], 0))
+    n_i = c // Tc - np.concatenate([[0], c[:-1]]) // Tc
+    want = np.zeros(1000, np.int64)
+    np.add.at(want, ev["line"], np.where(kind == 1, n_i * Tc, 0))
+    np.testing.assert_array_equal(r["copy_sampled"], want)
+
+
+# ----------------------------------------------------- error handling --
+
+def test_errors():
+    ok = [(5, 1, 0, 0, 0)]
+    assert run_case({"threshold": 10, "num_lines": 1}, ok)["status"] == oracle.OK
+    assert run_case({"threshold": 10, "num_lines": 1}, [(5, 1, 1, 0, 0)])["status"] == oracle.EINVAL
+    assert run_case({"threshold": 10, "num_lines": 1}, [(5, 1, 0, 0, 3)])["status"] == oracle.EINVAL
+    assert run_case({"threshold": 10, "num_lines": 1}, [(-5, 0, 0, 0, 1)])["status"] == oracle.EINVAL
+    assert run_case({"threshold": 10, "num_lines": 1}, [(1 << 32, 0, 0, 0, 2)])["status"] == oracle.EINVAL
+    assert run_case({"threshold": 10, "num_lines": 1}, [(1 << 52, 1, 0, 0, 0)])["status"] == oracle.EINVAL
+    assert run_case({"threshold": 0, "num_lines": 1}, ok)["status"] == oracle.EINVAL
+    big = (1 << 52) - 1
+    rows = [(big, i + 1, 0, 0, 0) for i in range(600)]
+    assert run_case({"threshold": 10, "num_lines": 1}, rows)["status"] == oracle.EOVERFLOW
+    # invalid input wins over overflow
+    assert run_case({"threshold": 10, "num_lines": 1}, rows + [(1, 1, 5, 0, 0)])["status"] == oracle.EINVAL
+
+
+def test_resolve_at_end_option():
+    rows = [(20, 1, 0, 0, 0), (-20, 1, 1, 0, 0)]
+    r0 = run_case({"threshold": 10, "num_lines": 2}, rows)
+    r1 = run_case({"threshold": 10, "num_lines": 2, "options": oracle.OPT_RESOLVE_AT_END}, rows)
+    assert r0["leak_frees"][0] == 0 and r0["tracked"]["freed"][0] == 1
+    assert r1["leak_frees"][0] == 1
+
+
+def test_empty_trace():
+    r = oracle.run(np.zeros(0, tg.EVENT_DTYPE), threshold=10, num_lines=3)
+    assert r["status"] == oracle.OK and r["K"] == 0 and r["final_F"] == 0
