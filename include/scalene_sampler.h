@@ -1,0 +1,229 @@
+/*
+ * scalene_sampler.h - C ABI of the MI355X threshold sampler.
+ *
+ * The library runs the memory-profiling core of Scalene (Berger, Stern,
+ * Altmayer Pizzorno, arXiv:2212.07597) offline over recorded event traces on
+ * one gfx950 GPU:
+ *   - threshold-based sampling of the footprint (section 3.2): a sample is
+ *     taken when the bytes allocated minus the bytes freed since the last
+ *     sample reach T in absolute value, and the counters restart;
+ *   - per-sample attribution to the triggering line with the Python/native
+ *     split of the sample's bytes, footprint timeline and maximum (section 3.3);
+ *   - the leak rule (track the sampled allocation at each new high-water mark,
+ *     check every free against it) and the (frees, mallocs) leak score with
+ *     its rule-of-succession likelihood (section 3.4);
+ *   - copy volume by rate-based sampling of copied bytes (section 3.5);
+ *   - the Python/native time split from timer-signal delays (section 2.1).
+ *
+ * All functions are callable from C; none throws.  Pointers marked "device"
+ * must be device memory of the sampler's GPU; "host" pointers are ordinary
+ * host memory.  Every function returns an SMP_* status unless noted.
+ *
+ * Readings where the paper is silent (identical in the CPU oracle):
+ *   the footprint and the sample reference start at 0 before event 0; ">="
+ *   triggers; a sample resets the reference to the footprint at the sample
+ *   (overshoot discarded); the sample belongs to the triggering event's line;
+ *   only memory events move the footprint; the Python/native split is the
+ *   signed net bytes of each kind in the sample's window; the high-water mark
+ *   is the largest footprint of an earlier tracked sample (initially 0) and a
+ *   growth sample is tracked when its footprint is strictly greater; a tracked
+ *   object is reclaimed if a free of its ptr_id occurs before the next tracked
+ *   sample; the last tracked object is unresolved unless
+ *   SMP_OPT_RESOLVE_AT_END; per-line sums wrap modulo 2^64.
+ */
+#ifndef SCALENE_SAMPLER_H
+#define SCALENE_SAMPLER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SMP_API __attribute__((visibility("default")))
+
+/* ---- status codes ---------------------------------------------------- */
+#define SMP_OK 0
+#define SMP_EINVAL 1    /* bad argument, or a malformed event (reported by fetch) */
+#define SMP_EBUDGET 2   /* not enough free budget now; fetch a finished trace and retry */
+#define SMP_ETOOBIG 3   /* the trace alone exceeds the whole budget */
+#define SMP_EAGAIN 4    /* trace not finished yet */
+#define SMP_EDEVICE 5   /* a HIP call failed; the sampler is unusable and must be destroyed */
+#define SMP_EOVERFLOW 6 /* a footprint, Python-footprint or copy prefix left (-2^61, 2^61) */
+#define SMP_ENOMEM 7    /* host allocation failed */
+#define SMP_ESTATE 8    /* call not valid in the trace's current state (unknown id, not run, ...) */
+
+/* ---- options ----------------------------------------------------------- */
+#define SMP_OPT_PRIME_T 1u        /* use the smallest prime >= threshold (section 3.2) */
+#define SMP_OPT_RESOLVE_AT_END 2u /* also score the last tracked object at the end of the trace */
+
+/* ---- event record: 24 bytes, array of structs --------------------------
+ * delta   : memory event: signed bytes (allocation > 0, free < 0), |delta| < 2^52
+ *           copy event  : bytes copied, 0 <= delta < 2^52
+ *           timer event : signal delay in microseconds, 0 <= delta < 2^32
+ * ptr_id  : identity of the allocation (compared on frees by the leak rule)
+ * line_id : source line, < num_lines
+ * flags   : bit 0 = 0 Python / 1 native; bits 1-2 = kind (0 memory, 1 copy, 2 timer)
+ */
+typedef struct {
+    int64_t delta;
+    uint32_t ptr_id;
+    uint32_t line_id;
+    uint8_t flags;
+    uint8_t pad[7];
+} smp_event_t;
+
+/* ---- per-trace parameters ----------------------------------------------
+ * threshold      : T >= 1 and < 2^60 (section 3.2)
+ * copy_threshold : Tc >= 1, bytes per copy-volume sample (section 3.5)
+ * num_lines      : line ids are < num_lines, 1 <= num_lines <= 2^31
+ * quantum_us     : timer quantum q added to Python time per timer event (section 2.1)
+ * options        : SMP_OPT_* bits
+ */
+typedef struct {
+    int64_t threshold;
+    int64_t copy_threshold;
+    uint32_t num_lines;
+    uint32_t quantum_us;
+    uint32_t options;
+    uint32_t reserved; /* must be 0 */
+} smp_params_t;
+
+/* one sample (section 3.3): event index of the triggering event, its line,
+ * footprint after it, and the net Python / native bytes since the previous
+ * sample (py + nat = F - F_previous_sample) */
+typedef struct {
+    uint32_t event_idx;
+    uint32_t line;
+    int64_t F;
+    int64_t py;
+    int64_t nat;
+} smp_sample_t;
+
+/* one tracked object (section 3.4): the sample that tracked it, its line and
+ * ptr_id, and whether a free of it was seen before the next tracked sample
+ * (for the last one: before the end of the trace) */
+typedef struct {
+    uint32_t event_idx;
+    uint32_t line;
+    uint32_t ptr;
+    uint32_t freed;
+} smp_tracked_t;
+
+/* per-line histogram order inside smp_profile_t.hist (num_lines entries each) */
+enum {
+    SMP_H_PY_BYTES = 0,   /* sum of py over samples attributed to the line */
+    SMP_H_NAT_BYTES,      /* sum of nat */
+    SMP_H_GROWTH_N,       /* number of growth samples */
+    SMP_H_SHRINK_N,       /* number of shrink samples */
+    SMP_H_GROWTH_BYTES,   /* sum of |F - F_prev| over growth samples */
+    SMP_H_SHRINK_BYTES,   /* sum of |F - F_prev| over shrink samples */
+    SMP_H_LEAK_MALLOCS,   /* leak score: objects tracked at this line */
+    SMP_H_LEAK_FREES,     /* leak score: tracked objects found reclaimed */
+    SMP_H_COPY_SAMPLED,   /* copy volume: Tc per copy sample */
+    SMP_H_COPY_EXACT,     /* copy volume: exact bytes copied */
+    SMP_H_PY_TIME,        /* q per timer event (microseconds) */
+    SMP_H_NAT_TIME,       /* delay per timer event (microseconds) */
+    SMP_H_COUNT
+};
+
+/* leak likelihood order inside smp_profile_t.leak (num_lines entries each):
+ * reduced rationals num/den with den > 0 (0/0 for lines with no tracked object)
+ *   Laplace's rule of succession, frees as successes: 1-(f+1)/(m+2)
+ *   the formula as printed in the paper:             1-(f+1)/(m-f+2)   */
+enum { SMP_L_LAP_NUM = 0, SMP_L_LAP_DEN, SMP_L_LIT_NUM, SMP_L_LIT_DEN, SMP_L_COUNT };
+/* report gates inside smp_profile_t.gates: likelihood > 95 % (section 3.4) */
+enum { SMP_G_LAP = 0, SMP_G_LIT, SMP_G_COUNT };
+
+typedef struct {
+    uint64_t n_samples;
+    uint64_t n_tracked;
+    uint32_t num_lines;
+    int32_t status;    /* SMP_OK, SMP_EINVAL (malformed event) or SMP_EOVERFLOW */
+} smp_profile_sizes_t;
+
+/* caller-owned host buffers, sized from smp_profile_sizes_t; any array
+ * pointer may be NULL to skip it */
+typedef struct {
+    smp_sample_t *samples;   /* n_samples */
+    smp_tracked_t *tracked;  /* n_tracked */
+    int64_t *hist;           /* SMP_H_COUNT * num_lines */
+    int64_t *leak;           /* SMP_L_COUNT * num_lines */
+    uint8_t *gates;          /* SMP_G_COUNT * num_lines */
+    /* filled scalars */
+    int64_t final_F;         /* footprint after the last event */
+    int64_t peak_F;          /* max(0, max footprint over all events) */
+    int64_t peak_sampled_F;  /* max(0, max footprint over samples) */
+    int64_t threshold_used;  /* T, or the prime chosen by SMP_OPT_PRIME_T */
+    uint64_t n_samples;
+    uint64_t n_tracked;
+    int32_t status;
+    int32_t reserved;
+} smp_profile_t;
+
+typedef struct smp_sampler smp_sampler_t; /* opaque, owned by the library */
+
+/* Device bytes one trace of n_events needs inside the workspace (exact; the
+ * admission rule of submit_trace).  ev_on_device = 0 adds room for a device
+ * copy of the events.  Returns 0 for invalid params. */
+SMP_API uint64_t workspace_bytes(uint64_t n_events, const smp_params_t *params, int ev_on_device);
+
+/* Create a sampler on HIP device `device` that launches on `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream) and carves all its device
+ * state out of `workspace` (device, caller-owned, at least 256-byte aligned,
+ * `workspace_size` bytes; it must outlive the sampler).  mem_budget caps the
+ * bytes admitted traces may hold at once (0 = the whole workspace minus the
+ * sampler's fixed part).  On success *out receives the sampler. */
+SMP_API int sampler_create(int device, void *hip_stream, uint64_t mem_budget, void *workspace,
+                           uint64_t workspace_size, smp_sampler_t **out);
+
+/* Admit one trace.  ev: n events (host if ev_on_device = 0: copied
+ * asynchronously on the sampler's stream, the buffer may be reused when this
+ * returns; device if ev_on_device = 1: borrowed, must stay valid and
+ * unchanged until the trace's fetch_profile).  n < 2^32 - 1.  Returns
+ * SMP_ETOOBIG if workspace_bytes(n) exceeds the budget, SMP_EBUDGET if it does
+ * not fit now.  *trace_id receives a handle.  The trace waits for run(). */
+SMP_API int submit_trace(smp_sampler_t *s, const smp_event_t *ev, uint64_t n, const smp_params_t *params,
+                         int ev_on_device, uint64_t *trace_id);
+
+/* Launch every submitted, not yet launched trace as one batch on the
+ * sampler's stream (one persistent kernel over all their segments).
+ * blocking = 1 waits for completion. */
+SMP_API int run(smp_sampler_t *s, int blocking);
+
+/* SMP_OK if the trace's batch finished, SMP_EAGAIN if still running,
+ * SMP_ESTATE for unknown or not launched ids. */
+SMP_API int poll(smp_sampler_t *s, uint64_t trace_id);
+
+/* Two-call fetch.  With out == NULL: waits for the trace, fills *sizes.
+ * With out != NULL: copies the profile into the caller's host buffers (sized
+ * from *sizes), fills the scalars, releases the trace's workspace and
+ * invalidates trace_id.  The returned status is the call's; the trace's own
+ * status (SMP_OK / SMP_EINVAL / SMP_EOVERFLOW) is in sizes->status and
+ * out->status. */
+SMP_API int fetch_profile(smp_sampler_t *s, uint64_t trace_id, smp_profile_sizes_t *sizes, smp_profile_t *out);
+
+/* Device pointers of a finished trace's results, for callers that keep them
+ * on the GPU (valid until fetch_profile releases the trace).  Any out pointer
+ * may be NULL. */
+SMP_API int trace_device_results(smp_sampler_t *s, uint64_t trace_id, void **samples, void **hist,
+                                 uint64_t *n_samples);
+
+/* Timing of the last run() (milliseconds, HIP events on the sampler's
+ * stream): the main sampling kernel alone, and the whole launch sequence. */
+SMP_API int sampler_last_timing(smp_sampler_t *s, float *main_kernel_ms, float *total_ms);
+
+/* Bytes of the workspace the sampler keeps for itself (descriptor tables,
+ * counters); the rest is the trace budget. */
+SMP_API uint64_t sampler_fixed_bytes(void);
+
+SMP_API void sampler_destroy(smp_sampler_t *s);
+
+/* Static string for a status code. */
+SMP_API const char *error_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,246 @@
+"""MI355X threshold sampler: Python binding of the C ABI in include/scalene_sampler.h.
+
+This module only marshals arguments; every step of the method runs in the HIP
+kernels of ``libscalene_hip.so``.  PyTorch provides device memory (the
+workspace, device-resident event buffers) and streams.  If the library is not
+built, importing works but every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from ._build import LIB_PATH
+
+SMP_OK, SMP_EINVAL, SMP_EBUDGET, SMP_ETOOBIG, SMP_EAGAIN = 0, 1, 2, 3, 4
+SMP_EDEVICE, SMP_EOVERFLOW, SMP_ENOMEM, SMP_ESTATE = 5, 6, 7, 8
+OPT_PRIME_T, OPT_RESOLVE_AT_END = 1, 2
+
+HIST_NAMES = (
+    "py_bytes", "nat_bytes", "growth_n", "shrink_n", "growth_bytes", "shrink_bytes",
+    "leak_mallocs", "leak_frees", "copy_sampled", "copy_exact", "py_time_us", "nat_time_us",
+)
+LEAK_NAMES = ("lap_num", "lap_den", "lit_num", "lit_den")
+GATE_NAMES = ("lap_gate", "lit_gate")
+
+SAMPLE_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("F", "<i8"), ("py", "<i8"), ("nat", "<i8")])
+TRACKED_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("ptr", "<u4"), ("freed", "<u4")])
+
+EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", "fetch_profile",
+            "trace_device_results", "sampler_last_timing", "sampler_fixed_bytes", "sampler_destroy",
+            "error_string")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("threshold", ctypes.c_int64),
+        ("copy_threshold", ctypes.c_int64),
+        ("num_lines", ctypes.c_uint32),
+        ("quantum_us", ctypes.c_uint32),
+        ("options", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class ProfileSizes(ctypes.Structure):
+    _fields_ = [
+        ("n_samples", ctypes.c_uint64),
+        ("n_tracked", ctypes.c_uint64),
+        ("num_lines", ctypes.c_uint32),
+        ("status", ctypes.c_int32),
+    ]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [
+        ("samples", ctypes.c_void_p),
+        ("tracked", ctypes.c_void_p),
+        ("hist", ctypes.c_void_p),
+        ("leak", ctypes.c_void_p),
+        ("gates", ctypes.c_void_p),
+        ("final_F", ctypes.c_int64),
+        ("peak_F", ctypes.c_int64),
+        ("peak_sampled_F", ctypes.c_int64),
+        ("threshold_used", ctypes.c_int64),
+        ("n_samples", ctypes.c_uint64),
+        ("n_tracked", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class SamplerError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed: {code} ({error_string(code)})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it is not built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        u64, i32, vp = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p
+        L.workspace_bytes.argtypes = [u64, ctypes.POINTER(Params), i32]
+        L.workspace_bytes.restype = u64
+        L.sampler_create.argtypes = [i32, vp, u64, vp, u64, ctypes.POINTER(vp)]
+        L.sampler_create.restype = i32
+        L.submit_trace.argtypes = [vp, vp, u64, ctypes.POINTER(Params), i32, ctypes.POINTER(u64)]
+        L.submit_trace.restype = i32
+        L.run.argtypes = [vp, i32]
+        L.run.restype = i32
+        L.poll.argtypes = [vp, u64]
+        L.poll.restype = i32
+        L.fetch_profile.argtypes = [vp, u64, ctypes.POINTER(ProfileSizes), ctypes.POINTER(Profile)]
+        L.fetch_profile.restype = i32
+        L.trace_device_results.argtypes = [vp, u64, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(u64)]
+        L.trace_device_results.restype = i32
+        L.sampler_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+        L.sampler_last_timing.restype = i32
+        L.sampler_fixed_bytes.argtypes = []
+        L.sampler_fixed_bytes.restype = u64
+        L.sampler_destroy.argtypes = [vp]
+        L.sampler_destroy.restype = None
+        L.error_string.argtypes = [i32]
+        L.error_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def error_string(code: int) -> str:
+    return lib().error_string(int(code)).decode()
+
+
+def make_params(threshold, num_lines, copy_threshold=None, quantum_us=10_000, options=0) -> Params:
+    return Params(int(threshold), int(copy_threshold if copy_threshold is not None else threshold),
+                  int(num_lines), int(quantum_us), int(options), 0)
+
+
+def workspace_bytes(n_events, params: Params, ev_on_device=True) -> int:
+    return int(lib().workspace_bytes(int(n_events), ctypes.byref(params), 1 if ev_on_device else 0))
+
+
+def sampler_fixed_bytes() -> int:
+    return int(lib().sampler_fixed_bytes())
+
+
+def _check(fn, code):
+    if code != SMP_OK:
+        raise SamplerError(fn, code)
+
+
+class Sampler:
+    """One sampler on one GPU: a workspace tensor, a stream and the C handle.
+
+    ``workspace`` bytes of device memory are allocated with torch (or pass a
+    uint8 CUDA tensor).  ``stream`` defaults to torch's current stream.
+    """
+
+    def __init__(self, workspace=1 << 30, device=0, stream=None, mem_budget=0):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if isinstance(workspace, torch.Tensor):
+            self.ws = workspace
+        else:
+            self.ws = torch.empty(int(workspace), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check("sampler_create", lib().sampler_create(device, ctypes.c_void_p(self.stream.cuda_stream), int(mem_budget),
+                                                      ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                                      ctypes.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sampler_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- C ABI mirrors --
+    def submit_trace(self, events, params: Params):
+        """events: numpy array of 24-byte records (copied) or a CUDA tensor
+        holding them (borrowed until fetch).  Returns the trace id."""
+        tid = ctypes.c_uint64()
+        if hasattr(events, "data_ptr"):
+            n = events.numel() * events.element_size() // 24
+            rc = lib().submit_trace(self.h, ctypes.c_void_p(events.data_ptr()), n, ctypes.byref(params), 1,
+                                    ctypes.byref(tid))
+            if rc == SMP_OK:
+                self._keep[tid.value] = events
+        else:
+            ev = np.ascontiguousarray(events)
+            n = ev.nbytes // 24
+            rc = lib().submit_trace(self.h, ctypes.c_void_p(ev.ctypes.data if n else 0), n, ctypes.byref(params), 0,
+                                    ctypes.byref(tid))
+        _check("submit_trace", rc)
+        return tid.value
+
+    def try_submit(self, events, params: Params):
+        """Like submit_trace but returns (status, id) instead of raising on budget codes."""
+        try:
+            return SMP_OK, self.submit_trace(events, params)
+        except SamplerError as e:
+            if e.code in (SMP_EBUDGET, SMP_ETOOBIG):
+                return e.code, None
+            raise
+
+    def run(self, blocking=False):
+        _check("run", lib().run(self.h, 1 if blocking else 0))
+
+    def poll(self, trace_id) -> bool:
+        rc = lib().poll(self.h, int(trace_id))
+        if rc == SMP_EAGAIN:
+            return False
+        _check("poll", rc)
+        return True
+
+    def fetch_profile(self, trace_id) -> dict:
+        sizes = ProfileSizes()
+        _check("fetch_profile", lib().fetch_profile(self.h, int(trace_id), ctypes.byref(sizes), None))
+        K, H, L = int(sizes.n_samples), int(sizes.n_tracked), int(sizes.num_lines)
+        samples = np.empty(K, SAMPLE_DTYPE)
+        tracked = np.empty(H, TRACKED_DTYPE)
+        hist = np.empty((len(HIST_NAMES), L), np.int64)
+        leak = np.empty((len(LEAK_NAMES), L), np.int64)
+        gates = np.empty((len(GATE_NAMES), L), np.uint8)
+        out = Profile(samples.ctypes.data if K else None, tracked.ctypes.data if H else None, hist.ctypes.data,
+                      leak.ctypes.data, gates.ctypes.data)
+        _check("fetch_profile", lib().fetch_profile(self.h, int(trace_id), ctypes.byref(sizes), ctypes.byref(out)))
+        self._keep.pop(int(trace_id), None)
+        res = {"status": int(out.status), "K": K, "H": H, "samples": samples, "tracked": tracked,
+               "final_F": int(out.final_F), "peak_F": int(out.peak_F), "peak_sampled_F": int(out.peak_sampled_F),
+               "threshold_used": int(out.threshold_used)}
+        for k, name in enumerate(HIST_NAMES):
+            res[name] = hist[k]
+        for k, name in enumerate(LEAK_NAMES):
+            res[name] = leak[k]
+        for k, name in enumerate(GATE_NAMES):
+            res[name] = gates[k]
+        return res
+
+    def last_timing(self):
+        a, b = ctypes.c_float(), ctypes.c_float()
+        _check("sampler_last_timing", lib().sampler_last_timing(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return float(a.value), float(b.value)
+
+    # -- convenience --
+    def profile(self, events, threshold, num_lines, copy_threshold=None, quantum_us=10_000, options=0):
+        p = make_params(threshold, num_lines, copy_threshold, quantum_us, options)
+        tid = self.submit_trace(events, p)
+        self.run(blocking=True)
+        return self.fetch_profile(tid)

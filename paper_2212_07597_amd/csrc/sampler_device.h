@@ -1,0 +1,200 @@
+// Device-side data layout and wave64 helpers for the gfx950 sampler kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smp {
+
+// ---- tiling --------------------------------------------------------------
+// A segment is NW windows of 64 events; one wavefront owns a segment at a time
+// (lane l of window w holds event 64*w + l of the segment).
+constexpr int NW = 8;
+constexpr int SEG = 64 * NW;
+constexpr int WAVES = 4;                 // wavefronts per workgroup
+constexpr int BLOCK = 64 * WAVES;
+constexpr int NSLOT = 128;               // LDS histogram cache slots per workgroup
+constexpr int NCNT = 10;                 // counters cached per slot
+constexpr int CHAIN_CAP = 32;            // chains followed by the all-entry analysis
+constexpr int NWORD = 20;                // status words per segment
+
+constexpr int64_t MAX_ABS_DELTA = (int64_t)1 << 52;
+constexpr int64_t MAX_ABS_F = (int64_t)1 << 61;
+
+// per-line histogram indices (same order as the public SMP_H_* enum)
+enum { H_PY = 0, H_NAT, H_GN, H_SN, H_GB, H_SB, H_LEAK_M, H_LEAK_F, H_CS, H_CE, H_PT, H_NT, H_COUNT };
+// cached counter slot -> histogram index
+__device__ constexpr int kCacheToHist[NCNT] = {H_PY, H_NAT, H_GN, H_SN, H_GB, H_SB, H_CS, H_CE, H_PT, H_NT};
+enum { C_PY = 0, C_NAT, C_GN, C_SN, C_GB, C_SB, C_CS, C_CE, C_PT, C_NT };
+
+// status words of one segment (each: 2-bit state | 62-bit payload, written once per run)
+enum {
+    W_AF = 0, W_AP, W_AC,          // aggregate sums: footprint, Python footprint, copy bytes
+    W_IF, W_IP, W_IC,              // inclusive prefixes of the same
+    W_MLO, W_MHI,                  // chain map: entry offsets [lo, hi] that take no sample here
+    W_MCF, W_MCP,                  // chain map: exit for every other entry (state 2) or none (1)
+    W_XF, W_XP,                    // final exit state: reference offset, absolute Python reference
+    W_BCNT, W_BGM, W_BGR, W_BGP,   // aggregate: samples, best growth footprint (2 = present), its event, its ptr
+    W_ICNT, W_IGM, W_IGR, W_IGP,   // inclusive of the same
+};
+
+struct Sample {
+    uint32_t event_idx;
+    uint32_t line;
+    int64_t F;
+    int64_t py;
+    int64_t nat;
+};
+
+struct Tracked {
+    uint32_t event_idx;
+    uint32_t line;
+    uint32_t ptr;
+    uint32_t freed;
+};
+
+struct Scalars {
+    int64_t final_F;
+    int64_t peak_F;
+    int64_t peak_S;
+    uint64_t K;
+    uint64_t H;
+    uint32_t err;      // bit 0: malformed event, bit 1: overflow
+    uint32_t pad;
+    uint64_t reserved[2];
+};
+
+// Per-trace descriptor, built by the host for every launch.
+struct Desc {
+    const uint8_t* ev;       // n 24-byte records
+    uint64_t n;
+    int64_t T;
+    int64_t Tc;
+    int64_t q;
+    uint32_t L;
+    uint32_t options;
+    int32_t tc_shift;        // log2(Tc) if Tc is a power of two, else -1
+    uint32_t pad0;
+    uint64_t seg_begin;      // first global segment index of this trace
+    uint64_t nseg;
+    uint64_t* status;        // nseg * NWORD words
+    Sample* samples;         // capacity n + 1
+    uint32_t* sample_ptr;    // capacity n + 1, written for tracked samples
+    Tracked* tracked;        // capacity n + 1
+    uint64_t* tracked_bits;  // by sample rank
+    uint64_t* freed_bits;    // by event index
+    int64_t* hist;           // H_COUNT * L
+    int64_t* leak;           // 4 * L
+    uint8_t* gates;          // 2 * L
+    Scalars* scal;
+    uint64_t* blk;           // compaction block sums
+    uint64_t blk_begin;      // first global compaction block of this trace
+    uint64_t nblk;
+    uint8_t* zero_ptr;       // contiguous range cleared before each launch
+    uint64_t zero_bytes;
+    uint64_t zero_begin;     // offset of that range in the launch's flattened clear space
+    uint64_t line_begin;     // offset of this trace's lines in the flattened line space
+};
+
+// ---- wave64 helpers -------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ int readlane32(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint64_t readlaneu64(uint64_t v, int l) { return (uint64_t)readlane64((int64_t)v, l); }
+
+__device__ __forceinline__ int shfl32(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+
+__device__ __forceinline__ int64_t shfl64(int64_t v, int src) {
+    uint32_t lo = (uint32_t)shfl32((int)(uint32_t)(uint64_t)v, src);
+    uint32_t hi = (uint32_t)shfl32((int)(uint32_t)((uint64_t)v >> 32), src);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int64_t wave_incl_sum(int64_t x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t y = shfl64(x, l >= d ? l - d : l);
+        if (l >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int64_t wave_incl_max(int64_t x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t y = shfl64(x, l >= d ? l - d : l);
+        if (l >= d && y > x) x = y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int64_t wave_incl_min(int64_t x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t y = shfl64(x, l >= d ? l - d : l);
+        if (l >= d && y < x) x = y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t x) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) x += shfl64(x, lane_id() ^ d);
+    return x;
+}
+
+__device__ __forceinline__ int64_t wave_max(int64_t x) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t y = shfl64(x, lane_id() ^ d);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int64_t wave_min(int64_t x) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t y = shfl64(x, lane_id() ^ d);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int ctz64(uint64_t m) { return __builtin_ctzll(m); }
+__device__ __forceinline__ int top64(uint64_t m) { return 63 - __builtin_clzll(m); }
+
+// ---- status words: 2-bit state in bits 62-63, 62-bit biased payload --------
+__device__ __forceinline__ uint64_t pack(int64_t v, uint32_t state) {
+    return (((uint64_t)v + ((uint64_t)1 << 61)) & (((uint64_t)1 << 62) - 1)) | ((uint64_t)state << 62);
+}
+__device__ __forceinline__ int64_t unpack(uint64_t w) {
+    return (int64_t)(w & (((uint64_t)1 << 62) - 1)) - ((int64_t)1 << 61);
+}
+__device__ __forceinline__ uint32_t wstate(uint64_t w) { return (uint32_t)(w >> 62); }
+
+__device__ __forceinline__ uint64_t ld_status(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_status(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace smp

@@ -1,0 +1,533 @@
+// Host side of the C ABI: workspace arena, trace admission, batch launch,
+// completion tracking and result copy-out.  Every computation on trace data
+// runs in the kernels of sampler_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "sampler_device.h"
+#include "scalene_sampler.h"
+
+namespace smp {
+int sample_grid_limit();
+hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, unsigned long long* ticket, hipStream_t s);
+hipError_t launch_sample(const Desc* desc, int ntraces, uint64_t nseg_total, unsigned long long* ticket, int grid,
+                         hipStream_t s);
+hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines, hipStream_t s);
+}  // namespace smp
+
+using namespace smp;
+
+static_assert(sizeof(smp_event_t) == 24, "event record layout");
+static_assert(sizeof(smp_sample_t) == sizeof(Sample), "sample layout");
+static_assert(sizeof(smp_tracked_t) == sizeof(Tracked), "tracked layout");
+
+namespace {
+
+constexpr uint64_t ALIGN = 256;
+constexpr int RUN_SLOTS = 8;
+constexpr int MAX_TRACES_PER_RUN = 4096;
+constexpr uint64_t CBLK_WORDS = 1024;
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// ---- deterministic Miller-Rabin for 64-bit integers ----
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t m) {
+    uint64_t r = 1;
+    a %= m;
+    while (e) {
+        if (e & 1) r = mulmod(r, a, m);
+        a = mulmod(a, a, m);
+        e >>= 1;
+    }
+    return r;
+}
+bool is_prime_mr(uint64_t n) {
+    if (n < 2) return false;
+    static const uint64_t small[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    for (uint64_t p : small) {
+        if (n % p == 0) return n == p;
+    }
+    uint64_t d = n - 1;
+    int s = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++s;
+    }
+    for (uint64_t a : small) {
+        uint64_t x = powmod(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int r = 1; r < s; ++r) {
+            x = mulmod(x, x, n);
+            if (x == n - 1) {
+                comp = false;
+                break;
+            }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+// Byte layout of one trace's region in the workspace.
+struct Layout {
+    uint64_t nseg, words, nblk;
+    uint64_t ev, samples, sample_ptr, tracked;  // offsets
+    uint64_t zero, status, tracked_bits, freed_bits, hist, leak, gates, scal, blk, zero_end;
+    uint64_t total;
+};
+
+Layout make_layout(uint64_t n, uint32_t L, bool ev_copy) {
+    Layout y{};
+    y.nseg = (n + SEG - 1) / SEG;
+    y.words = (n + 1 + 63) / 64;
+    y.nblk = (y.words + CBLK_WORDS - 1) / CBLK_WORDS;
+    uint64_t o = 0;
+    y.ev = o;
+    if (ev_copy) o = align_up(o + 24 * n, ALIGN);
+    y.samples = o;
+    o = align_up(o + sizeof(Sample) * (n + 1), ALIGN);
+    y.sample_ptr = o;
+    o = align_up(o + 4 * (n + 1), ALIGN);
+    y.tracked = o;
+    o = align_up(o + sizeof(Tracked) * (n + 1), ALIGN);
+    y.zero = o;
+    y.status = o;
+    o += 8 * NWORD * y.nseg;
+    y.tracked_bits = o;
+    o += 8 * y.words;
+    y.freed_bits = o;
+    o += 8 * y.words;
+    y.hist = o;
+    o += 8 * (uint64_t)H_COUNT * L;
+    y.leak = o;
+    o += 8 * 4 * (uint64_t)L;
+    y.gates = o;
+    o = align_up(o + 2 * (uint64_t)L, 8);
+    y.scal = o;
+    o += sizeof(Scalars);
+    y.blk = o;
+    o += 8 * y.nblk;
+    o = align_up(o, ALIGN);
+    y.zero_end = o;
+    y.total = o;
+    return y;
+}
+
+bool params_ok(const smp_params_t* p) {
+    return p && p->threshold >= 1 && p->threshold < ((int64_t)1 << 60) && p->copy_threshold >= 1 && p->num_lines >= 1 &&
+           p->num_lines <= (1u << 31) && p->reserved == 0 && (p->options & ~3u) == 0;
+}
+
+enum TraceState { PENDING = 0, LAUNCHED = 1 };
+
+struct TraceRec {
+    uint64_t id = 0;
+    int state = PENDING;
+    uint64_t n = 0;
+    smp_params_t params{};
+    int64_t T_used = 0;
+    uint64_t off = 0, bytes = 0;
+    Layout lay{};
+    const uint8_t* ev = nullptr;
+    int slot = -1;
+    uint64_t run_seq = 0;
+};
+
+struct RunSlot {
+    Desc* host_desc = nullptr;   // pinned staging
+    Desc* dev_desc = nullptr;
+    unsigned long long* dev_ticket = nullptr;
+    hipEvent_t e_start = nullptr, e_main0 = nullptr, e_main1 = nullptr, e_end = nullptr;
+    bool busy = false;
+    uint64_t seq = 0;
+};
+
+}  // namespace
+
+struct smp_sampler {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint8_t* ws = nullptr;
+    uint64_t ws_size = 0;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    uint64_t arena_base = 0;  // offset of the trace arena inside the workspace
+    std::map<uint64_t, uint64_t> free_list;  // offset -> size
+    std::map<uint64_t, TraceRec> traces;
+    RunSlot slots[RUN_SLOTS];
+    uint64_t next_id = 1;
+    uint64_t run_seq = 0;
+    int grid = 0;
+    bool failed = false;
+    float last_main_ms = 0, last_total_ms = 0;
+    uint64_t last_seq = 0;
+};
+
+namespace {
+
+uint64_t fixed_bytes() {
+    return align_up((uint64_t)RUN_SLOTS * (align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN) + ALIGN), ALIGN);
+}
+
+bool arena_alloc(smp_sampler* s, uint64_t bytes, uint64_t* off) {
+    for (auto it = s->free_list.begin(); it != s->free_list.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const uint64_t rest = it->second - bytes;
+            const uint64_t noff = it->first + bytes;
+            s->free_list.erase(it);
+            if (rest) s->free_list[noff] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void arena_free(smp_sampler* s, uint64_t off, uint64_t bytes) {
+    auto it = s->free_list.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != s->free_list.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        s->free_list.erase(nx);
+    }
+    if (it != s->free_list.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            s->free_list.erase(it);
+        }
+    }
+}
+
+int fail(smp_sampler* s) {
+    s->failed = true;
+    return SMP_EDEVICE;
+}
+
+#define HIPCHK(expr)                          \
+    do {                                      \
+        if ((expr) != hipSuccess) return fail(s); \
+    } while (0)
+
+// Wait for a slot's launch to finish and record its timing.
+int retire_slot(smp_sampler* s, RunSlot& r) {
+    if (!r.busy) return SMP_OK;
+    HIPCHK(hipEventSynchronize(r.e_end));
+    float a = 0, b = 0;
+    HIPCHK(hipEventElapsedTime(&a, r.e_main0, r.e_main1));
+    HIPCHK(hipEventElapsedTime(&b, r.e_start, r.e_end));
+    if (r.seq >= s->last_seq) {
+        s->last_seq = r.seq;
+        s->last_main_ms = a;
+        s->last_total_ms = b;
+    }
+    r.busy = false;
+    return SMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t sampler_fixed_bytes(void) { return fixed_bytes(); }
+
+uint64_t workspace_bytes(uint64_t n_events, const smp_params_t* params, int ev_on_device) {
+    if (!params_ok(params) || n_events >= 0xFFFFFFFFull) return 0;
+    return make_layout(n_events, params->num_lines, ev_on_device == 0).total;
+}
+
+const char* error_string(int status) {
+    switch (status) {
+        case SMP_OK: return "ok";
+        case SMP_EINVAL: return "invalid argument or malformed event";
+        case SMP_EBUDGET: return "not enough free workspace budget now";
+        case SMP_ETOOBIG: return "trace exceeds the whole workspace budget";
+        case SMP_EAGAIN: return "trace not finished";
+        case SMP_EDEVICE: return "HIP device error; destroy the sampler";
+        case SMP_EOVERFLOW: return "footprint, Python footprint or copy prefix outside (-2^61, 2^61)";
+        case SMP_ENOMEM: return "host allocation failed";
+        case SMP_ESTATE: return "unknown trace id or wrong trace state";
+        default: return "unknown status";
+    }
+}
+
+int sampler_create(int device, void* hip_stream, uint64_t mem_budget, void* workspace, uint64_t workspace_size,
+                   smp_sampler_t** out) {
+    if (!out) return SMP_EINVAL;
+    *out = nullptr;
+    if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return SMP_EINVAL;
+    const uint64_t fixed = fixed_bytes();
+    if (workspace_size < fixed + ALIGN) return SMP_EINVAL;
+    smp_sampler* s = new (std::nothrow) smp_sampler();
+    if (!s) return SMP_ENOMEM;
+    s->device = device;
+    s->stream = (hipStream_t)hip_stream;
+    s->ws = (uint8_t*)workspace;
+    s->ws_size = workspace_size;
+    s->arena_base = fixed;
+    const uint64_t arena = (workspace_size - fixed) / ALIGN * ALIGN;
+    s->budget = mem_budget == 0 || mem_budget > arena ? arena : mem_budget;
+    s->free_list[fixed] = arena;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete s;
+        return SMP_EDEVICE;
+    }
+    const uint64_t slot_bytes = align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN) + ALIGN;
+    for (int i = 0; i < RUN_SLOTS; ++i) {
+        RunSlot& r = s->slots[i];
+        r.dev_desc = (Desc*)(s->ws + i * slot_bytes);
+        r.dev_ticket = (unsigned long long*)(s->ws + i * slot_bytes + align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN));
+        if (hipHostMalloc((void**)&r.host_desc, sizeof(Desc) * MAX_TRACES_PER_RUN, hipHostMallocDefault) != hipSuccess ||
+            hipEventCreate(&r.e_start) != hipSuccess || hipEventCreate(&r.e_main0) != hipSuccess ||
+            hipEventCreate(&r.e_main1) != hipSuccess || hipEventCreate(&r.e_end) != hipSuccess) {
+            sampler_destroy(s);
+            return SMP_EDEVICE;
+        }
+    }
+    s->grid = sample_grid_limit();
+    if (s->grid <= 0) {
+        sampler_destroy(s);
+        return SMP_EDEVICE;
+    }
+    *out = s;
+    return SMP_OK;
+}
+
+void sampler_destroy(smp_sampler_t* s) {
+    if (!s) return;
+    if (!s->failed) {
+        for (auto& r : s->slots)
+            if (r.busy && r.e_end) (void)hipEventSynchronize(r.e_end);
+    }
+    for (auto& r : s->slots) {
+        if (r.host_desc) (void)hipHostFree(r.host_desc);
+        if (r.e_start) (void)hipEventDestroy(r.e_start);
+        if (r.e_main0) (void)hipEventDestroy(r.e_main0);
+        if (r.e_main1) (void)hipEventDestroy(r.e_main1);
+        if (r.e_end) (void)hipEventDestroy(r.e_end);
+    }
+    delete s;
+}
+
+int submit_trace(smp_sampler_t* s, const smp_event_t* ev, uint64_t n, const smp_params_t* params, int ev_on_device,
+                 uint64_t* trace_id) {
+    if (!s || !trace_id || !params_ok(params) || n >= 0xFFFFFFFFull || (n && !ev)) return SMP_EINVAL;
+    if (s->failed) return SMP_EDEVICE;
+    const bool copy = ev_on_device == 0;
+    const Layout lay = make_layout(n, params->num_lines, copy);
+    if (lay.total > s->budget) return SMP_ETOOBIG;
+    if (s->used + lay.total > s->budget) return SMP_EBUDGET;
+    uint64_t off = 0;
+    if (!arena_alloc(s, lay.total, &off)) return SMP_EBUDGET;
+    TraceRec t;
+    t.id = s->next_id++;
+    t.n = n;
+    t.params = *params;
+    t.T_used = params->threshold;
+    if (params->options & SMP_OPT_PRIME_T) {
+        uint64_t v = (uint64_t)params->threshold;
+        while (!is_prime_mr(v)) ++v;
+        t.T_used = (int64_t)v;
+    }
+    t.off = off;
+    t.bytes = lay.total;
+    t.lay = lay;
+    if (copy) {
+        t.ev = s->ws + off + lay.ev;
+        if (n) {
+            if (hipSetDevice(s->device) != hipSuccess ||
+                hipMemcpyAsync((void*)t.ev, ev, 24 * n, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+                hipStreamSynchronize(s->stream) != hipSuccess) {
+                arena_free(s, off, lay.total);
+                return fail(s);
+            }
+        }
+    } else {
+        t.ev = (const uint8_t*)ev;
+    }
+    s->used += lay.total;
+    *trace_id = t.id;
+    s->traces.emplace(t.id, t);
+    return SMP_OK;
+}
+
+int run(smp_sampler_t* s, int blocking) {
+    if (!s) return SMP_EINVAL;
+    if (s->failed) return SMP_EDEVICE;
+    std::vector<TraceRec*> pend;
+    for (auto& kv : s->traces)
+        if (kv.second.state == PENDING) pend.push_back(&kv.second);
+    if (pend.empty()) return SMP_OK;
+    HIPCHK(hipSetDevice(s->device));
+    size_t done = 0;
+    while (done < pend.size()) {
+        const size_t cnt = std::min<size_t>(MAX_TRACES_PER_RUN, pend.size() - done);
+        // pick the oldest slot
+        int si = 0;
+        for (int i = 1; i < RUN_SLOTS; ++i)
+            if (!s->slots[i].busy && (s->slots[si].busy || s->slots[i].seq < s->slots[si].seq)) si = i;
+        if (s->slots[si].busy) {
+            for (int i = 0; i < RUN_SLOTS; ++i)
+                if (s->slots[i].seq < s->slots[si].seq) si = i;
+        }
+        RunSlot& r = s->slots[si];
+        if (int rc = retire_slot(s, r)) return rc;
+        uint64_t seg = 0, blk = 0, zero = 0, lines = 0;
+        for (size_t k = 0; k < cnt; ++k) {
+            TraceRec& t = *pend[done + k];
+            Desc& D = r.host_desc[k];
+            std::memset(&D, 0, sizeof(Desc));
+            uint8_t* base = s->ws + t.off;
+            D.ev = t.ev;
+            D.n = t.n;
+            D.T = t.T_used;
+            D.Tc = t.params.copy_threshold;
+            D.q = t.params.quantum_us;
+            D.L = t.params.num_lines;
+            D.options = t.params.options;
+            D.tc_shift = -1;
+            if ((D.Tc & (D.Tc - 1)) == 0) D.tc_shift = __builtin_ctzll((uint64_t)D.Tc);
+            D.seg_begin = seg;
+            D.nseg = t.lay.nseg;
+            D.status = (uint64_t*)(base + t.lay.status);
+            D.samples = (Sample*)(base + t.lay.samples);
+            D.sample_ptr = (uint32_t*)(base + t.lay.sample_ptr);
+            D.tracked = (Tracked*)(base + t.lay.tracked);
+            D.tracked_bits = (uint64_t*)(base + t.lay.tracked_bits);
+            D.freed_bits = (uint64_t*)(base + t.lay.freed_bits);
+            D.hist = (int64_t*)(base + t.lay.hist);
+            D.leak = (int64_t*)(base + t.lay.leak);
+            D.gates = base + t.lay.gates;
+            D.scal = (Scalars*)(base + t.lay.scal);
+            D.blk = (uint64_t*)(base + t.lay.blk);
+            D.blk_begin = blk;
+            D.nblk = t.lay.nblk;
+            D.zero_ptr = base + t.lay.zero;
+            D.zero_bytes = t.lay.zero_end - t.lay.zero;
+            D.zero_begin = zero;
+            D.line_begin = lines;
+            seg += D.nseg;
+            blk += D.nblk;
+            zero += D.zero_bytes;
+            lines += D.L;
+            t.state = LAUNCHED;
+            t.slot = si;
+        }
+        r.seq = ++s->run_seq;
+        for (size_t k = 0; k < cnt; ++k) pend[done + k]->run_seq = r.seq;
+        HIPCHK(hipMemcpyAsync(r.dev_desc, r.host_desc, sizeof(Desc) * cnt, hipMemcpyHostToDevice, s->stream));
+        HIPCHK(hipEventRecord(r.e_start, s->stream));
+        HIPCHK(launch_clear(r.dev_desc, (int)cnt, zero, r.dev_ticket, s->stream));
+        HIPCHK(hipEventRecord(r.e_main0, s->stream));
+        const uint64_t want = (seg + WAVES - 1) / WAVES;
+        const int grid = (int)std::min<uint64_t>(want ? want : 1, (uint64_t)s->grid);
+        HIPCHK(launch_sample(r.dev_desc, (int)cnt, seg, r.dev_ticket, grid, s->stream));
+        HIPCHK(hipEventRecord(r.e_main1, s->stream));
+        HIPCHK(launch_finish(r.dev_desc, (int)cnt, blk, lines, s->stream));
+        HIPCHK(hipEventRecord(r.e_end, s->stream));
+        r.busy = true;
+        done += cnt;
+    }
+    if (blocking) {
+        for (auto& r : s->slots)
+            if (int rc = retire_slot(s, r)) return rc;
+    }
+    return SMP_OK;
+}
+
+int poll(smp_sampler_t* s, uint64_t trace_id) {
+    if (!s) return SMP_EINVAL;
+    auto it = s->traces.find(trace_id);
+    if (it == s->traces.end() || it->second.state != LAUNCHED) return SMP_ESTATE;
+    if (s->failed) return SMP_EDEVICE;
+    RunSlot& r = s->slots[it->second.slot];
+    if (!r.busy || r.seq != it->second.run_seq) return SMP_OK;
+    const hipError_t q = hipEventQuery(r.e_end);
+    if (q == hipSuccess) return SMP_OK;
+    if (q == hipErrorNotReady) return SMP_EAGAIN;
+    return fail(s);
+}
+
+static int wait_trace(smp_sampler_t* s, TraceRec& t) {
+    RunSlot& r = s->slots[t.slot];
+    if (r.busy && r.seq == t.run_seq) return retire_slot(s, r);
+    return SMP_OK;
+}
+
+int fetch_profile(smp_sampler_t* s, uint64_t trace_id, smp_profile_sizes_t* sizes, smp_profile_t* out) {
+    if (!s || !sizes) return SMP_EINVAL;
+    auto it = s->traces.find(trace_id);
+    if (it == s->traces.end() || it->second.state != LAUNCHED) return SMP_ESTATE;
+    if (s->failed) return SMP_EDEVICE;
+    TraceRec& t = it->second;
+    HIPCHK(hipSetDevice(s->device));
+    if (int rc = wait_trace(s, t)) return rc;
+    uint8_t* base = s->ws + t.off;
+    Scalars sc;
+    HIPCHK(hipMemcpy(&sc, base + t.lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    int32_t status = SMP_OK;
+    if (sc.err & 1u) status = SMP_EINVAL;
+    else if (sc.err & 2u) status = SMP_EOVERFLOW;
+    else if (sc.err & 12u) status = SMP_EDEVICE;  // internal consistency fault
+    sizes->n_samples = sc.K;
+    sizes->n_tracked = sc.H;
+    sizes->num_lines = t.params.num_lines;
+    sizes->status = status;
+    if (!out) return SMP_OK;
+    const uint64_t L = t.params.num_lines;
+    if (out->samples && sc.K)
+        HIPCHK(hipMemcpy(out->samples, base + t.lay.samples, sizeof(Sample) * sc.K, hipMemcpyDeviceToHost));
+    if (out->tracked && sc.H)
+        HIPCHK(hipMemcpy(out->tracked, base + t.lay.tracked, sizeof(Tracked) * sc.H, hipMemcpyDeviceToHost));
+    if (out->hist) HIPCHK(hipMemcpy(out->hist, base + t.lay.hist, 8 * H_COUNT * L, hipMemcpyDeviceToHost));
+    if (out->leak) HIPCHK(hipMemcpy(out->leak, base + t.lay.leak, 8 * 4 * L, hipMemcpyDeviceToHost));
+    if (out->gates) HIPCHK(hipMemcpy(out->gates, base + t.lay.gates, 2 * L, hipMemcpyDeviceToHost));
+    out->final_F = sc.final_F;
+    out->peak_F = sc.peak_F;
+    out->peak_sampled_F = sc.peak_S;
+    out->threshold_used = t.T_used;
+    out->n_samples = sc.K;
+    out->n_tracked = sc.H;
+    out->status = status;
+    arena_free(s, t.off, t.bytes);
+    s->used -= t.bytes;
+    s->traces.erase(it);
+    return SMP_OK;
+}
+
+int trace_device_results(smp_sampler_t* s, uint64_t trace_id, void** samples, void** hist, uint64_t* n_samples) {
+    if (!s) return SMP_EINVAL;
+    auto it = s->traces.find(trace_id);
+    if (it == s->traces.end() || it->second.state != LAUNCHED) return SMP_ESTATE;
+    if (s->failed) return SMP_EDEVICE;
+    TraceRec& t = it->second;
+    if (int rc = wait_trace(s, t)) return rc;
+    uint8_t* base = s->ws + t.off;
+    if (samples) *samples = base + t.lay.samples;
+    if (hist) *hist = base + t.lay.hist;
+    if (n_samples) {
+        Scalars sc;
+        HIPCHK(hipMemcpy(&sc, base + t.lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
+        *n_samples = sc.K;
+    }
+    return SMP_OK;
+}
+
+int sampler_last_timing(smp_sampler_t* s, float* main_kernel_ms, float* total_ms) {
+    if (!s) return SMP_EINVAL;
+    if (s->failed) return SMP_EDEVICE;
+    for (auto& r : s->slots)
+        if (int rc = retire_slot(s, r)) return rc;
+    if (main_kernel_ms) *main_kernel_ms = s->last_main_ms;
+    if (total_ms) *total_ms = s->last_total_ms;
+    return SMP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,318 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Everything the method computes is integer, so every comparison is exact:
+sample records, tracked objects, the twelve per-line arrays, scalars, leak
+rationals and gates.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2212_07597_amd as smp
+import tracegen as tg
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+KEYS = ("final_F", "peak_F", "peak_sampled_F", "threshold_used", "K", "H")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sampler():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    s = smp.Sampler(workspace=48 << 30)
+    yield s
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+
+
+def compare(g, o, label=""):
+    assert g["status"] == o["status"], (label, g["status"], o["status"])
+    if o["status"] != oracle.OK:
+        return
+    for k in KEYS:
+        assert g[k] == o[k], (label, k, g[k], o[k])
+    gs, os_ = g["samples"], o["samples"]
+    assert gs.shape == os_.shape, (label, gs.shape, os_.shape)
+    for f in ("event_idx", "line", "F", "py", "nat"):
+        if not np.array_equal(gs[f], os_[f]):
+            bad = np.flatnonzero(gs[f] != os_[f])[:5]
+            raise AssertionError(f"{label}: samples.{f} differ at {bad}: gpu {gs[bad]} oracle {os_[bad]}")
+    for f in ("event_idx", "line", "ptr", "freed"):
+        assert np.array_equal(g["tracked"][f], o["tracked"][f]), (label, "tracked", f)
+    for name in oracle.HIST_NAMES + ("lap_num", "lap_den", "lit_num", "lit_den", "lap_gate", "lit_gate"):
+        if not np.array_equal(g[name], o[name]):
+            bad = np.flatnonzero(g[name] != o[name])[:5]
+            raise AssertionError(f"{label}: {name} differs at lines {bad}: gpu {g[name][bad]} oracle {o[name][bad]}")
+
+
+def run_batch(sampler, cases):
+    """cases: list of (label, events, kwargs).  One run() for all of them."""
+    ids = []
+    for label, ev, kw in cases:
+        p = smp.make_params(kw["threshold"], kw["num_lines"], kw.get("copy_threshold"),
+                            kw.get("quantum_us", 10_000), kw.get("options", 0))
+        ids.append(sampler.submit_trace(ev, p))
+    say(f"  run of {len(cases)} traces")
+    sampler.run(blocking=True)
+    return [sampler.fetch_profile(i) for i in ids]
+
+
+def check_batch(sampler, cases):
+    outs = run_batch(sampler, cases)
+    for (label, ev, kw), g in zip(cases, outs):
+        o = oracle.run(ev, **kw)
+        compare(g, o, label)
+
+
+def test_golden_fixtures(sampler):
+    say("golden fixtures")
+    cases = []
+    expects = []
+    for name in sorted(os.listdir(GOLDEN)):
+        if not name.endswith(".json"):
+            continue
+        d = json.load(open(os.path.join(GOLDEN, name)))
+        for k, c in enumerate(d.get("cases", [d])):
+            ev = tg.make_events([tuple(r) for r in c["events"]])
+            p = c["params"]
+            kw = dict(threshold=p["threshold"], num_lines=p["num_lines"], copy_threshold=p.get("copy_threshold"),
+                      quantum_us=p.get("quantum_us", 10_000), options=p.get("options", 0))
+            cases.append((f"{d['id']}.{k}", ev, kw))
+            expects.append(c["expect"])
+    outs = run_batch(sampler, cases)
+    for (label, ev, kw), g, exp in zip(cases, outs, expects):
+        got = [[int(x["event_idx"]), int(x["line"]), int(x["F"]), int(x["py"]), int(x["nat"])] for x in g["samples"]]
+        assert got == exp["samples"], label
+        for key in ("final_F", "peak_F", "peak_sampled_F"):
+            if key in exp:
+                assert g[key] == exp[key], (label, key)
+        compare(g, oracle.run(ev, **kw), label)
+
+
+def tiny_trace(rng, n, kinds=True):
+    rows = []
+    for i in range(n):
+        kind = 0
+        if kinds and rng.random() < 0.15:
+            kind = 1 if rng.random() < 0.5 else 2
+        if kind == 0:
+            d = int(rng.integers(-40, 41))
+        else:
+            d = int(rng.integers(0, 30))
+        rows.append((d, int(rng.integers(1, 12)), int(rng.integers(0, 5)), int(rng.integers(0, 2)), kind))
+    return tg.make_events(rows)
+
+
+def test_tiny_random_batch(sampler):
+    say("tiny random traces, one batch")
+    rng = np.random.default_rng(99)
+    cases = []
+    for i in range(300):
+        n = int(rng.integers(0, 50))
+        T = int(rng.integers(1, 60))
+        opts = int(rng.integers(0, 4))
+        cases.append((f"tiny{i}", tiny_trace(rng, n), dict(threshold=T, num_lines=5,
+                                                           copy_threshold=int(rng.integers(1, 20)), options=opts)))
+    check_batch(sampler, cases)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 511, 512, 513, 1023, 1025, 4096 + 17])
+def test_segment_boundaries(sampler, n):
+    say(f"segment boundary n={n}")
+    rng = np.random.default_rng(n)
+    ev = tiny_trace(rng, n)
+    cases = [(f"b{n}T{T}", ev, dict(threshold=T, num_lines=5)) for T in (1, 5, 30, 100, 1000)]
+    check_batch(sampler, cases)
+
+
+def test_config1_mix(sampler):
+    say("config-1 mix: seeds x thresholds")
+    cases = []
+    for seed in (1, 2, 3):
+        ev, _ = tg.config1(seed=seed)
+        for T in (256 * tg.KiB, tg.MiB, 10 * tg.MiB, 3 * tg.MiB + 1):
+            cases.append((f"c1 s{seed} T{T}", ev, dict(threshold=T, num_lines=64)))
+    check_batch(sampler, cases)
+
+
+def adversarial_cases():
+    out = []
+    n = 20_000
+    mono = tg.make_events([(1, i + 1, i % 3, 0) for i in range(n)])
+    for T in (1, 7, 1000, n - 1, n, n + 1, 10 ** 9):
+        out.append((f"mono T{T}", mono, dict(threshold=T, num_lines=3)))
+    zeros = tg.make_events([(0, i + 1, 0, 0) for i in range(3000)])
+    out.append(("zeros", zeros, dict(threshold=1, num_lines=1)))
+    alt = tg.make_events([((-1) ** i * 50, i + 1, i % 2, i % 2) for i in range(5000)])
+    for T in (49, 50, 51, 100):
+        out.append((f"alt T{T}", alt, dict(threshold=T, num_lines=2)))
+    # forced events every 37 events in a drift of small steps
+    rows = []
+    for i in range(30_000):
+        d = 10_000 if i % 37 == 0 else (3 if i % 2 else -2)
+        if i % 74 == 0:
+            d = -10_000
+        rows.append((d, i + 1, i % 11, i % 2))
+    forced = tg.make_events(rows)
+    for T in (1000, 4000, 5001, 9000):
+        out.append((f"forced T{T}", forced, dict(threshold=T, num_lines=11)))
+    # slow drift with rare samples (segments that never collapse)
+    rng = np.random.default_rng(5)
+    steps = rng.integers(-100, 130, 50_000)
+    drift = tg.make_events([(int(d), i + 1, i % 7, int(d) & 1) for i, d in enumerate(steps)])
+    for T in (5_000, 40_000, 200_000):
+        out.append((f"drift T{T}", drift, dict(threshold=T, num_lines=7)))
+    # leak heavy: free every tracked allocation right after it is sampled
+    rows = []
+    pid = 1
+    for i in range(10_000):
+        rows.append((100, pid, i % 5, 0))
+        if i % 3 == 0:
+            rows.append((-100, pid, (i + 1) % 5, 0))
+        pid += 1
+    leak = tg.make_events(rows)
+    for T in (100, 250, 1000):
+        for opt in (0, smp.OPT_RESOLVE_AT_END):
+            out.append((f"leak T{T} o{opt}", leak, dict(threshold=T, num_lines=5, options=opt)))
+    # prime threshold option
+    ev, _ = tg.config1(seed=4, n=30_000)
+    out.append(("prime", ev, dict(threshold=tg.MiB, num_lines=64, options=smp.OPT_PRIME_T)))
+    return out
+
+
+def test_adversarial(sampler):
+    say("adversarial traces")
+    check_batch(sampler, adversarial_cases())
+
+
+def test_copy_and_timer_mix(sampler):
+    say("copy + timer mix")
+    ev = tg.mix(9, 300_000, num_lines=1000, zipf_s=1.05, copy_frac=0.10, timer_frac=0.01)
+    cases = [("c5mix Tc=T", ev, dict(threshold=4 * tg.MiB, copy_threshold=4 * tg.MiB, num_lines=1000)),
+             ("c5mix Tc odd", ev, dict(threshold=4 * tg.MiB, copy_threshold=3 * tg.MiB + 7, num_lines=1000)),
+             ("c5mix T64M", ev, dict(threshold=64 * tg.MiB, num_lines=1000))]
+    check_batch(sampler, cases)
+
+
+def test_errors(sampler):
+    say("error codes")
+    ok = tg.make_events([(5, 1, 0, 0)] * 700)
+    bad_line = ok.copy()
+    bad_line["line"][650] = 9
+    bad_kind = ok.copy()
+    bad_kind["flags"][3] = 6
+    bad_copy = ok.copy()
+    bad_copy["flags"][100] = 2
+    bad_copy["delta"][100] = -1
+    big = tg.make_events([((1 << 52) - 1, i + 1, 0, 0) for i in range(1200)])
+    cases = [("ok", ok, dict(threshold=10, num_lines=1)), ("bad_line", bad_line, dict(threshold=10, num_lines=1)),
+             ("bad_kind", bad_kind, dict(threshold=10, num_lines=1)),
+             ("bad_copy", bad_copy, dict(threshold=10, num_lines=1)),
+             ("overflow", big, dict(threshold=10, num_lines=1))]
+    outs = run_batch(sampler, cases)
+    want = [smp.SMP_OK, smp.SMP_EINVAL, smp.SMP_EINVAL, smp.SMP_EINVAL, smp.SMP_EOVERFLOW]
+    assert [o["status"] for o in outs] == want
+    for (label, ev, kw), g in zip(cases, outs):
+        assert oracle.run(ev, **kw)["status"] == g["status"], label
+
+
+def test_budget_admission(sampler):
+    say("admission by budget")
+    import torch
+    p = smp.make_params(10, 4)
+    need = smp.workspace_bytes(10_000, p, ev_on_device=False)
+    ws = torch.empty(smp.sampler_fixed_bytes() + need + 4096, dtype=torch.uint8, device="cuda")
+    s = smp.Sampler(workspace=ws)
+    ev = tg.make_events([(1, i + 1, 0, 0) for i in range(10_000)])
+    tid = s.submit_trace(ev, p)
+    assert s.try_submit(ev, p)[0] == smp.SMP_EBUDGET
+    assert s.try_submit(tg.make_events([(1, 1, 0, 0)] * 100_000), p)[0] == smp.SMP_ETOOBIG
+    s.run(blocking=True)
+    assert s.poll(tid)
+    r = s.fetch_profile(tid)
+    compare(r, oracle.run(ev, threshold=10, num_lines=4))
+    tid2 = s.submit_trace(ev, p)  # space is free again
+    s.run(blocking=True)
+    compare(s.fetch_profile(tid2), oracle.run(ev, threshold=10, num_lines=4))
+    s.close()
+
+
+def test_alone_equals_in_batch(sampler):
+    say("determinism: alone vs in a batch")
+    ev, _ = tg.config1(seed=7, n=50_000)
+    kw = dict(threshold=tg.MiB, num_lines=64)
+    alone = run_batch(sampler, [("alone", ev, kw)])[0]
+    others = [(f"o{i}", tg.config1(seed=100 + i, n=20_000 + 997 * i)[0], kw) for i in range(20)]
+    mixed = run_batch(sampler, others[:10] + [("mid", ev, kw)] + others[10:])[10]
+    compare(alone, mixed, "alone vs batch")
+    compare(alone, oracle.run(ev, **kw), "alone vs oracle")
+
+
+def test_device_resident_events(sampler):
+    say("device-resident events")
+    import torch
+    ev, _ = tg.config1(seed=8)
+    dev = torch.from_numpy(ev.view(np.uint8)).to("cuda")
+    p = smp.make_params(tg.MiB, 64)
+    tid = sampler.submit_trace(dev, p)
+    sampler.run(blocking=True)
+    compare(sampler.fetch_profile(tid), oracle.run(ev, threshold=tg.MiB, num_lines=64))
+
+
+def test_config3_batch(sampler):
+    say("config 3: 1024 traces in one launch")
+    plan = tg.config3_plan()
+    cases = []
+    for t, (n, T, seed) in enumerate(plan):
+        ev, kw = tg.config3_trace(n, T, seed)
+        cases.append((f"c3 t{t}", ev, dict(threshold=kw["threshold"], num_lines=kw["num_lines"])))
+    outs = run_batch(sampler, cases)
+    say("  oracle")
+    for (label, ev, kw), g in zip(cases, outs):
+        compare(g, oracle.run(ev, **kw), label)
+
+
+def test_config2_full(sampler):
+    say("config 2: 1e8 events, generating")
+    import torch
+    ev, kw = tg.config2()
+    dev = torch.from_numpy(ev.view(np.uint8)).to("cuda")
+    p = smp.make_params(kw["threshold"], kw["num_lines"])
+    say("  gpu")
+    tid = sampler.submit_trace(dev, p)
+    sampler.run(blocking=True)
+    g = sampler.fetch_profile(tid)
+    del dev
+    say("  oracle")
+    o = oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"])
+    compare(g, o, "config2")
+    assert g["K"] > 1_000_000
+
+
+def test_config5_mix_1e8(sampler):
+    say("config-5 mix at 1e8 events, generating")
+    import torch
+    ev, kw = tg.config5(n=100_000_000)
+    dev = torch.from_numpy(ev.view(np.uint8)).to("cuda")
+    p = smp.make_params(kw["threshold"], kw["num_lines"], kw["copy_threshold"], kw["quantum_us"])
+    say("  gpu")
+    tid = sampler.submit_trace(dev, p)
+    sampler.run(blocking=True)
+    g = sampler.fetch_profile(tid)
+    del dev
+    say("  oracle")
+    o = oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"], copy_threshold=kw["copy_threshold"],
+                   quantum_us=kw["quantum_us"])
+    compare(g, o, "config5 1e8")
