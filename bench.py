@@ -1,0 +1,238 @@
+"""Benchmark: one pass of the whole sampler over one synthetic trace per step.
+
+Workload (single GPU): config 2 - one trace of 1e8 events (lifetime mix: 95 %
+small Python objects, 5 % native arrays of 1-256 MiB, exponential lifetimes,
+10,000 lines, T = 10 MiB).  The trace is generated on the host (seeded),
+copied to HBM once, and every step runs submit_trace (device-resident
+events) + run + release on the sampler's stream.  Inputs are resident in HBM
+when the timed region starts.
+
+Prints one JSON line with events/s, the main kernel's roofline figures
+(algorithmic bytes = 24 B per event read once, over the kernel's own HIP-event
+duration) and the CPU oracle timed on the host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "trace events/s + HBM GB/s (batched/served vs plain); p50/p99 trace latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_EVENT = 24
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--events", type=int, default=100_000_000)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and served measurements")
+    ap.add_argument("--served-requests", type=int, default=1000)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sampler has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import __graft_entry__ as ge
+    ge.build_if_missing()
+    import paper_2212_07597_amd as smp
+    import tracegen as tg
+
+    log(f"generating config 2 ({args.events} events)")
+    t0 = time.time()
+    ev, kw = tg.config2(seed=args.seed, n=args.events)
+    log(f"  generated in {time.time() - t0:.1f}s")
+    n = ev.shape[0]
+    dev = torch.from_numpy(ev.view(np.uint8)).to("cuda")
+    params = smp.make_params(kw["threshold"], kw["num_lines"])
+    need = smp.workspace_bytes(n, params, ev_on_device=True)
+    s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + need + (1 << 20))
+    stream = s.stream
+
+    def step():
+        tid = s.submit_trace(dev, params)
+        s.run(blocking=True)
+        return tid
+
+    last = {"K": 0}
+
+    def release(tid):
+        K, status = s.release(tid)
+        if status != smp.SMP_OK:
+            raise RuntimeError(f"trace status {status}")
+        last["K"] = K
+
+    log("warmup")
+    for _ in range(args.warmup):
+        release(step())
+    torch.cuda.synchronize()
+
+    kern_ms = []
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        tid = step()
+        km, tm = s.last_timing()
+        kern_ms.append((km, tm))
+        release(tid)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    K = last["K"]
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = n * args.steps / elapsed
+    main_ms = sum(k for k, _ in kern_ms) / len(kern_ms)
+    launch_ms = sum(t for _, t in kern_ms) / len(kern_ms)
+    achieved = BYTES_PER_EVENT * n / (main_ms * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline (oracle)")
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            r = oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"])
+            reps += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t0
+        assert r["K"] == K, (r["K"], K)
+        cpu = {"value": round(n * reps / dt, 1), "unit": "events/s", "cores": 1, "kind": "oracle",
+               "sample": f"the full config-2 trace ({n} events), {reps} sequential pass(es), one host thread"}
+
+    s.close()
+    del dev
+    torch.cuda.empty_cache()
+    extras = {}
+    if not args.no_extras:
+        extras["batched"] = bench_batched(smp, tg, torch, np)
+        extras["served"] = bench_served(smp, tg, torch, np, args.served_requests)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "config2: one trace, 1e8 events, lifetime mix (95% Python 16-512 B, 5% native "
+                               "1-256 MiB, exp lifetimes mean 1e4), 10000 lines Zipf 1.2, T=10 MiB",
+                   "events": n, "samples": K, "seed": args.seed, "path": "plain one-trace-per-launch",
+                   "kernel_ms": round(main_ms, 4), "launch_sequence_ms": round(launch_ms, 4)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    out.update(extras)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(smp, tg, torch, np, steps=3):
+    """Config 3: 1024 traces (log-uniform 1e3-1e6 events, T from {256 KiB,
+    1 MiB, 10 MiB}) in one launch, against a loop of one launch per trace."""
+    log("batched: generating config 3")
+    plan = tg.config3_plan()
+    traces = [tg.config3_trace(n, T, seed) for (n, T, seed) in plan]
+    total = sum(len(ev) for ev, _ in traces)
+    devs = [torch.from_numpy(ev.view(np.uint8)).to("cuda") for ev, _ in traces]
+    params = [smp.make_params(kw["threshold"], kw["num_lines"]) for _, kw in traces]
+    need = sum(smp.workspace_bytes(len(ev), p) for (ev, _), p in zip(traces, params))
+    s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + need + (64 << 20))
+
+    def batched():
+        ids = [s.submit_trace(d, p) for d, p in zip(devs, params)]
+        s.run(blocking=True)
+        km, _ = s.last_timing()
+        for i in ids:
+            s.release(i)
+        return km
+
+    def plain():
+        for d, p in zip(devs, params):
+            tid = s.submit_trace(d, p)
+            s.run(blocking=True)
+            s.release(tid)
+
+    batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = [batched() for _ in range(steps)]
+    tb = (time.perf_counter() - t0) / steps
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    tp = time.perf_counter() - t0
+    s.close()
+    del devs
+    torch.cuda.empty_cache()
+    kms_avg = sum(kms) / len(kms)
+    return {"workload": "config3: 1024 traces, lengths 10^(3+3u), config-1 mix, 1000 lines, T in {256K,1M,10M}",
+            "events": total, "batched_events_per_s": round(total / tb, 1), "batched_ms": round(tb * 1e3, 3),
+            "batched_kernel_ms": round(kms_avg, 3),
+            "batched_kernel_hbm_gbs": round(BYTES_PER_EVENT * total / (kms_avg * 1e-3) / 1e9, 1),
+            "plain_events_per_s": round(total / tp, 1), "plain_ms": round(tp * 1e3, 3),
+            "speedup_vs_plain": round(tp / tb, 2)}
+
+
+def bench_served(smp, tg, torch, np, n_req, rates=(200.0, 1000.0, 5000.0)):
+    """Config 4: Poisson arrivals, LogNormal(ln 5e4, 1.5) lengths capped at
+    2e7, config-1 mix, T = 1 MiB, events in pinned host memory (each request
+    crosses PCIe), 32 GiB admission budget.  Served (continuous batching)
+    against plain (one launch per request, in order)."""
+    from paper_2212_07597_amd import serve
+    log(f"served: generating {n_req} requests")
+    plan = tg.config4_plan(base_seed=4, n_req=n_req, rate=1000.0)
+    pool = []
+    for i, (length, _, seed) in enumerate(plan):
+        ev, kw = tg.config4_trace(length, seed)
+        pool.append((torch.from_numpy(ev.view(np.uint8)).pin_memory(), length, kw))
+    p = smp.make_params(pool[0][2]["threshold"], pool[0][2]["num_lines"])
+    budget = 32 << 30
+    s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + budget + (1 << 20))
+    out = {"workload": "config4: Poisson arrivals, LogNormal(ln 5e4, 1.5) lengths capped at 2e7, config-1 mix, "
+                       "T=1 MiB, pinned host events, 32 GiB budget",
+           "requests": n_req, "events": int(sum(x[1] for x in pool)), "rates": {}}
+    for rate in rates:
+        arr = tg.config4_plan(base_seed=40 + int(rate), n_req=n_req, rate=rate)
+        reqs = [serve.Request(i, a, pool[i][0], p, pool[i][1]) for i, (_, a, _) in enumerate(arr)]
+        log(f"served: rate {rate}/s")
+        o_s, mk_s = serve.serve(s, reqs, max_inflight=4)
+        o_p, mk_p = serve.serve_plain(s, reqs)
+        st_s, st_p = serve.latency_stats(o_s), serve.latency_stats(o_p)
+        out["rates"][str(int(rate))] = {
+            "served": {**st_s, "events_per_s": round(out["events"] / (mk_s / 1e9), 1)},
+            "plain": {**st_p, "events_per_s": round(out["events"] / (mk_p / 1e9), 1)}}
+    s.close()
+    return out
+
+
+if __name__ == "__main__":
+    main()

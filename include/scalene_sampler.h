@@ -164,7 +164,7 @@ typedef struct {
 typedef struct smp_sampler smp_sampler_t; /* opaque, owned by the library */
 
 /* Device bytes one trace of n_events needs inside the workspace (exact; the
- * admission rule of submit_trace).  ev_on_device = 0 adds room for a device
+ * admission rule of submit_trace).  ev_on_device != 1 adds room for a device
  * copy of the events.  Returns 0 for invalid params. */
 SMP_API uint64_t workspace_bytes(uint64_t n_events, const smp_params_t *params, int ev_on_device);
 
@@ -177,17 +177,21 @@ SMP_API uint64_t workspace_bytes(uint64_t n_events, const smp_params_t *params, 
 SMP_API int sampler_create(int device, void *hip_stream, uint64_t mem_budget, void *workspace,
                            uint64_t workspace_size, smp_sampler_t **out);
 
-/* Admit one trace.  ev: n events (host if ev_on_device = 0: copied
- * asynchronously on the sampler's stream, the buffer may be reused when this
- * returns; device if ev_on_device = 1: borrowed, must stay valid and
- * unchanged until the trace's fetch_profile).  n < 2^32 - 1.  Returns
+/* Admit one trace.  ev: n events.  ev_on_device = 0: host memory, copied
+ * into the workspace before this returns (the buffer may be reused at once);
+ * 1: device memory, borrowed (must stay valid and unchanged until the trace's
+ * fetch_profile); 2: pinned host memory (hipHostMalloc), copied asynchronously
+ * on the caller's stream (must stay unchanged until the trace's
+ * fetch_profile).  n < 2^32 - 1.  Returns
  * SMP_ETOOBIG if workspace_bytes(n) exceeds the budget, SMP_EBUDGET if it does
  * not fit now.  *trace_id receives a handle.  The trace waits for run(). */
 SMP_API int submit_trace(smp_sampler_t *s, const smp_event_t *ev, uint64_t n, const smp_params_t *params,
                          int ev_on_device, uint64_t *trace_id);
 
-/* Launch every submitted, not yet launched trace as one batch on the
- * sampler's stream (one persistent kernel over all their segments).
+/* Launch every submitted, not yet launched trace as one batch (one
+ * persistent kernel over all their segments).  The launch runs on one of the
+ * sampler's internal streams, ordered after all work queued so far on the
+ * caller's stream, so consecutive batches may overlap on the device.
  * blocking = 1 waits for completion. */
 SMP_API int run(smp_sampler_t *s, int blocking);
 
@@ -212,6 +216,11 @@ SMP_API int trace_device_results(smp_sampler_t *s, uint64_t trace_id, void **sam
 /* Timing of the last run() (milliseconds, HIP events on the sampler's
  * stream): the main sampling kernel alone, and the whole launch sequence. */
 SMP_API int sampler_last_timing(smp_sampler_t *s, float *main_kernel_ms, float *total_ms);
+
+/* Diagnostics: the 32 control words of the last launch (word 0: segment
+ * tickets handed out, word 1: abort flag; words 8-23 hold per-phase cycle
+ * counts only in builds with SMP_PHASE_STATS, else 0). */
+SMP_API int sampler_last_counters(smp_sampler_t *s, uint64_t *out32);
 
 /* Bytes of the workspace the sampler keeps for itself (descriptor tables,
  * counters); the rest is the trace budget. */

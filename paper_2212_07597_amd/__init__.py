@@ -29,8 +29,8 @@ SAMPLE_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("F", "<i8"), ("
 TRACKED_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("ptr", "<u4"), ("freed", "<u4")])
 
 EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", "fetch_profile",
-            "trace_device_results", "sampler_last_timing", "sampler_fixed_bytes", "sampler_destroy",
-            "error_string")
+            "trace_device_results", "sampler_last_timing", "sampler_last_counters", "sampler_fixed_bytes",
+            "sampler_destroy", "error_string")
 
 
 class Params(ctypes.Structure):
@@ -104,6 +104,8 @@ def lib():
         L.trace_device_results.restype = i32
         L.sampler_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
         L.sampler_last_timing.restype = i32
+        L.sampler_last_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.sampler_last_counters.restype = i32
         L.sampler_fixed_bytes.argtypes = []
         L.sampler_fixed_bytes.restype = u64
         L.sampler_destroy.argtypes = [vp]
@@ -173,12 +175,16 @@ class Sampler:
 
     # -- C ABI mirrors --
     def submit_trace(self, events, params: Params):
-        """events: numpy array of 24-byte records (copied) or a CUDA tensor
-        holding them (borrowed until fetch).  Returns the trace id."""
+        """events: numpy array of 24-byte records (copied before returning), a
+        CUDA tensor holding them (borrowed until fetch) or a pinned CPU tensor
+        (copied asynchronously, kept until fetch).  Returns the trace id."""
         tid = ctypes.c_uint64()
         if hasattr(events, "data_ptr"):
             n = events.numel() * events.element_size() // 24
-            rc = lib().submit_trace(self.h, ctypes.c_void_p(events.data_ptr()), n, ctypes.byref(params), 1,
+            mode = 1 if events.is_cuda else 2
+            if mode == 2 and not events.is_pinned():
+                raise ValueError("CPU tensors must be pinned; pass a numpy array for pageable memory")
+            rc = lib().submit_trace(self.h, ctypes.c_void_p(events.data_ptr()), n, ctypes.byref(params), mode,
                                     ctypes.byref(tid))
             if rc == SMP_OK:
                 self._keep[tid.value] = events
@@ -233,10 +239,24 @@ class Sampler:
             res[name] = gates[k]
         return res
 
+    def release(self, trace_id):
+        """Wait for a trace and free its workspace without copying results out.
+        Returns (n_samples, status)."""
+        sizes = ProfileSizes()
+        empty = Profile()
+        _check("fetch_profile", lib().fetch_profile(self.h, int(trace_id), ctypes.byref(sizes), ctypes.byref(empty)))
+        self._keep.pop(int(trace_id), None)
+        return int(sizes.n_samples), int(sizes.status)
+
     def last_timing(self):
         a, b = ctypes.c_float(), ctypes.c_float()
         _check("sampler_last_timing", lib().sampler_last_timing(self.h, ctypes.byref(a), ctypes.byref(b)))
         return float(a.value), float(b.value)
+
+    def last_counters(self):
+        buf = (ctypes.c_uint64 * 32)()
+        _check("sampler_last_counters", lib().sampler_last_counters(self.h, buf))
+        return list(buf)
 
     # -- convenience --
     def profile(self, events, threshold, num_lines, copy_threshold=None, quantum_us=10_000, options=0):

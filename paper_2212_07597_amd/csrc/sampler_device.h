@@ -23,8 +23,6 @@ constexpr int64_t MAX_ABS_F = (int64_t)1 << 61;
 
 // per-line histogram indices (same order as the public SMP_H_* enum)
 enum { H_PY = 0, H_NAT, H_GN, H_SN, H_GB, H_SB, H_LEAK_M, H_LEAK_F, H_CS, H_CE, H_PT, H_NT, H_COUNT };
-// cached counter slot -> histogram index
-__device__ constexpr int kCacheToHist[NCNT] = {H_PY, H_NAT, H_GN, H_SN, H_GB, H_SB, H_CS, H_CE, H_PT, H_NT};
 enum { C_PY = 0, C_NAT, C_GN, C_SN, C_GB, C_SB, C_CS, C_CE, C_PT, C_NT };
 
 // status words of one segment (each: 2-bit state | 62-bit payload, written once per run)
@@ -32,10 +30,12 @@ enum {
     W_AF = 0, W_AP, W_AC,          // aggregate sums: footprint, Python footprint, copy bytes
     W_IF, W_IP, W_IC,              // inclusive prefixes of the same
     W_MLO, W_MHI,                  // chain map: entry offsets [lo, hi] that take no sample here
-    W_MCF, W_MCP,                  // chain map: exit for every other entry (state 2) or none (1)
-    W_XF, W_XP,                    // final exit state: reference offset, absolute Python reference
+    W_MCF,                         // chain map: exit offset for every other entry (state 2) or none (1)
+    W_XF,                          // final exit offset (reference minus footprint at the segment end)
     W_BCNT, W_BGM, W_BGR, W_BGP,   // aggregate: samples, best growth footprint (2 = present), its event, its ptr
     W_ICNT, W_IGM, W_IGR, W_IGP,   // inclusive of the same
+    W_LSA,                         // Python footprint at this segment's last sample (2) or no sample (1)
+    W_LSI,                         // Python footprint at the last sample up to this segment's end
 };
 
 struct Sample {
@@ -124,59 +124,58 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ int64_t wave_incl_sum(int64_t x) {
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int64_t y = shfl64(x, l >= d ? l - d : l);
-        if (l >= d) x += y;
-    }
+// DPP move of a 64-bit value (two 32-bit halves).  Lanes whose source is
+// outside the row or whose row is masked off receive `old`.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v, uint64_t old) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)old, (int)(uint32_t)v, CTRL, ROWS, 0xf, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(old >> 32), (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xf, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// DPP controls (gfx9 family): row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143, wave_shr:1 = 0x138.
+struct OpAdd {
+    static constexpr uint64_t id = 0;
+    __device__ static int64_t f(int64_t a, int64_t b) { return (int64_t)((uint64_t)a + (uint64_t)b); }
+};
+struct OpMax {
+    static constexpr uint64_t id = 0x8000000000000000ull;
+    __device__ static int64_t f(int64_t a, int64_t b) { return a > b ? a : b; }
+};
+struct OpMin {
+    static constexpr uint64_t id = 0x7FFFFFFFFFFFFFFFull;
+    __device__ static int64_t f(int64_t a, int64_t b) { return a < b ? a : b; }
+};
+
+// Inclusive wave64 scan: Hillis-Steele inside each row of 16 lanes, then
+// row 0's total into row 1 (and row 2's into row 3), then lanes 0-31's total
+// into rows 2 and 3.  Must be called with all 64 lanes active.
+template <class Op>
+__device__ __forceinline__ int64_t wave_scan(int64_t x) {
+    x = Op::f(x, (int64_t)dpp64<0x111>((uint64_t)x, Op::id));
+    x = Op::f(x, (int64_t)dpp64<0x112>((uint64_t)x, Op::id));
+    x = Op::f(x, (int64_t)dpp64<0x114>((uint64_t)x, Op::id));
+    x = Op::f(x, (int64_t)dpp64<0x118>((uint64_t)x, Op::id));
+    x = Op::f(x, (int64_t)dpp64<0x142, 0xa>((uint64_t)x, Op::id));
+    x = Op::f(x, (int64_t)dpp64<0x143, 0xc>((uint64_t)x, Op::id));
     return x;
 }
 
-__device__ __forceinline__ int64_t wave_incl_max(int64_t x) {
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int64_t y = shfl64(x, l >= d ? l - d : l);
-        if (l >= d && y > x) x = y;
-    }
-    return x;
+__device__ __forceinline__ int64_t wave_incl_sum(int64_t x) { return wave_scan<OpAdd>(x); }
+__device__ __forceinline__ int64_t wave_incl_max(int64_t x) { return wave_scan<OpMax>(x); }
+__device__ __forceinline__ int64_t wave_incl_min(int64_t x) { return wave_scan<OpMin>(x); }
+
+// value of the previous lane (lane 0 gets `old`)
+__device__ __forceinline__ int64_t wave_shr1(int64_t x, int64_t old) {
+    return (int64_t)dpp64<0x138>((uint64_t)x, (uint64_t)old);
 }
 
-__device__ __forceinline__ int64_t wave_incl_min(int64_t x) {
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int64_t y = shfl64(x, l >= d ? l - d : l);
-        if (l >= d && y < x) x = y;
-    }
-    return x;
-}
-
-__device__ __forceinline__ int64_t wave_sum(int64_t x) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) x += shfl64(x, lane_id() ^ d);
-    return x;
-}
-
-__device__ __forceinline__ int64_t wave_max(int64_t x) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int64_t y = shfl64(x, lane_id() ^ d);
-        x = y > x ? y : x;
-    }
-    return x;
-}
-
-__device__ __forceinline__ int64_t wave_min(int64_t x) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int64_t y = shfl64(x, lane_id() ^ d);
-        x = y < x ? y : x;
-    }
-    return x;
-}
+// reductions: the inclusive scan's last lane, broadcast
+__device__ __forceinline__ int64_t wave_sum(int64_t x) { return readlane64(wave_scan<OpAdd>(x), 63); }
+__device__ __forceinline__ int64_t wave_max(int64_t x) { return readlane64(wave_scan<OpMax>(x), 63); }
+__device__ __forceinline__ int64_t wave_min(int64_t x) { return readlane64(wave_scan<OpMin>(x), 63); }
 
 __device__ __forceinline__ int ctz64(uint64_t m) { return __builtin_ctzll(m); }
 __device__ __forceinline__ int top64(uint64_t m) { return 63 - __builtin_clzll(m); }

@@ -144,6 +144,8 @@ struct RunSlot {
     Desc* host_desc = nullptr;   // pinned staging
     Desc* dev_desc = nullptr;
     unsigned long long* dev_ticket = nullptr;
+    hipStream_t stream = nullptr;  // launches of this slot; ordered after the caller's stream
+    hipEvent_t e_ready = nullptr;  // recorded on the caller's stream at run()
     hipEvent_t e_start = nullptr, e_main0 = nullptr, e_main1 = nullptr, e_end = nullptr;
     bool busy = false;
     uint64_t seq = 0;
@@ -285,6 +287,8 @@ int sampler_create(int device, void* hip_stream, uint64_t mem_budget, void* work
         r.dev_desc = (Desc*)(s->ws + i * slot_bytes);
         r.dev_ticket = (unsigned long long*)(s->ws + i * slot_bytes + align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN));
         if (hipHostMalloc((void**)&r.host_desc, sizeof(Desc) * MAX_TRACES_PER_RUN, hipHostMallocDefault) != hipSuccess ||
+            hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&r.e_ready, hipEventDisableTiming) != hipSuccess ||
             hipEventCreate(&r.e_start) != hipSuccess || hipEventCreate(&r.e_main0) != hipSuccess ||
             hipEventCreate(&r.e_main1) != hipSuccess || hipEventCreate(&r.e_end) != hipSuccess) {
             sampler_destroy(s);
@@ -308,6 +312,8 @@ void sampler_destroy(smp_sampler_t* s) {
     }
     for (auto& r : s->slots) {
         if (r.host_desc) (void)hipHostFree(r.host_desc);
+        if (r.stream) (void)hipStreamDestroy(r.stream);
+        if (r.e_ready) (void)hipEventDestroy(r.e_ready);
         if (r.e_start) (void)hipEventDestroy(r.e_start);
         if (r.e_main0) (void)hipEventDestroy(r.e_main0);
         if (r.e_main1) (void)hipEventDestroy(r.e_main1);
@@ -320,7 +326,8 @@ int submit_trace(smp_sampler_t* s, const smp_event_t* ev, uint64_t n, const smp_
                  uint64_t* trace_id) {
     if (!s || !trace_id || !params_ok(params) || n >= 0xFFFFFFFFull || (n && !ev)) return SMP_EINVAL;
     if (s->failed) return SMP_EDEVICE;
-    const bool copy = ev_on_device == 0;
+    if (ev_on_device < 0 || ev_on_device > 2) return SMP_EINVAL;
+    const bool copy = ev_on_device != 1;
     const Layout lay = make_layout(n, params->num_lines, copy);
     if (lay.total > s->budget) return SMP_ETOOBIG;
     if (s->used + lay.total > s->budget) return SMP_EBUDGET;
@@ -342,9 +349,10 @@ int submit_trace(smp_sampler_t* s, const smp_event_t* ev, uint64_t n, const smp_
     if (copy) {
         t.ev = s->ws + off + lay.ev;
         if (n) {
+            // mode 0: pageable source, wait for the copy; mode 2: pinned source, leave it queued
             if (hipSetDevice(s->device) != hipSuccess ||
                 hipMemcpyAsync((void*)t.ev, ev, 24 * n, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-                hipStreamSynchronize(s->stream) != hipSuccess) {
+                (ev_on_device == 0 && hipStreamSynchronize(s->stream) != hipSuccess)) {
                 arena_free(s, off, lay.total);
                 return fail(s);
             }
@@ -422,16 +430,19 @@ int run(smp_sampler_t* s, int blocking) {
         }
         r.seq = ++s->run_seq;
         for (size_t k = 0; k < cnt; ++k) pend[done + k]->run_seq = r.seq;
-        HIPCHK(hipMemcpyAsync(r.dev_desc, r.host_desc, sizeof(Desc) * cnt, hipMemcpyHostToDevice, s->stream));
-        HIPCHK(hipEventRecord(r.e_start, s->stream));
-        HIPCHK(launch_clear(r.dev_desc, (int)cnt, zero, r.dev_ticket, s->stream));
-        HIPCHK(hipEventRecord(r.e_main0, s->stream));
+        // everything the caller queued on its stream (event copies) comes first
+        HIPCHK(hipEventRecord(r.e_ready, s->stream));
+        HIPCHK(hipStreamWaitEvent(r.stream, r.e_ready, 0));
+        HIPCHK(hipMemcpyAsync(r.dev_desc, r.host_desc, sizeof(Desc) * cnt, hipMemcpyHostToDevice, r.stream));
+        HIPCHK(hipEventRecord(r.e_start, r.stream));
+        HIPCHK(launch_clear(r.dev_desc, (int)cnt, zero, r.dev_ticket, r.stream));
+        HIPCHK(hipEventRecord(r.e_main0, r.stream));
         const uint64_t want = (seg + WAVES - 1) / WAVES;
         const int grid = (int)std::min<uint64_t>(want ? want : 1, (uint64_t)s->grid);
-        HIPCHK(launch_sample(r.dev_desc, (int)cnt, seg, r.dev_ticket, grid, s->stream));
-        HIPCHK(hipEventRecord(r.e_main1, s->stream));
-        HIPCHK(launch_finish(r.dev_desc, (int)cnt, blk, lines, s->stream));
-        HIPCHK(hipEventRecord(r.e_end, s->stream));
+        HIPCHK(launch_sample(r.dev_desc, (int)cnt, seg, r.dev_ticket, grid, r.stream));
+        HIPCHK(hipEventRecord(r.e_main1, r.stream));
+        HIPCHK(launch_finish(r.dev_desc, (int)cnt, blk, lines, r.stream));
+        HIPCHK(hipEventRecord(r.e_end, r.stream));
         r.busy = true;
         done += cnt;
     }
@@ -517,6 +528,18 @@ int trace_device_results(smp_sampler_t* s, uint64_t trace_id, void** samples, vo
         HIPCHK(hipMemcpy(&sc, base + t.lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
         *n_samples = sc.K;
     }
+    return SMP_OK;
+}
+
+int sampler_last_counters(smp_sampler_t* s, uint64_t* out32) {
+    if (!s || !out32) return SMP_EINVAL;
+    if (s->failed) return SMP_EDEVICE;
+    int si = -1;
+    for (int i = 0; i < RUN_SLOTS; ++i)
+        if (s->slots[i].seq && (si < 0 || s->slots[i].seq > s->slots[si].seq)) si = i;
+    if (si < 0) return SMP_ESTATE;
+    if (int rc = retire_slot(s, s->slots[si])) return rc;
+    HIPCHK(hipMemcpy(out32, s->slots[si].dev_ticket, 32 * sizeof(uint64_t), hipMemcpyDeviceToHost));
     return SMP_OK;
 }
 

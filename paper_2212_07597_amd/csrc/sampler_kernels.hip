@@ -27,6 +27,21 @@
 //    per-event histogram updates.
 #include "sampler_device.h"
 
+// Optional per-phase cycle counters (diagnostic builds only, -DSMP_PHASE_STATS):
+// each wave accumulates shader-clock cycles per phase and a few event counts,
+// then adds them once to ctl[8 + i] at exit.
+#ifdef SMP_PHASE_STATS
+#define PH_DECL uint64_t ph[16] = {0}; uint64_t ph_t = clock64();
+#define PH_MARK(i) do { const uint64_t _n = clock64(); ph[i] += _n - ph_t; ph_t = _n; } while (0)
+#define PH_COUNT(i, v) ph[i] += (uint64_t)(v)
+#define PH_FLUSH(ctl) do { if (lane_id() == 0) for (int _i = 0; _i < 16; ++_i) atomicAdd(&(ctl)[8 + _i], ph[_i]); } while (0)
+#else
+#define PH_DECL
+#define PH_MARK(i) do {} while (0)
+#define PH_COUNT(i, v) do {} while (0)
+#define PH_FLUSH(ctl) do {} while (0)
+#endif
+
 namespace smp {
 
 __device__ __forceinline__ int cache_to_hist(int c) {
@@ -84,69 +99,84 @@ __device__ __forceinline__ void hist_add(HistCache& hc, const Desc& D, uint32_t 
 
 // ---------------------------------------------------------------- look-backs
 
-// Every wait on another segment's status polls with a budget.  Running out
-// (only possible through an internal fault) raises the launch-wide abort word,
-// after which every wait returns at once, so all waves always exit.
-constexpr uint32_t SPIN_BUDGET = 1u << 27;
+// Every wait on another segment's status polls with a budget and an
+// exponential back-off.  Running out of budget (only possible through an
+// internal fault) raises the launch-wide abort word, after which every wait
+// returns at once, so all waves always exit.
+constexpr uint32_t SPIN_BUDGET = 1u << 24;
 
-__device__ __forceinline__ bool spin_abort(unsigned long long* ctl, uint32_t& budget) {
+struct Spin {
+    uint32_t budget = SPIN_BUDGET;
+    uint32_t reps = 1;
+};
+
+__device__ __forceinline__ bool spin_abort(unsigned long long* ctl, Spin& sp) {
     if (ld_status((const uint64_t*)&ctl[1])) return true;
-    __builtin_amdgcn_s_sleep(2);
-    if (--budget == 0) {
+    for (uint32_t i = 0; i < sp.reps; ++i) __builtin_amdgcn_s_sleep(4);
+    if (sp.reps < 8) sp.reps <<= 1;
+    if (--sp.budget == 0) {
         st_status((uint64_t*)&ctl[1], 1);
         return true;
     }
     return false;
 }
 
-// Exclusive prefix of (footprint, Python footprint, copy bytes) for segment g.
-__device__ bool lookback_sums(uint64_t* status, int64_t g, int64_t g0, int64_t& oF, int64_t& oP, int64_t& oC,
-                              unsigned long long* ctl) {
+// ------------------------------------------------- decoupled look-backs
+//
+// Segment g looks at its predecessors g-1-l (lane l, nearest first).  It
+// needs the nearest one that has published an inclusive value and the
+// aggregates of all segments after it.  Having them, it can also compute the
+// inclusive values of those intermediate segments, and it publishes them
+// ("helping"): the resolved frontier then advances as fast as aggregates
+// appear instead of one look-back at a time.  Identical values may be
+// written by several waves; a reader sees either copy.
+
+// Exclusive (F, P, C) prefix of segment g.
+__device__ bool scan_sums(uint64_t* status, int64_t g, int64_t& oF, int64_t& oP, int64_t& oC, unsigned long long* ctl) {
     const int l = lane_id();
-    uint32_t budget = SPIN_BUDGET;
     int64_t accF = 0, accP = 0, accC = 0;
     int64_t base = g - 1;
-    for (;;) {
+    bool first = true;
+    Spin sp;
+    while (base >= 0) {
         const int64_t jj = base - l;
-        const bool in = jj >= g0;
-        uint64_t iF = 0, iP = 0, iC = 0;
+        const bool in = jj >= 0;
+        uint64_t iF = 0, iP = 0, iC = 0, aF = 0, aP = 0, aC = 0;
+        uint64_t* w = status + (in ? jj : 0) * NWORD;
         if (in) {
-            const uint64_t* w = status + jj * NWORD;
             iF = ld_status(w + W_IF);
             iP = ld_status(w + W_IP);
             iC = ld_status(w + W_IC);
-        }
-        const bool has_incl = in && wstate(iF) && wstate(iP) && wstate(iC);
-        const uint64_t im = ballot(has_incl);
-        const uint64_t inm = ballot(in);
-        const int lim = im ? ctz64(im) : __popcll(inm);
-        const bool need = in && l < lim;
-        uint64_t aF = 0, aP = 0, aC = 0;
-        if (need) {
-            const uint64_t* w = status + jj * NWORD;
             aF = ld_status(w + W_AF);
             aP = ld_status(w + W_AP);
             aC = ld_status(w + W_AC);
         }
+        const bool incl_ok = in && wstate(iF) && wstate(iP) && wstate(iC);
+        const uint64_t im = ballot(incl_ok);
+        const int lim = im ? ctz64(im) : __popcll(ballot(in));
+        const bool need = in && l < lim;
         if (ballot(need && !(wstate(aF) && wstate(aP) && wstate(aC)))) {
-            if (spin_abort(ctl, budget)) return false;
+            if (spin_abort(ctl, sp)) return false;
             continue;
         }
-        int64_t vF = 0, vP = 0, vC = 0;
-        if (need) {
-            vF = unpack(aF);
-            vP = unpack(aP);
-            vC = unpack(aC);
-        } else if (im && l == lim) {
-            vF = unpack(iF);
-            vP = unpack(iP);
-            vC = unpack(iC);
+        const bool at = im && l == lim;
+        const int64_t vF = need ? unpack(aF) : (at ? unpack(iF) : 0);
+        const int64_t vP = need ? unpack(aP) : (at ? unpack(iP) : 0);
+        const int64_t vC = need ? unpack(aC) : (at ? unpack(iC) : 0);
+        // suffix sums toward older segments: S_l = sum over lanes >= l
+        const int64_t xF = wave_incl_sum(vF), xP = wave_incl_sum(vP), xC = wave_incl_sum(vC);
+        const int64_t tF = readlane64(xF, 63), tP = readlane64(xP, 63), tC = readlane64(xC, 63);
+        if (first && im && need && !incl_ok) {
+            st_status(w + W_IF, pack(tF - xF + vF, 1));
+            st_status(w + W_IP, pack(tP - xP + vP, 1));
+            st_status(w + W_IC, pack(tC - xC + vC, 1));
         }
-        accF += wave_sum(vF);
-        accP += wave_sum(vP);
-        accC += wave_sum(vC);
-        if (im || base - 64 < g0) break;
+        accF += tF;
+        accP += tP;
+        accC += tC;
+        if (im) break;
         base -= 64;
+        first = false;
     }
     oF = accF;
     oP = accP;
@@ -154,143 +184,196 @@ __device__ bool lookback_sums(uint64_t* status, int64_t g, int64_t g0, int64_t& 
     return true;
 }
 
-// Combine (count, best growth record) over the segments before g.
-// Record order: value > wins; ties keep the earlier segment.
-__device__ bool lookback_best(uint64_t* status, int64_t g, int64_t g0, int64_t& oCnt, bool& oHas, int64_t& oVal,
-                              uint32_t& oIdx, uint32_t& oPtr, unsigned long long* ctl) {
+// (count, best growth record) items, combined in segment order: counts add;
+// the record with the larger footprint wins, the earlier one on ties.  The
+// state before a trace is a high-water mark of 0 with nothing tracked.
+struct Best {
+    int64_t cnt;
+    bool has;
+    int64_t val;
+    uint32_t idx, ptr;
+};
+
+__device__ __forceinline__ Best with_baseline(Best b) {
+    if (b.has && b.val <= 0) b.has = false;  // a high-water mark of 0 beats it
+    if (!b.has) b.val = 0;
+    return b;
+}
+
+// value of lane l + d (lanes past 63 get `fill`)
+__device__ __forceinline__ int64_t lane_down(int64_t x, int d, int64_t fill) {
     const int l = lane_id();
-    uint32_t budget = SPIN_BUDGET;
-    int64_t cnt = 0;
-    bool has = false;   // running best from later segments (processed first)
-    int64_t val = 0;
-    uint32_t idx = 0, ptr = 0;
+    const int64_t y = shfl64(x, l + d < 64 ? l + d : l);
+    return l + d < 64 ? y : fill;
+}
+
+// Exclusive Best prefix of segment g (baseline applied).
+__device__ bool scan_best(uint64_t* status, int64_t g, Best& out, unsigned long long* ctl) {
+    const int l = lane_id();
+    Best acc{0, false, 0, 0, 0};  // later segments combined so far
     int64_t base = g - 1;
-    bool reached_start = false;
-    for (;;) {
+    bool first = true;
+    Spin sp;
+    while (base >= 0) {
         const int64_t jj = base - l;
-        const bool in = jj >= g0;
-        uint64_t ic = 0, ig = 0, ir = 0, ip = 0;
+        const bool in = jj >= 0;
+        uint64_t ic = 0, ig = 0, ir = 0, ip = 0, ac = 0, ag = 0, ar = 0, ap = 0;
+        uint64_t* w = status + (in ? jj : 0) * NWORD;
         if (in) {
-            const uint64_t* w = status + jj * NWORD;
-            ic = ld_status(w + W_ICNT);
-            ig = ld_status(w + W_IGM);
-            ir = ld_status(w + W_IGR);
-            ip = ld_status(w + W_IGP);
+            ic = ld_status(w + W_ICNT); ig = ld_status(w + W_IGM); ir = ld_status(w + W_IGR); ip = ld_status(w + W_IGP);
+            ac = ld_status(w + W_BCNT); ag = ld_status(w + W_BGM); ar = ld_status(w + W_BGR); ap = ld_status(w + W_BGP);
         }
-        const bool has_incl = in && wstate(ic) && wstate(ig) && wstate(ir) && wstate(ip);
-        const uint64_t im = ballot(has_incl);
-        const uint64_t inm = ballot(in);
-        const int lim = im ? ctz64(im) : __popcll(inm);
+        const bool incl_ok = in && wstate(ic) && wstate(ig) && wstate(ir) && wstate(ip);
+        const uint64_t im = ballot(incl_ok);
+        const int lim = im ? ctz64(im) : __popcll(ballot(in));
         const bool need = in && l < lim;
-        uint64_t ac = 0, ag = 0, ar = 0, ap = 0;
-        if (need) {
-            const uint64_t* w = status + jj * NWORD;
-            ac = ld_status(w + W_BCNT);
-            ag = ld_status(w + W_BGM);
-            ar = ld_status(w + W_BGR);
-            ap = ld_status(w + W_BGP);
-        }
         if (ballot(need && !(wstate(ac) && wstate(ag) && wstate(ar) && wstate(ap)))) {
-            if (spin_abort(ctl, budget)) return false;
+            if (spin_abort(ctl, sp)) return false;
             continue;
         }
-        uint64_t c = 0, gm = 0, gr = 0, gp = 0;
-        bool use = false;
-        if (need) {
-            c = ac; gm = ag; gr = ar; gp = ap;
-            use = true;
-        } else if (im && l == lim) {
-            c = ic; gm = ig; gr = ir; gp = ip;
-            use = true;
+        const bool at = im && l == lim;
+        const bool use = need || at;
+        const uint64_t c = at ? ic : ac, gm = at ? ig : ag, gr = at ? ir : ar, gp = at ? ip : ap;
+        const int64_t cnt = use ? unpack(c) : 0;
+        const bool has = use && wstate(gm) == 2;
+        const int64_t val = has ? unpack(gm) : INT64_MIN;
+        const uint32_t idx = (uint32_t)unpack(gr), ptr = (uint32_t)unpack(gp);
+        // suffix (toward older) counts and maxima
+        const int64_t xc = wave_incl_sum(cnt);
+        const int64_t tc = readlane64(xc, 63);
+        const int64_t rev = shfl64(val, 63 - l);
+        const int64_t M = shfl64(wave_incl_max(rev), 63 - l);  // max over lanes >= l
+        // the earliest holder of M for lane l is the first lane >= l where the
+        // suffix maximum drops (or the last lane)
+        const int64_t Mn = lane_down(M, 1, INT64_MIN);
+        const uint64_t bnd = ballot(M != INT64_MIN && M > Mn);
+        const uint64_t ge = bnd & ~lanemask_lt();
+        const int src = ge ? ctz64(ge) : l;
+        const uint32_t sidx = (uint32_t)shfl32((int)idx, src), sptr = (uint32_t)shfl32((int)ptr, src);
+        if (first && im && need && !incl_ok) {
+            Best inc{tc - xc + cnt, M != INT64_MIN, M, sidx, sptr};
+            inc = with_baseline(inc);
+            st_status(w + W_ICNT, pack(inc.cnt, 1));
+            st_status(w + W_IGM, pack(inc.val, inc.has ? 2 : 1));
+            st_status(w + W_IGR, pack((int64_t)inc.idx, 1));
+            st_status(w + W_IGP, pack((int64_t)inc.ptr, 1));
         }
-        cnt += wave_sum(use ? unpack(c) : 0);
-        const bool lh = use && wstate(gm) == 2;
-        const int64_t lv = lh ? unpack(gm) : INT64_MIN;
-        const int64_t mx = wave_max(lv);
-        const uint64_t at = ballot(lh && lv == mx);
-        if (at) {
-            const int src = top64(at);  // highest lane = earliest segment
-            if (!has || mx >= val) {
-                has = true;
-                val = mx;
-                idx = (uint32_t)unpack(readlaneu64(gr, src));
-                ptr = (uint32_t)unpack(readlaneu64(gp, src));
-            }
+        // the whole window (lane 0's suffix) comes before everything in acc
+        Best win;
+        win.cnt = tc;
+        const int64_t M0 = readlane64(M, 0);
+        win.has = M0 != INT64_MIN;
+        win.val = M0;
+        win.idx = (uint32_t)readlane32((int)sidx, 0);
+        win.ptr = (uint32_t)readlane32((int)sptr, 0);
+        Best r = win;
+        r.cnt = win.cnt + acc.cnt;
+        if (acc.has && (!win.has || acc.val > win.val)) {
+            r.has = true;
+            r.val = acc.val;
+            r.idx = acc.idx;
+            r.ptr = acc.ptr;
         }
+        acc = r;
         if (im) break;
-        if (base - 64 < g0) {
-            reached_start = true;
-            break;
-        }
         base -= 64;
+        first = false;
     }
-    (void)reached_start;
-    // the state before the trace is a high-water mark of 0 with nothing tracked
-    if (has && val <= 0) has = false;
-    oCnt = cnt;
-    oHas = has;
-    oVal = has ? val : 0;
-    oIdx = idx;
-    oPtr = ptr;
+    out = with_baseline(acc);
     return true;
 }
 
-// Entry state (reference offset, absolute Python reference) of segment g.
-__device__ bool lookback_chain(uint64_t* status, int64_t g, int64_t g0, int64_t& eF, int64_t& eP,
-                               unsigned long long* ctl) {
+// Absolute Python footprint at the last sample before segment g (0 if none).
+__device__ bool scan_last_sample(uint64_t* status, int64_t g, int64_t& oP, unsigned long long* ctl) {
     const int l = lane_id();
-    uint32_t budget = SPIN_BUDGET;
+    int64_t base = g - 1;
+    bool first = true;
+    Spin sp;
+    while (base >= 0) {
+        const int64_t jj = base - l;
+        const bool in = jj >= 0;
+        uint64_t li = 0, la = 0;
+        uint64_t* w = status + (in ? jj : 0) * NWORD;
+        if (in) {
+            li = ld_status(w + W_LSI);
+            la = ld_status(w + W_LSA);
+        }
+        // a lane resolves the search if its segment has a sample or a known exit value
+        const bool hit = in && (wstate(la) == 2 || wstate(li) != 0);
+        const uint64_t hm = ballot(hit);
+        const int lim = hm ? ctz64(hm) : __popcll(ballot(in));
+        if (ballot(in && l < lim && wstate(la) == 0)) {
+            if (spin_abort(ctl, sp)) return false;
+            continue;
+        }
+        if (hm) {
+            const uint64_t src_w = wstate(readlaneu64(la, lim)) == 2 ? readlaneu64(la, lim) : readlaneu64(li, lim);
+            const int64_t v = unpack(src_w);
+            if (first && in && l < lim && wstate(li) == 0) st_status(w + W_LSI, pack(v, 1));
+            oP = v;
+            return true;
+        }
+        base -= 64;
+        first = false;
+    }
+    oP = 0;
+    return true;
+}
+
+// Entry reference offset of segment g (relative to its first event).
+__device__ bool lookback_chain(const uint64_t* status, int64_t g, int64_t& eF, unsigned long long* ctl) {
+    const int l = lane_id();
+    Spin sp;
     int i0;
-    uint64_t xF, xP;
+    uint64_t xF;
+    // fast path: the predecessor's exit (published early when its map is total)
+    for (int tries = 0; tries < 3; ++tries) {
+        const uint64_t a = ld_status(status + (g - 1) * NWORD + W_XF);
+        if (wstate(a)) {
+            eF = unpack(a);
+            return true;
+        }
+        if (spin_abort(ctl, sp)) return false;
+    }
     // nearest predecessor (within 64) that has published its exit
     for (;;) {
         const int64_t jj = g - 1 - l;
-        const bool in = jj >= g0;
-        xF = 0;
-        xP = 0;
-        if (in) {
-            const uint64_t* w = status + jj * NWORD;
-            xF = ld_status(w + W_XF);
-            xP = ld_status(w + W_XP);
-        }
-        const uint64_t xm = ballot(in && wstate(xF) && wstate(xP));
+        const bool in = jj >= 0;
+        xF = in ? ld_status(status + jj * NWORD + W_XF) : 0;
+        const uint64_t xm = ballot(in && wstate(xF));
         if (xm) {
             i0 = ctz64(xm);
             break;
         }
-        if (spin_abort(ctl, budget)) return false;
+        if (spin_abort(ctl, sp)) return false;
     }
     int64_t F = unpack(readlaneu64(xF, i0));
-    int64_t P = unpack(readlaneu64(xP, i0));
     // apply the maps of the segments after it, oldest first
     for (int i = i0 - 1; i >= 0; --i) {
         const uint64_t* w = status + (g - 1 - i) * NWORD;
+        Spin sp2;
         for (;;) {
-            const uint64_t x0 = ld_status(w + W_XF), x1 = ld_status(w + W_XP);
-            if (wstate(x0) && wstate(x1)) {
+            const uint64_t x0 = ld_status(w + W_XF);
+            if (wstate(x0)) {
                 F = unpack(x0);
-                P = unpack(x1);
                 break;
             }
-            const uint64_t lo = ld_status(w + W_MLO), hi = ld_status(w + W_MHI);
-            const uint64_t cf = ld_status(w + W_MCF), cp = ld_status(w + W_MCP);
+            const uint64_t lo = ld_status(w + W_MLO), hi = ld_status(w + W_MHI), cf = ld_status(w + W_MCF);
             const uint64_t sf = ld_status(w + W_AF);
-            if (wstate(lo) && wstate(hi) && wstate(cf) && wstate(cp) && wstate(sf)) {
+            if (wstate(lo) && wstate(hi) && wstate(cf) && wstate(sf)) {
                 if (F >= unpack(lo) && F <= unpack(hi)) {
                     F -= unpack(sf);
                     break;
                 }
                 if (wstate(cf) == 2) {
                     F = unpack(cf);
-                    P = unpack(cp);
                     break;
                 }
             }
-            if (spin_abort(ctl, budget)) return false;
+            if (spin_abort(ctl, sp2)) return false;
         }
     }
     eF = F;
-    eP = P;
     return true;
 }
 
@@ -311,6 +394,48 @@ __device__ __forceinline__ bool follow(int64_t f, int64_t T, int64_t& ref, int& 
         ref = readlane64(f, j);
         last = w * 64 + j;
         st = j;
+    }
+}
+
+// One chain followed through a segment: its reference, sample masks (lane w
+// holds window w's mask), the largest growth-sample footprint (earliest on
+// ties), the largest sampled footprint and the last sample's index.
+struct ChainRun {
+    int64_t ref;
+    uint64_t mvec;
+    int64_t gbest;
+    int gnode;
+    int64_t smax;
+    int lastS;
+};
+
+// Follow cr from window w0 (after lane st0) through window wend (below lane
+// stend), sampling wherever the footprint is at least T away from the
+// reference (section 3.2).
+__device__ void run_chain(const int64_t* F, int64_t T, ChainRun& cr, int w0, int st0, int wend, int stend) {
+    const int l = lane_id();
+    for (int w = w0; w <= wend; ++w) {
+        const int64_t f = F[w * 64 + l];
+        int stl = w == w0 ? st0 : -1;
+        const int lim = w == wend ? stend : 64;
+        uint64_t m = 0;
+        for (;;) {
+            const int64_t d = f - cr.ref;
+            const uint64_t ex = ballot(l > stl && l < lim && (d >= T || d <= -T));
+            if (!ex) break;
+            const int jj = ctz64(ex);
+            const int64_t fj = readlane64(f, jj);
+            if (fj > cr.ref && (cr.gnode < 0 || fj > cr.gbest)) {
+                cr.gbest = fj;
+                cr.gnode = w * 64 + jj;
+            }
+            if (fj > cr.smax) cr.smax = fj;
+            cr.ref = fj;
+            m |= 1ull << jj;
+            stl = jj;
+            cr.lastS = w * 64 + jj;
+        }
+        if (l == w) cr.mvec |= m;
     }
 }
 
@@ -343,6 +468,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
 
     int cur_t = -1;
     int64_t peakF = 0, peakS = 0;
+    PH_DECL
 
     for (;;) {
         unsigned long long tk = 0;
@@ -372,6 +498,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
         const uint32_t L = D.L;
         uint64_t* st = D.status + j * NWORD;
         uint32_t err = 0;
+        PH_MARK(0);
+        PH_COUNT(12, 1);
 
         // ---- P1: load, decode, validate, scan ----------------------------
         uint64_t q0[NW], q1[NW], q2[NW];
@@ -453,42 +581,33 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
         }
         const int64_t sumF = cF, sumP = cP, sumC = cC;
         if (l < 3) st_status(st + W_AF + l, pack(l == 0 ? sumF : (l == 1 ? sumP : sumC), 1));
-
-        // ---- prefix sums from the preceding segments ------------------------
-        int64_t F0 = 0, P0 = 0, C0 = 0;
-        if (j > 0 && !lookback_sums(D.status, j, 0, F0, P0, C0, ctl)) err |= 8u;
-        if (l < 3) st_status(st + W_IF + l, pack(l == 0 ? F0 + sumF : (l == 1 ? P0 + sumP : C0 + sumC), 1));
-
-        {
-            const int64_t hiF = wave_max(mxF), loF = wave_min(mnF);
-            const int64_t hiP = wave_max(mxP), loP = wave_min(mnP);
-            if (F0 + hiF >= MAX_ABS_F || F0 + loF <= -MAX_ABS_F || P0 + hiP >= MAX_ABS_F || P0 + loP <= -MAX_ABS_F ||
-                C0 + sumC >= MAX_ABS_F || F0 >= MAX_ABS_F || F0 <= -MAX_ABS_F)
-                err |= 2u;
-            if (nv > 0 && F0 + hiF > peakF) peakF = F0 + hiF;
-        }
-
-        // copy volume: one Tc sample per multiple of Tc crossed (section 3.5)
-        if (any_copy) {
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                if (copym[w] && dC[w] != 0) {
-                    const uint64_t cout = (uint64_t)(C0 + sC[w]);
-                    const uint64_t cin = cout - (uint64_t)dC[w];
-                    uint64_t ns;
-                    if (D.tc_shift >= 0)
-                        ns = (cout >> D.tc_shift) - (cin >> D.tc_shift);
-                    else
-                        ns = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
-                    hist_add(hc, D, t, lnC[w], C_CS, (int64_t)(ns * (uint64_t)D.Tc), C_CE, dC[w], -1, 0, -1, 0);
-                }
-            }
-        }
+        PH_MARK(1);
 
         // ---- P2: all-entry analysis: the segment's map on entry states --------
         bool map_total = false;
-        int64_t map_kF = 0, map_kP = 0;
+        int64_t map_kF = 0;
+        // An event with |delta| >= 2T-1 samples for every entry state, so the
+        // chain from the first such event onwards is the same for all entries.
+        int fwin = -1, flane = -1;
+        ChainRun p2run{0, 0, 0, -1, INT64_MIN, -1};
         if (j > 0) {
+            const uint64_t wf = ballot(l < NW && forced_v != 0);
+            if (wf) {
+                fwin = ctz64(wf);
+                flane = ctz64(readlaneu64(forced_v, fwin));
+                p2run.ref = readlane64(S.F[fwin * 64 + l], flane);
+                run_chain(S.F, T, p2run, fwin, flane, NW - 1, 64);
+                map_total = true;
+                map_kF = p2run.ref - sumF;
+                if (l == 0) st_status(st + W_MLO, pack(1, 1));
+                if (l == 1) st_status(st + W_MHI, pack(0, 1));
+                if (l == 2) st_status(st + W_MCF, pack(map_kF, 2));
+                if (l == 3) st_status(st + W_XF, pack(map_kF, 1));
+                PH_COUNT(13, 1);
+                PH_COUNT(15, 1);
+            }
+        }
+        if (j > 0 && fwin < 0) {
             int64_t Lo = -T + 1, Hi = T - 1;
             int nch = 0;
             bool ovf = false;
@@ -536,7 +655,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
                 }
                 if (Lo <= Hi) {
                     const int64_t im = wave_incl_max(f), in = wave_incl_min(f);
-                    int64_t em = shfl64(im, l > 0 ? l - 1 : 0), en = shfl64(in, l > 0 ? l - 1 : 0);
+                    const int64_t em = wave_shr1(im, INT64_MIN), en = wave_shr1(in, INT64_MAX);
                     int64_t lob = Lo, hib = Hi;
                     if (l > 0) {
                         lob = (em - T + 1) > Lo ? (em - T + 1) : Lo;
@@ -574,70 +693,101 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
             if (Lo > T) Lo = T;
             if (Hi < -T) Hi = -T;
             bool has_const = !ovf && nch == 1;
-            int64_t kF = 0, kP = 0;
-            if (has_const) {
-                const int64_t r = readlane64(chref, 0);
-                const int lst = readlane32(chlast, 0);
-                kF = r - sumF;
-                kP = P0 + S.P[lst];
-            }
+            int64_t kF = 0;
+            if (has_const) kF = readlane64(chref, 0) - sumF;
             // publish the map
             if (l == 0) st_status(st + W_MLO, pack(Lo, 1));
             if (l == 1) st_status(st + W_MHI, pack(Hi, 1));
             if (l == 2) st_status(st + W_MCF, pack(kF, has_const ? 2 : 1));
-            if (l == 3) st_status(st + W_MCP, pack(kP, 1));
+            PH_COUNT(13, has_const ? 1 : 0);
+            PH_COUNT(14, ovf ? 1 : 0);
             if (has_const && Lo > Hi) {
+                PH_COUNT(15, 1);
                 map_total = true;
                 map_kF = kF;
-                map_kP = kP;
                 if (l == 0) st_status(st + W_XF, pack(kF, 1));
-                if (l == 1) st_status(st + W_XP, pack(kP, 1));
             }
         }
 
-        // ---- P4: entry state, then the segment's own samples -----------------
-        int64_t eF = 0, eP = 0;
-        if (j > 0 && !lookback_chain(D.status, j, 0, eF, eP, ctl)) err |= 8u;
-        uint64_t smask_v = 0;  // lane w: sample mask of window w
-        int64_t ref = eF;
-        int lastS = -1;
-        int64_t gbest = 0;
-        int gnode = -1;
-        int64_t smax = INT64_MIN;
-        for (int w = 0; w < NW; ++w) {
-            const int64_t f = S.F[w * 64 + l];
-            int stl = -1;
-            uint64_t m = 0;
-            for (;;) {
-                const int64_t d = f - ref;
-                const uint64_t ex = ballot(l > stl && (d >= T || d <= -T));
-                if (!ex) break;
-                const int jj = ctz64(ex);
-                const int64_t fj = readlane64(f, jj);
-                if (fj > ref && (gnode < 0 || fj > gbest)) {
-                    gbest = fj;
-                    gnode = w * 64 + jj;
-                }
-                if (fj > smax) smax = fj;
-                ref = fj;
-                m |= 1ull << jj;
-                stl = jj;
-                lastS = w * 64 + jj;
-            }
-            if (l == w) smask_v = m;
+        PH_MARK(4);
+
+        // ---- prefix sums from the preceding segments ------------------------
+        int64_t F0 = 0, P0 = 0, C0 = 0;
+        if (j > 0 && !scan_sums(D.status, j, F0, P0, C0, ctl)) err |= 8u;
+        if (l < 3) st_status(st + W_IF + l, pack(l == 0 ? F0 + sumF : (l == 1 ? P0 + sumP : C0 + sumC), 1));
+        PH_MARK(2);
+
+        {
+            const int64_t hiF = wave_max(mxF), loF = wave_min(mnF);
+            const int64_t hiP = wave_max(mxP), loP = wave_min(mnP);
+            if (F0 + hiF >= MAX_ABS_F || F0 + loF <= -MAX_ABS_F || P0 + hiP >= MAX_ABS_F || P0 + loP <= -MAX_ABS_F ||
+                C0 + sumC >= MAX_ABS_F || F0 >= MAX_ABS_F || F0 <= -MAX_ABS_F)
+                err |= 2u;
+            if (nv > 0 && F0 + hiF > peakF) peakF = F0 + hiF;
         }
+
+        // copy volume: one Tc sample per multiple of Tc crossed (section 3.5)
+        if (any_copy) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                if (copym[w] && dC[w] != 0) {
+                    const uint64_t cout = (uint64_t)(C0 + sC[w]);
+                    const uint64_t cin = cout - (uint64_t)dC[w];
+                    uint64_t ns;
+                    if (D.tc_shift >= 0)
+                        ns = (cout >> D.tc_shift) - (cin >> D.tc_shift);
+                    else
+                        ns = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
+                    hist_add(hc, D, t, lnC[w], C_CS, (int64_t)(ns * (uint64_t)D.Tc), C_CE, dC[w], -1, 0, -1, 0);
+                }
+            }
+        }
+
+        PH_MARK(3);
+
+        // ---- P4: entry state, then the segment's own samples -----------------
+        int64_t eF = 0;
+        if (j > 0 && !lookback_chain(D.status, j, eF, ctl)) err |= 8u;
+        PH_MARK(5);
+        ChainRun cr{eF, 0, 0, -1, INT64_MIN, -1};
+        if (fwin >= 0) {
+            // entry-dependent samples come only before the forced event
+            run_chain(S.F, T, cr, 0, -1, fwin, flane);
+            const int64_t fc = readlane64(S.F[fwin * 64 + l], flane);
+            if (fc > cr.ref && (cr.gnode < 0 || fc > cr.gbest)) {
+                cr.gbest = fc;
+                cr.gnode = fwin * 64 + flane;
+            }
+            if (fc > cr.smax) cr.smax = fc;
+            if (l == fwin) cr.mvec |= 1ull << flane;
+            cr.mvec |= p2run.mvec;
+            if (p2run.gnode >= 0 && (cr.gnode < 0 || p2run.gbest > cr.gbest)) {
+                cr.gbest = p2run.gbest;
+                cr.gnode = p2run.gnode;
+            }
+            if (p2run.smax > cr.smax) cr.smax = p2run.smax;
+            cr.lastS = p2run.lastS >= 0 ? p2run.lastS : fwin * 64 + flane;
+            cr.ref = p2run.ref;
+        } else {
+            run_chain(S.F, T, cr, 0, -1, NW - 1, 64);
+        }
+        const uint64_t smask_v = cr.mvec;
+        const int64_t ref = cr.ref;
+        const int lastS = cr.lastS;
+        const int64_t gbest = cr.gbest;
+        const int gnode = cr.gnode;
+        const int64_t smax = cr.smax;
         const int64_t xF = ref - sumF;
-        const int64_t xP = lastS >= 0 ? P0 + S.P[lastS] : eP;
         if (!map_total) {
             if (l == 0) st_status(st + W_XF, pack(xF, 1));
-            if (l == 1) st_status(st + W_XP, pack(xP, 1));
-        } else if (xF != map_kF || xP != map_kP) {
+        } else if (xF != map_kF) {
             err |= 4u;  // internal: the all-entry map disagrees with the simulated chain
         }
         const int count = (int)wave_sum(l < NW ? (int64_t)__popcll(smask_v) : 0);
         if (smax != INT64_MIN && F0 + smax > peakS) peakS = F0 + smax;
 
-        // ---- P5: publish (count, best growth record), then combine ------------
+        PH_MARK(6);
+        // ---- P5: publish (count, best growth record, last-sample Python footprint) ----
         {
             const bool hg = gnode >= 0;
             const int64_t gval = F0 + gbest;
@@ -647,28 +797,35 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
             if (l == 1) st_status(st + W_BGM, pack(hg ? gval : 0, hg ? 2 : 1));
             if (l == 2) st_status(st + W_BGR, pack((int64_t)gidx, 1));
             if (l == 3) st_status(st + W_BGP, pack((int64_t)gptr, 1));
-            int64_t base = 0, hv = 0;
-            bool hh = false;
-            uint32_t hidx = 0, hptr = 0;
-            if (j > 0 && !lookback_best(D.status, j, 0, base, hh, hv, hidx, hptr, ctl)) err |= 8u;
+            const int64_t lsP = lastS >= 0 ? P0 + S.P[lastS] : 0;
+            if (l == 4) st_status(st + W_LSA, pack(lsP, lastS >= 0 ? 2 : 1));
+            Best pre{0, false, 0, 0, 0};
+            if (j > 0 && !scan_best(D.status, j, pre, ctl)) err |= 8u;
+            {
+                Best inc = pre;
+                inc.cnt += count;
+                if (hg && gval > (pre.has ? pre.val : 0)) {
+                    inc.has = true;
+                    inc.val = gval;
+                    inc.idx = gidx;
+                    inc.ptr = gptr;
+                }
+                if (l == 0) st_status(st + W_ICNT, pack(inc.cnt, 1));
+                if (l == 1) st_status(st + W_IGM, pack(inc.has ? inc.val : 0, inc.has ? 2 : 1));
+                if (l == 2) st_status(st + W_IGR, pack((int64_t)inc.idx, 1));
+                if (l == 3) st_status(st + W_IGP, pack((int64_t)inc.ptr, 1));
+            }
+            int64_t eP = 0;
+            if (j > 0 && !scan_last_sample(D.status, j, eP, ctl)) err |= 8u;
+            if (l == 0) st_status(st + W_LSI, pack(lastS >= 0 ? lsP : eP, 1));
+            int64_t base = pre.cnt, hv = pre.val;
+            bool hh = pre.has;
+            uint32_t hidx = pre.idx, hptr = pre.ptr;
+            PH_MARK(7);
             if (base < 0 || base > (int64_t)D.n) {  // only reachable after an internal fault
                 err |= 8u;
                 base = 0;
             }
-            // inclusive record
-            bool nh = hh;
-            int64_t nvv = hv;
-            uint32_t nidx = hidx, nptr = hptr;
-            if (hg && gval > (hh ? hv : 0)) {
-                nh = true;
-                nvv = gval;
-                nidx = gidx;
-                nptr = gptr;
-            }
-            if (l == 0) st_status(st + W_ICNT, pack(base + count, 1));
-            if (l == 1) st_status(st + W_IGM, pack(nh ? nvv : 0, nh ? 2 : 1));
-            if (l == 2) st_status(st + W_IGR, pack((int64_t)nidx, 1));
-            if (l == 3) st_status(st + W_IGP, pack((int64_t)nptr, 1));
             if ((uint64_t)j == D.nseg - 1 && l == 0) {
                 D.scal->K = (uint64_t)(base + count);
                 D.scal->final_F = F0 + sumF;
@@ -756,8 +913,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
                 cnt += __popcll(m);
             }
         }
+        PH_MARK(8);
         if (err && l == 0) atomicOr(&D.scal->err, err);
     }
+    PH_FLUSH(ctl);
     if (cur_t >= 0 && l == 0) {
         atomicMax((long long*)&desc[cur_t].scal->peak_F, (long long)peakF);
         atomicMax((long long*)&desc[cur_t].scal->peak_S, (long long)peakS);
@@ -781,7 +940,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
 __global__ void k_clear(const Desc* __restrict__ desc, int ntraces, uint64_t total_bytes, unsigned long long* ctl) {
     const uint64_t chunk = 1ull << 16;
     const uint64_t begin = (uint64_t)blockIdx.x * chunk;
-    if (blockIdx.x == 0 && threadIdx.x < 2) ctl[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 32) ctl[threadIdx.x] = 0;
     if (begin >= total_bytes) return;
     const uint64_t end = begin + chunk < total_bytes ? begin + chunk : total_bytes;
     // traces overlapping [begin, end)
