@@ -77,7 +77,7 @@ struct Desc {
     uint32_t pad0;
     uint64_t seg_begin;      // first global segment index of this trace
     uint64_t nseg;
-    uint64_t* status;        // nseg * NWORD words
+    uint64_t* status;        // NWORD planes of nseg words (word w of segment j at w * nseg + j)
     Sample* samples;         // capacity n + 1
     uint32_t* sample_ptr;    // capacity n + 1, written for tracked samples
     Tracked* tracked;        // capacity n + 1
@@ -163,7 +163,37 @@ __device__ __forceinline__ int64_t wave_scan(int64_t x) {
     return x;
 }
 
-__device__ __forceinline__ int64_t wave_incl_sum(int64_t x) { return wave_scan<OpAdd>(x); }
+// 64-bit inclusive sum scan as carry-chained DPP adds, in place: each step
+// adds the shifted/broadcast value to the lane's own (lanes whose source is
+// outside the row, or whose row is masked off, keep their value).  The
+// s_nop 1 gives the two wait states a DPP read of a just-written VGPR needs.
+__device__ __forceinline__ int64_t wave_incl_sum(int64_t x) {
+    uint32_t lo = (uint32_t)(uint64_t)x, hi = (uint32_t)((uint64_t)x >> 32);
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_co_u32_dpp %0, vcc, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:0\n\t"
+        "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:0\n\t"
+        "s_nop 1\n\t"
+        "v_add_co_u32_dpp %0, vcc, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:0\n\t"
+        "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:0\n\t"
+        "s_nop 1\n\t"
+        "v_add_co_u32_dpp %0, vcc, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:0\n\t"
+        "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:0\n\t"
+        "s_nop 1\n\t"
+        "v_add_co_u32_dpp %0, vcc, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:0\n\t"
+        "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:0\n\t"
+        "s_nop 1\n\t"
+        "v_add_co_u32_dpp %0, vcc, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_co_u32_dpp %0, vcc, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        : "+v"(lo), "+v"(hi)
+        :
+        : "vcc");
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ int64_t wave_incl_max(int64_t x) { return wave_scan<OpMax>(x); }
 __device__ __forceinline__ int64_t wave_incl_min(int64_t x) { return wave_scan<OpMin>(x); }
 
@@ -173,7 +203,7 @@ __device__ __forceinline__ int64_t wave_shr1(int64_t x, int64_t old) {
 }
 
 // reductions: the inclusive scan's last lane, broadcast
-__device__ __forceinline__ int64_t wave_sum(int64_t x) { return readlane64(wave_scan<OpAdd>(x), 63); }
+__device__ __forceinline__ int64_t wave_sum(int64_t x) { return readlane64(wave_incl_sum(x), 63); }
 __device__ __forceinline__ int64_t wave_max(int64_t x) { return readlane64(wave_scan<OpMax>(x), 63); }
 __device__ __forceinline__ int64_t wave_min(int64_t x) { return readlane64(wave_scan<OpMin>(x), 63); }
 
@@ -188,6 +218,14 @@ __device__ __forceinline__ int64_t unpack(uint64_t w) {
     return (int64_t)(w & (((uint64_t)1 << 62) - 1)) - ((int64_t)1 << 61);
 }
 __device__ __forceinline__ uint32_t wstate(uint64_t w) { return (uint32_t)(w >> 62); }
+
+// The status words of one trace, stored plane by plane so that a wave reading
+// one word of 64 consecutive segments touches four cache lines.
+struct StatusView {
+    uint64_t* p;
+    int64_t ns;  // segments in the trace
+    __device__ __forceinline__ uint64_t* at(int word, int64_t seg) const { return p + (int64_t)word * ns + seg; }
+};
 
 __device__ __forceinline__ uint64_t ld_status(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -18,6 +18,9 @@ hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, uns
 hipError_t launch_sample(const Desc* desc, int ntraces, uint64_t nseg_total, unsigned long long* ticket, int grid,
                          hipStream_t s);
 hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines, hipStream_t s);
+#ifdef SMP_PHASE_STATS
+int read_lbstat(unsigned long long* out8, bool reset);
+#endif
 }  // namespace smp
 
 using namespace smp;
@@ -530,6 +533,10 @@ int trace_device_results(smp_sampler_t* s, uint64_t trace_id, void** samples, vo
     }
     return SMP_OK;
 }
+
+#ifdef SMP_PHASE_STATS
+SMP_API int sampler_lbstat(uint64_t* out8) { return smp::read_lbstat((unsigned long long*)out8, true); }
+#endif
 
 int sampler_last_counters(smp_sampler_t* s, uint64_t* out32) {
     if (!s || !out32) return SMP_EINVAL;

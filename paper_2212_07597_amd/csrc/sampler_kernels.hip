@@ -44,6 +44,15 @@
 
 namespace smp {
 
+#ifdef SMP_PHASE_STATS
+// look-back diagnostics: [0] sums iterations, [1] sums spins, [2] sums lim total,
+// [3] best iterations, [4] best spins, [5] best lim total, [6] ls spins, [7] chain slow path
+__device__ unsigned long long g_lbstat[8];
+#define LB_COUNT(i, v) do { if (lane_id() == 0) atomicAdd(&g_lbstat[i], (unsigned long long)(v)); } while (0)
+#else
+#define LB_COUNT(i, v) do {} while (0)
+#endif
+
 __device__ __forceinline__ int cache_to_hist(int c) {
     switch (c) {
         case C_PY: return H_PY;
@@ -62,8 +71,7 @@ __device__ __forceinline__ int cache_to_hist(int c) {
 struct SegLds {
     int64_t F[SEG];     // footprint after each event, relative to the segment start
     int64_t P[SEG];     // Python footprint after each event, relative
-    uint32_t line[SEG];
-    uint32_t ptr[SEG];
+    uint32_t ptr[SEG];  // line ids are re-read from the records at samples
 };
 
 struct HistCache {
@@ -131,9 +139,22 @@ __device__ __forceinline__ bool spin_abort(unsigned long long* ctl, Spin& sp) {
 // appear instead of one look-back at a time.  Identical values may be
 // written by several waves; a reader sees either copy.
 
-// Exclusive (F, P, C) prefix of segment g.
-__device__ bool scan_sums(uint64_t* status, int64_t g, int64_t& oF, int64_t& oP, int64_t& oC, unsigned long long* ctl) {
+// Exclusive (F, P, C) prefix of segment g.  Loads are kept small: the
+// predecessor's inclusive first (three lanes), then one state word per lane to
+// find the nearest published inclusive, then the aggregates of the segments
+// after it; a wait re-reads only the lanes still missing.
+__device__ bool scan_sums(const StatusView& sv, int64_t g, int64_t& oF, int64_t& oP, int64_t& oC, unsigned long long* ctl) {
     const int l = lane_id();
+    {
+        uint64_t v = 0;
+        if (l < 3) v = ld_status(sv.at(W_IF + l, g - 1));
+        if ((ballot(l < 3 && wstate(v)) & 7ull) == 7ull) {
+            oF = unpack(readlaneu64(v, 0));
+            oP = unpack(readlaneu64(v, 1));
+            oC = unpack(readlaneu64(v, 2));
+            return true;
+        }
+    }
     int64_t accF = 0, accP = 0, accC = 0;
     int64_t base = g - 1;
     bool first = true;
@@ -141,35 +162,43 @@ __device__ bool scan_sums(uint64_t* status, int64_t g, int64_t& oF, int64_t& oP,
     while (base >= 0) {
         const int64_t jj = base - l;
         const bool in = jj >= 0;
-        uint64_t iF = 0, iP = 0, iC = 0, aF = 0, aP = 0, aC = 0;
-        uint64_t* w = status + (in ? jj : 0) * NWORD;
-        if (in) {
-            iF = ld_status(w + W_IF);
-            iP = ld_status(w + W_IP);
-            iC = ld_status(w + W_IC);
-            aF = ld_status(w + W_AF);
-            aP = ld_status(w + W_AP);
-            aC = ld_status(w + W_AC);
-        }
-        const bool incl_ok = in && wstate(iF) && wstate(iP) && wstate(iC);
-        const uint64_t im = ballot(incl_ok);
+        const int64_t js = in ? jj : 0;
+        const uint64_t iF = in ? ld_status(sv.at(W_IF, js)) : 0;
+        const uint64_t im = ballot(in && wstate(iF));
         const int lim = im ? ctz64(im) : __popcll(ballot(in));
         const bool need = in && l < lim;
-        if (ballot(need && !(wstate(aF) && wstate(aP) && wstate(aC)))) {
-            if (spin_abort(ctl, sp)) return false;
-            continue;
-        }
         const bool at = im && l == lim;
-        const int64_t vF = need ? unpack(aF) : (at ? unpack(iF) : 0);
-        const int64_t vP = need ? unpack(aP) : (at ? unpack(iP) : 0);
-        const int64_t vC = need ? unpack(aC) : (at ? unpack(iC) : 0);
+        uint64_t x0 = 0, x1 = 0, x2 = 0;   // aggregate (need) or inclusive (at) words
+        bool have = !(need || at);
+        for (;;) {
+            if (!have) {
+                if (need) {
+                    x0 = ld_status(sv.at(W_AF, js));
+                    x1 = ld_status(sv.at(W_AP, js));
+                    x2 = ld_status(sv.at(W_AC, js));
+                } else {
+                    x0 = iF;
+                    x1 = ld_status(sv.at(W_IP, js));
+                    x2 = ld_status(sv.at(W_IC, js));
+                }
+                have = wstate(x0) && wstate(x1) && wstate(x2);
+            }
+            if (!ballot(!have)) break;
+            LB_COUNT(1, 1);
+            if (spin_abort(ctl, sp)) return false;
+        }
+        LB_COUNT(0, 1);
+        LB_COUNT(2, lim);
+        const int64_t vF = (need || at) ? unpack(x0) : 0;
+        const int64_t vP = (need || at) ? unpack(x1) : 0;
+        const int64_t vC = (need || at) ? unpack(x2) : 0;
         // suffix sums toward older segments: S_l = sum over lanes >= l
         const int64_t xF = wave_incl_sum(vF), xP = wave_incl_sum(vP), xC = wave_incl_sum(vC);
         const int64_t tF = readlane64(xF, 63), tP = readlane64(xP, 63), tC = readlane64(xC, 63);
-        if (first && im && need && !incl_ok) {
-            st_status(w + W_IF, pack(tF - xF + vF, 1));
-            st_status(w + W_IP, pack(tP - xP + vP, 1));
-            st_status(w + W_IC, pack(tC - xC + vC, 1));
+        if (first && im && need) {
+            st_status(sv.at(W_IF, js), pack(tF - xF + vF, 1));
+            st_status(sv.at(W_IP, js), pack(tP - xP + vP, 1));
+            st_status(sv.at(W_IC, js), pack(tC - xC + vC, 1));
         }
         accF += tF;
         accP += tP;
@@ -207,9 +236,23 @@ __device__ __forceinline__ int64_t lane_down(int64_t x, int d, int64_t fill) {
     return l + d < 64 ? y : fill;
 }
 
-// Exclusive Best prefix of segment g (baseline applied).
-__device__ bool scan_best(uint64_t* status, int64_t g, Best& out, unsigned long long* ctl) {
+// Exclusive Best prefix of segment g (baseline applied), loading as scan_sums.
+__device__ bool scan_best(const StatusView& sv, int64_t g, Best& out, unsigned long long* ctl) {
     const int l = lane_id();
+    {
+        uint64_t v = 0;
+        if (l < 4) v = ld_status(sv.at(W_ICNT + l, g - 1));
+        if ((ballot(l < 4 && wstate(v)) & 15ull) == 15ull) {
+            const uint64_t wg = readlaneu64(v, 1);
+            out.cnt = unpack(readlaneu64(v, 0));
+            out.has = wstate(wg) == 2;
+            out.val = unpack(wg);
+            out.idx = (uint32_t)unpack(readlaneu64(v, 2));
+            out.ptr = (uint32_t)unpack(readlaneu64(v, 3));
+            out = with_baseline(out);
+            return true;
+        }
+    }
     Best acc{0, false, 0, 0, 0};  // later segments combined so far
     int64_t base = g - 1;
     bool first = true;
@@ -217,23 +260,36 @@ __device__ bool scan_best(uint64_t* status, int64_t g, Best& out, unsigned long 
     while (base >= 0) {
         const int64_t jj = base - l;
         const bool in = jj >= 0;
-        uint64_t ic = 0, ig = 0, ir = 0, ip = 0, ac = 0, ag = 0, ar = 0, ap = 0;
-        uint64_t* w = status + (in ? jj : 0) * NWORD;
-        if (in) {
-            ic = ld_status(w + W_ICNT); ig = ld_status(w + W_IGM); ir = ld_status(w + W_IGR); ip = ld_status(w + W_IGP);
-            ac = ld_status(w + W_BCNT); ag = ld_status(w + W_BGM); ar = ld_status(w + W_BGR); ap = ld_status(w + W_BGP);
-        }
-        const bool incl_ok = in && wstate(ic) && wstate(ig) && wstate(ir) && wstate(ip);
-        const uint64_t im = ballot(incl_ok);
+        const int64_t js = in ? jj : 0;
+        const uint64_t ic = in ? ld_status(sv.at(W_ICNT, js)) : 0;
+        const uint64_t im = ballot(in && wstate(ic));
         const int lim = im ? ctz64(im) : __popcll(ballot(in));
         const bool need = in && l < lim;
-        if (ballot(need && !(wstate(ac) && wstate(ag) && wstate(ar) && wstate(ap)))) {
-            if (spin_abort(ctl, sp)) return false;
-            continue;
-        }
         const bool at = im && l == lim;
+        uint64_t c = 0, gm = 0, gr = 0, gp = 0;
+        bool have = !(need || at);
+        for (;;) {
+            if (!have) {
+                if (need) {
+                    c = ld_status(sv.at(W_BCNT, js));
+                    gm = ld_status(sv.at(W_BGM, js));
+                    gr = ld_status(sv.at(W_BGR, js));
+                    gp = ld_status(sv.at(W_BGP, js));
+                } else {
+                    c = ic;
+                    gm = ld_status(sv.at(W_IGM, js));
+                    gr = ld_status(sv.at(W_IGR, js));
+                    gp = ld_status(sv.at(W_IGP, js));
+                }
+                have = wstate(c) && wstate(gm) && wstate(gr) && wstate(gp);
+            }
+            if (!ballot(!have)) break;
+            LB_COUNT(4, 1);
+            if (spin_abort(ctl, sp)) return false;
+        }
+        LB_COUNT(3, 1);
+        LB_COUNT(5, lim);
         const bool use = need || at;
-        const uint64_t c = at ? ic : ac, gm = at ? ig : ag, gr = at ? ir : ar, gp = at ? ip : ap;
         const int64_t cnt = use ? unpack(c) : 0;
         const bool has = use && wstate(gm) == 2;
         const int64_t val = has ? unpack(gm) : INT64_MIN;
@@ -250,13 +306,13 @@ __device__ bool scan_best(uint64_t* status, int64_t g, Best& out, unsigned long 
         const uint64_t ge = bnd & ~lanemask_lt();
         const int src = ge ? ctz64(ge) : l;
         const uint32_t sidx = (uint32_t)shfl32((int)idx, src), sptr = (uint32_t)shfl32((int)ptr, src);
-        if (first && im && need && !incl_ok) {
+        if (first && im && need) {
             Best inc{tc - xc + cnt, M != INT64_MIN, M, sidx, sptr};
             inc = with_baseline(inc);
-            st_status(w + W_ICNT, pack(inc.cnt, 1));
-            st_status(w + W_IGM, pack(inc.val, inc.has ? 2 : 1));
-            st_status(w + W_IGR, pack((int64_t)inc.idx, 1));
-            st_status(w + W_IGP, pack((int64_t)inc.ptr, 1));
+            st_status(sv.at(W_ICNT, js), pack(inc.cnt, 1));
+            st_status(sv.at(W_IGM, js), pack(inc.val, inc.has ? 2 : 1));
+            st_status(sv.at(W_IGR, js), pack((int64_t)inc.idx, 1));
+            st_status(sv.at(W_IGP, js), pack((int64_t)inc.ptr, 1));
         }
         // the whole window (lane 0's suffix) comes before everything in acc
         Best win;
@@ -284,7 +340,7 @@ __device__ bool scan_best(uint64_t* status, int64_t g, Best& out, unsigned long 
 }
 
 // Absolute Python footprint at the last sample before segment g (0 if none).
-__device__ bool scan_last_sample(uint64_t* status, int64_t g, int64_t& oP, unsigned long long* ctl) {
+__device__ bool scan_last_sample(const StatusView& sv, int64_t g, int64_t& oP, unsigned long long* ctl) {
     const int l = lane_id();
     int64_t base = g - 1;
     bool first = true;
@@ -293,23 +349,24 @@ __device__ bool scan_last_sample(uint64_t* status, int64_t g, int64_t& oP, unsig
         const int64_t jj = base - l;
         const bool in = jj >= 0;
         uint64_t li = 0, la = 0;
-        uint64_t* w = status + (in ? jj : 0) * NWORD;
+        const int64_t js = in ? jj : 0;
         if (in) {
-            li = ld_status(w + W_LSI);
-            la = ld_status(w + W_LSA);
+            li = ld_status(sv.at(W_LSI, js));
+            la = ld_status(sv.at(W_LSA, js));
         }
         // a lane resolves the search if its segment has a sample or a known exit value
         const bool hit = in && (wstate(la) == 2 || wstate(li) != 0);
         const uint64_t hm = ballot(hit);
         const int lim = hm ? ctz64(hm) : __popcll(ballot(in));
         if (ballot(in && l < lim && wstate(la) == 0)) {
+            LB_COUNT(6, 1);
             if (spin_abort(ctl, sp)) return false;
             continue;
         }
         if (hm) {
             const uint64_t src_w = wstate(readlaneu64(la, lim)) == 2 ? readlaneu64(la, lim) : readlaneu64(li, lim);
             const int64_t v = unpack(src_w);
-            if (first && in && l < lim && wstate(li) == 0) st_status(w + W_LSI, pack(v, 1));
+            if (first && in && l < lim && wstate(li) == 0) st_status(sv.at(W_LSI, js), pack(v, 1));
             oP = v;
             return true;
         }
@@ -321,25 +378,26 @@ __device__ bool scan_last_sample(uint64_t* status, int64_t g, int64_t& oP, unsig
 }
 
 // Entry reference offset of segment g (relative to its first event).
-__device__ bool lookback_chain(const uint64_t* status, int64_t g, int64_t& eF, unsigned long long* ctl) {
+__device__ bool lookback_chain(const const StatusView& sv, int64_t g, int64_t& eF, unsigned long long* ctl) {
     const int l = lane_id();
     Spin sp;
     int i0;
     uint64_t xF;
     // fast path: the predecessor's exit (published early when its map is total)
     for (int tries = 0; tries < 3; ++tries) {
-        const uint64_t a = ld_status(status + (g - 1) * NWORD + W_XF);
+        const uint64_t a = ld_status(sv.at(W_XF, g - 1));
         if (wstate(a)) {
             eF = unpack(a);
             return true;
         }
         if (spin_abort(ctl, sp)) return false;
     }
+    LB_COUNT(7, 1);
     // nearest predecessor (within 64) that has published its exit
     for (;;) {
         const int64_t jj = g - 1 - l;
         const bool in = jj >= 0;
-        xF = in ? ld_status(status + jj * NWORD + W_XF) : 0;
+        xF = in ? ld_status(sv.at(W_XF, jj)) : 0;
         const uint64_t xm = ballot(in && wstate(xF));
         if (xm) {
             i0 = ctz64(xm);
@@ -350,16 +408,16 @@ __device__ bool lookback_chain(const uint64_t* status, int64_t g, int64_t& eF, u
     int64_t F = unpack(readlaneu64(xF, i0));
     // apply the maps of the segments after it, oldest first
     for (int i = i0 - 1; i >= 0; --i) {
-        const uint64_t* w = status + (g - 1 - i) * NWORD;
+        const int64_t js = g - 1 - i;
         Spin sp2;
         for (;;) {
-            const uint64_t x0 = ld_status(w + W_XF);
+            const uint64_t x0 = ld_status(sv.at(W_XF, js));
             if (wstate(x0)) {
                 F = unpack(x0);
                 break;
             }
-            const uint64_t lo = ld_status(w + W_MLO), hi = ld_status(w + W_MHI), cf = ld_status(w + W_MCF);
-            const uint64_t sf = ld_status(w + W_AF);
+            const uint64_t lo = ld_status(sv.at(W_MLO, js)), hi = ld_status(sv.at(W_MHI, js)), cf = ld_status(sv.at(W_MCF, js));
+            const uint64_t sf = ld_status(sv.at(W_AF, js));
             if (wstate(lo) && wstate(hi) && wstate(cf) && wstate(sf)) {
                 if (F >= unpack(lo) && F <= unpack(hi)) {
                     F -= unpack(sf);
@@ -496,7 +554,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
         const int nv = (int)((D.n - (uint64_t)a) < (uint64_t)SEG ? (D.n - (uint64_t)a) : (uint64_t)SEG);
         const int64_t T = D.T;
         const uint32_t L = D.L;
-        uint64_t* st = D.status + j * NWORD;
+        const StatusView sv{D.status, (int64_t)D.nseg};
         uint32_t err = 0;
         PH_MARK(0);
         PH_COUNT(12, 1);
@@ -520,10 +578,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
         int64_t cF = 0, cP = 0, cC = 0;
         int64_t mxF = INT64_MIN, mnF = INT64_MAX, mxP = INT64_MIN, mnP = INT64_MAX;
         uint64_t forced_v = 0, free_v = 0;   // lane w: mask of window w
-        int64_t sC[NW], dC[NW];
-        uint32_t lnC[NW];
-        uint64_t copym[NW];
-        bool any_copy = false;
+        int64_t accC = 0;                     // per-lane copy bytes
+        bool any_aux = false;                 // segment holds copy or timer events
         const int64_t two_t = 2 * T - 1;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
@@ -535,10 +591,11 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
             const uint32_t flags = (uint32_t)(q2[w] & 0xFF);
             const uint32_t kind = (flags >> 1) & 3;
             const bool py = (flags & 1) == 0;
-            bool bad = valid && (kind == 3 || line >= L);
-            if (valid && kind == 0) bad |= delta >= MAX_ABS_DELTA || delta <= -MAX_ABS_DELTA;
-            if (valid && kind == 1) bad |= delta < 0 || delta >= MAX_ABS_DELTA;
-            if (valid && kind == 2) bad |= delta < 0 || delta > (int64_t)0xFFFFFFFFll;
+            // memory: |delta| < 2^52; copy: 0 <= delta < 2^52; timer: 0 <= delta < 2^32
+            const uint64_t shifted = (uint64_t)delta + (kind == 0 ? (uint64_t)(MAX_ABS_DELTA - 1) : 0ull);
+            const uint64_t span = kind == 0 ? (uint64_t)(2 * MAX_ABS_DELTA - 1)
+                                            : (kind == 1 ? (uint64_t)MAX_ABS_DELTA : (1ull << 32));
+            const bool bad = valid && (kind == 3 || line >= L || shifted >= span);
             const bool ok = valid && !bad;
             const int64_t dm = (ok && kind == 0) ? delta : 0;
             const int64_t dp = py ? dm : 0;
@@ -554,20 +611,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
             const int64_t sP = wave_incl_sum(dp) + cP;
             cF = readlane64(sF, 63);
             cP = readlane64(sP, 63);
-            const uint64_t cm = ballot(dc != 0);
-            copym[w] = cm;
-            if (cm) {
-                any_copy = true;
-                sC[w] = wave_incl_sum(dc) + cC;
-                cC = readlane64(sC[w], 63);
-            } else {
-                sC[w] = cC;
-            }
-            dC[w] = dc;
-            lnC[w] = line;
+            accC += dc;
+            if (ballot(ok && kind != 0)) any_aux = true;
             S.F[k] = sF;
             S.P[k] = sP;
-            S.line[k] = line;
             S.ptr[k] = ptr;
             if (valid) {
                 mxF = sF > mxF ? sF : mxF;
@@ -575,13 +622,17 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
                 mxP = sP > mxP ? sP : mxP;
                 mnP = sP < mnP ? sP : mnP;
             }
-            // timer events: Python time += quantum, native time += delay (section 2.1)
-            const bool tim = ok && kind == 2;
-            if (ballot(tim) && tim) hist_add(hc, D, t, line, C_PT, D.q, C_NT, delta, -1, 0, -1, 0);
         }
+        cC = wave_sum(accC);
         const int64_t sumF = cF, sumP = cP, sumC = cC;
-        if (l < 3) st_status(st + W_AF + l, pack(l == 0 ? sumF : (l == 1 ? sumP : sumC), 1));
+        if (l < 3) st_status(sv.at(W_AF + l, j), pack(l == 0 ? sumF : (l == 1 ? sumP : sumC), 1));
         PH_MARK(1);
+
+        // ---- prefix sums from the preceding segments ------------------------
+        int64_t F0 = 0, P0 = 0, C0 = 0;
+        if (j > 0 && !scan_sums(sv, j, F0, P0, C0, ctl)) err |= 8u;
+        if (l < 3) st_status(sv.at(W_IF + l, j), pack(l == 0 ? F0 + sumF : (l == 1 ? P0 + sumP : C0 + sumC), 1));
+        PH_MARK(2);
 
         // ---- P2: all-entry analysis: the segment's map on entry states --------
         bool map_total = false;
@@ -599,10 +650,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
                 run_chain(S.F, T, p2run, fwin, flane, NW - 1, 64);
                 map_total = true;
                 map_kF = p2run.ref - sumF;
-                if (l == 0) st_status(st + W_MLO, pack(1, 1));
-                if (l == 1) st_status(st + W_MHI, pack(0, 1));
-                if (l == 2) st_status(st + W_MCF, pack(map_kF, 2));
-                if (l == 3) st_status(st + W_XF, pack(map_kF, 1));
+                if (l == 0) st_status(sv.at(W_MLO, j), pack(1, 1));
+                if (l == 1) st_status(sv.at(W_MHI, j), pack(0, 1));
+                if (l == 2) st_status(sv.at(W_MCF, j), pack(map_kF, 2));
+                if (l == 3) st_status(sv.at(W_XF, j), pack(map_kF, 1));
                 PH_COUNT(13, 1);
                 PH_COUNT(15, 1);
             }
@@ -696,26 +747,21 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
             int64_t kF = 0;
             if (has_const) kF = readlane64(chref, 0) - sumF;
             // publish the map
-            if (l == 0) st_status(st + W_MLO, pack(Lo, 1));
-            if (l == 1) st_status(st + W_MHI, pack(Hi, 1));
-            if (l == 2) st_status(st + W_MCF, pack(kF, has_const ? 2 : 1));
+            if (l == 0) st_status(sv.at(W_MLO, j), pack(Lo, 1));
+            if (l == 1) st_status(sv.at(W_MHI, j), pack(Hi, 1));
+            if (l == 2) st_status(sv.at(W_MCF, j), pack(kF, has_const ? 2 : 1));
             PH_COUNT(13, has_const ? 1 : 0);
             PH_COUNT(14, ovf ? 1 : 0);
             if (has_const && Lo > Hi) {
                 PH_COUNT(15, 1);
                 map_total = true;
                 map_kF = kF;
-                if (l == 0) st_status(st + W_XF, pack(kF, 1));
+                if (l == 0) st_status(sv.at(W_XF, j), pack(kF, 1));
             }
         }
 
         PH_MARK(4);
 
-        // ---- prefix sums from the preceding segments ------------------------
-        int64_t F0 = 0, P0 = 0, C0 = 0;
-        if (j > 0 && !scan_sums(D.status, j, F0, P0, C0, ctl)) err |= 8u;
-        if (l < 3) st_status(st + W_IF + l, pack(l == 0 ? F0 + sumF : (l == 1 ? P0 + sumP : C0 + sumC), 1));
-        PH_MARK(2);
 
         {
             const int64_t hiF = wave_max(mxF), loF = wave_min(mnF);
@@ -726,19 +772,46 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
             if (nv > 0 && F0 + hiF > peakF) peakF = F0 + hiF;
         }
 
-        // copy volume: one Tc sample per multiple of Tc crossed (section 3.5)
-        if (any_copy) {
-#pragma unroll
+        // Copy volume (section 3.5: one Tc sample per multiple of Tc crossed by
+        // the cumulative copy bytes) and the timer split (section 2.1: Python
+        // time += quantum, native time += delay).  Only segments that hold such
+        // events re-read their records here.
+        if (any_aux) {
+            int64_t cc = C0;
             for (int w = 0; w < NW; ++w) {
-                if (copym[w] && dC[w] != 0) {
-                    const uint64_t cout = (uint64_t)(C0 + sC[w]);
-                    const uint64_t cin = cout - (uint64_t)dC[w];
-                    uint64_t ns;
-                    if (D.tc_shift >= 0)
-                        ns = (cout >> D.tc_shift) - (cin >> D.tc_shift);
-                    else
-                        ns = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
-                    hist_add(hc, D, t, lnC[w], C_CS, (int64_t)(ns * (uint64_t)D.Tc), C_CE, dC[w], -1, 0, -1, 0);
+                const int k = w * 64 + l;
+                uint64_t r0 = 0, r1 = 0, r2 = 0;
+                if (k < nv) {
+                    const uint64_t* rp = (const uint64_t*)(D.ev + (size_t)(a + k) * 24);
+                    r0 = rp[0];
+                    r1 = rp[1];
+                    r2 = rp[2];
+                }
+                const int64_t delta = (int64_t)r0;
+                const uint32_t line = (uint32_t)(r1 >> 32);
+                const uint32_t kind = ((uint32_t)r2 >> 1) & 3;
+                const bool lok = k < nv && line < L;
+                const bool cp = lok && kind == 1 && delta >= 0 && delta < MAX_ABS_DELTA;
+                const bool tm = lok && kind == 2 && delta >= 0 && delta <= (int64_t)0xFFFFFFFFll;
+                const int64_t dc = cp ? delta : 0;
+                const int64_t sc = wave_incl_sum(dc) + cc;
+                cc = readlane64(sc, 63);
+                if (cp || tm) {
+                    int c0 = C_PT, c1 = C_NT;
+                    int64_t v0 = D.q, v1 = delta;
+                    if (cp) {
+                        const uint64_t cout = (uint64_t)sc, cin = cout - (uint64_t)dc;
+                        uint64_t ns;
+                        if (D.tc_shift >= 0)
+                            ns = (cout >> D.tc_shift) - (cin >> D.tc_shift);
+                        else
+                            ns = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
+                        c0 = C_CS;
+                        c1 = C_CE;
+                        v0 = (int64_t)(ns * (uint64_t)D.Tc);
+                        v1 = dc;
+                    }
+                    hist_add(hc, D, t, line, c0, v0, c1, v1, -1, 0, -1, 0);
                 }
             }
         }
@@ -747,7 +820,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
 
         // ---- P4: entry state, then the segment's own samples -----------------
         int64_t eF = 0;
-        if (j > 0 && !lookback_chain(D.status, j, eF, ctl)) err |= 8u;
+        if (j > 0 && !lookback_chain(sv, j, eF, ctl)) err |= 8u;
         PH_MARK(5);
         ChainRun cr{eF, 0, 0, -1, INT64_MIN, -1};
         if (fwin >= 0) {
@@ -779,7 +852,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
         const int64_t smax = cr.smax;
         const int64_t xF = ref - sumF;
         if (!map_total) {
-            if (l == 0) st_status(st + W_XF, pack(xF, 1));
+            if (l == 0) st_status(sv.at(W_XF, j), pack(xF, 1));
         } else if (xF != map_kF) {
             err |= 4u;  // internal: the all-entry map disagrees with the simulated chain
         }
@@ -793,14 +866,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
             const int64_t gval = F0 + gbest;
             const uint32_t gidx = hg ? (uint32_t)(a + gnode) : 0u;
             const uint32_t gptr = hg ? S.ptr[gnode] : 0u;
-            if (l == 0) st_status(st + W_BCNT, pack(count, 1));
-            if (l == 1) st_status(st + W_BGM, pack(hg ? gval : 0, hg ? 2 : 1));
-            if (l == 2) st_status(st + W_BGR, pack((int64_t)gidx, 1));
-            if (l == 3) st_status(st + W_BGP, pack((int64_t)gptr, 1));
+            if (l == 0) st_status(sv.at(W_BCNT, j), pack(count, 1));
+            if (l == 1) st_status(sv.at(W_BGM, j), pack(hg ? gval : 0, hg ? 2 : 1));
+            if (l == 2) st_status(sv.at(W_BGR, j), pack((int64_t)gidx, 1));
+            if (l == 3) st_status(sv.at(W_BGP, j), pack((int64_t)gptr, 1));
             const int64_t lsP = lastS >= 0 ? P0 + S.P[lastS] : 0;
-            if (l == 4) st_status(st + W_LSA, pack(lsP, lastS >= 0 ? 2 : 1));
+            if (l == 4) st_status(sv.at(W_LSA, j), pack(lsP, lastS >= 0 ? 2 : 1));
             Best pre{0, false, 0, 0, 0};
-            if (j > 0 && !scan_best(D.status, j, pre, ctl)) err |= 8u;
+            if (j > 0 && !scan_best(sv, j, pre, ctl)) err |= 8u;
             {
                 Best inc = pre;
                 inc.cnt += count;
@@ -810,14 +883,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
                     inc.idx = gidx;
                     inc.ptr = gptr;
                 }
-                if (l == 0) st_status(st + W_ICNT, pack(inc.cnt, 1));
-                if (l == 1) st_status(st + W_IGM, pack(inc.has ? inc.val : 0, inc.has ? 2 : 1));
-                if (l == 2) st_status(st + W_IGR, pack((int64_t)inc.idx, 1));
-                if (l == 3) st_status(st + W_IGP, pack((int64_t)inc.ptr, 1));
+                if (l == 0) st_status(sv.at(W_ICNT, j), pack(inc.cnt, 1));
+                if (l == 1) st_status(sv.at(W_IGM, j), pack(inc.has ? inc.val : 0, inc.has ? 2 : 1));
+                if (l == 2) st_status(sv.at(W_IGR, j), pack((int64_t)inc.idx, 1));
+                if (l == 3) st_status(sv.at(W_IGP, j), pack((int64_t)inc.ptr, 1));
             }
             int64_t eP = 0;
-            if (j > 0 && !scan_last_sample(D.status, j, eP, ctl)) err |= 8u;
-            if (l == 0) st_status(st + W_LSI, pack(lastS >= 0 ? lsP : eP, 1));
+            if (j > 0 && !scan_last_sample(sv, j, eP, ctl)) err |= 8u;
+            if (l == 0) st_status(sv.at(W_LSI, j), pack(lastS >= 0 ? lsP : eP, 1));
             int64_t base = pre.cnt, hv = pre.val;
             bool hh = pre.has;
             uint32_t hidx = pre.idx, hptr = pre.ptr;
@@ -844,7 +917,6 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
                 const int k = w * 64 + l;
                 const int64_t f = S.F[k];
                 const int64_t p = S.P[k];
-                const uint32_t ln = S.line[k];
                 const uint32_t pt = S.ptr[k];
                 const uint64_t below = m & lanemask_lt();
                 uint64_t tmask = 0;
@@ -862,6 +934,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
                     const int64_t Fabs = F0 + f;
                     const int64_t rank = base + cnt + __popcll(below);
                     if (is_s && rank < (int64_t)D.n) {
+                        const uint32_t ln = ((const uint32_t*)(D.ev + (size_t)(a + k) * 24))[3];
                         Sample smp;
                         smp.event_idx = (uint32_t)(a + k);
                         smp.line = ln;
@@ -870,10 +943,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
                         smp.nat = nat;
                         D.samples[rank] = smp;
                         if (ln < L) {
-                            if (dl > 0)
-                                hist_add(hc, D, t, ln, C_PY, pyb, C_NAT, nat, C_GN, 1, C_GB, dl);
-                            else
-                                hist_add(hc, D, t, ln, C_PY, pyb, C_NAT, nat, C_SN, 1, C_SB, -dl);
+                            const bool gr = dl > 0;
+                            hist_add(hc, D, t, ln, C_PY, pyb, C_NAT, nat, gr ? C_GN : C_SN, 1, gr ? C_GB : C_SB,
+                                     gr ? dl : -dl);
                         }
                     }
                     uint64_t cand = ballot(is_s && dl > 0 && Fabs > hwm);
@@ -1129,6 +1201,17 @@ __global__ void k_leak_finalize(const Desc* __restrict__ desc, int ntraces, uint
 }
 
 // ------------------------------------------------------------ launchers
+
+#ifdef SMP_PHASE_STATS
+int read_lbstat(unsigned long long* out8, bool reset) {
+    if (hipMemcpyFromSymbol(out8, HIP_SYMBOL(g_lbstat), 8 * sizeof(unsigned long long)) != hipSuccess) return -1;
+    if (reset) {
+        unsigned long long z[8] = {0};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_lbstat), z, sizeof(z)) != hipSuccess) return -1;
+    }
+    return 0;
+}
+#endif
 
 int sample_grid_limit() {
     int dev = 0, cus = 0, per = 0;
