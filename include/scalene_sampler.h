@@ -213,13 +213,19 @@ SMP_API int fetch_profile(smp_sampler_t *s, uint64_t trace_id, smp_profile_sizes
 SMP_API int trace_device_results(smp_sampler_t *s, uint64_t trace_id, void **samples, void **hist,
                                  uint64_t *n_samples);
 
-/* Timing of the last run() (milliseconds, HIP events on the sampler's
- * stream): the main sampling kernel alone, and the whole launch sequence. */
+/* Timing of the last run() (milliseconds, HIP events on the launch's
+ * stream): the five sampling passes together (summarize, resolve, chain,
+ * scan, emit), and the whole launch sequence including clearing, the
+ * tracked-list compaction and the leak rationals. */
 SMP_API int sampler_last_timing(smp_sampler_t *s, float *main_kernel_ms, float *total_ms);
 
-/* Diagnostics: the 32 control words of the last launch (word 0: segment
- * tickets handed out, word 1: abort flag; words 8-23 hold per-phase cycle
- * counts only in builds with SMP_PHASE_STATS, else 0). */
+/* Per-pass timing of the last run(): pass_ms[0..4] = summarize, resolve,
+ * chain, scan, emit (milliseconds, HIP events around each kernel on the
+ * launch's stream).  pass_ms must hold 5 floats. */
+SMP_API int sampler_last_pass_timing(smp_sampler_t *s, float *pass_ms);
+
+/* Diagnostics: the 32 control words of the last launch (word 1: abort flag,
+ * words 2 and 3: tiles taken by the resolve and scan passes). */
 SMP_API int sampler_last_counters(smp_sampler_t *s, uint64_t *out32);
 
 /* Bytes of the workspace the sampler keeps for itself (descriptor tables,

@@ -29,8 +29,10 @@ SAMPLE_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("F", "<i8"), ("
 TRACKED_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("ptr", "<u4"), ("freed", "<u4")])
 
 EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", "fetch_profile",
-            "trace_device_results", "sampler_last_timing", "sampler_last_counters", "sampler_fixed_bytes",
-            "sampler_destroy", "error_string")
+            "trace_device_results", "sampler_last_timing", "sampler_last_pass_timing", "sampler_last_counters",
+            "sampler_fixed_bytes", "sampler_destroy", "error_string")
+
+PASS_NAMES = ("summarize", "resolve", "chain", "scan", "emit")
 
 
 class Params(ctypes.Structure):
@@ -104,6 +106,8 @@ def lib():
         L.trace_device_results.restype = i32
         L.sampler_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
         L.sampler_last_timing.restype = i32
+        L.sampler_last_pass_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+        L.sampler_last_pass_timing.restype = i32
         L.sampler_last_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
         L.sampler_last_counters.restype = i32
         L.sampler_fixed_bytes.argtypes = []
@@ -252,6 +256,12 @@ class Sampler:
         a, b = ctypes.c_float(), ctypes.c_float()
         _check("sampler_last_timing", lib().sampler_last_timing(self.h, ctypes.byref(a), ctypes.byref(b)))
         return float(a.value), float(b.value)
+
+    def last_pass_timing(self):
+        """Milliseconds of each sampling pass of the last run, by PASS_NAMES."""
+        buf = (ctypes.c_float * len(PASS_NAMES))()
+        _check("sampler_last_pass_timing", lib().sampler_last_pass_timing(self.h, buf))
+        return dict(zip(PASS_NAMES, (float(x) for x in buf)))
 
     def last_counters(self):
         buf = (ctypes.c_uint64 * 32)()

@@ -8,15 +8,18 @@ namespace smp {
 
 // ---- tiling --------------------------------------------------------------
 // A segment is NW windows of 64 events; one wavefront owns a segment at a time
-// (lane l of window w holds event 64*w + l of the segment).
+// (lane l of window w holds event 64*w + l of the segment).  The two passes
+// that combine segments work on tiles of TILE consecutive segments of one
+// trace, one segment per thread.
 constexpr int NW = 8;
 constexpr int SEG = 64 * NW;
-constexpr int WAVES = 4;                 // wavefronts per workgroup
+constexpr int WAVES = 4;                 // wavefronts per workgroup of the per-segment passes
 constexpr int BLOCK = 64 * WAVES;
+constexpr int TILE = 1024;               // segments per tile
+constexpr int TWAVES = TILE / 64;
 constexpr int NSLOT = 128;               // LDS histogram cache slots per workgroup
 constexpr int NCNT = 10;                 // counters cached per slot
 constexpr int CHAIN_CAP = 32;            // chains followed by the all-entry analysis
-constexpr int NWORD = 20;                // status words per segment
 
 constexpr int64_t MAX_ABS_DELTA = (int64_t)1 << 52;
 constexpr int64_t MAX_ABS_F = (int64_t)1 << 61;
@@ -25,17 +28,36 @@ constexpr int64_t MAX_ABS_F = (int64_t)1 << 61;
 enum { H_PY = 0, H_NAT, H_GN, H_SN, H_GB, H_SB, H_LEAK_M, H_LEAK_F, H_CS, H_CE, H_PT, H_NT, H_COUNT };
 enum { C_PY = 0, C_NAT, C_GN, C_SN, C_GB, C_SB, C_CS, C_CE, C_PT, C_NT };
 
-// status words of one segment (each: 2-bit state | 62-bit payload, written once per run)
+// Chain map of a segment over entry offsets: entries in [lo, hi] take no
+// sample; every other entry ends at one exit offset (CONST; TOTAL when the
+// interval is empty) or depends on the entry (SIM: follow the records).
+enum { MAP_SIM = 0, MAP_CONST = 1, MAP_TOTAL = 2 };
+
+// Per-segment values, one int64 plane each (plane p of segment j at
+// seg[p * nseg + j]), written once per run by the pass named.
+enum {
+    // summary pass: sums, extremes of the relative prefixes, chain map
+    SP_AF = 0, SP_AP, SP_AC, SP_MXF, SP_MNF, SP_MXP, SP_MNP, SP_LO, SP_HI, SP_KF, SP_KIND,
+    // resolve pass: exclusive prefixes, entry and exit offsets of the chain
+    SP_F0, SP_P0, SP_C0, SP_EF, SP_XF,
+    // chain pass: samples, best growth sample (value, event, ptr), Python footprint at the last sample, flags
+    SP_BCNT, SP_BGV, SP_BGI, SP_BGP, SP_LSV, SP_BFL,
+    // scan pass: state before the segment (rank base, high-water mark record, flags, last-sample Python footprint)
+    SP_XCNT, SP_XHV, SP_XHI, SP_XHP, SP_XFL, SP_XLS,
+    NSPLANE
+};
+
+// Look-back status words of one tile (each: 2-bit state | 62-bit payload,
+// written once per run; stored plane by plane like the segment values).
 enum {
     W_AF = 0, W_AP, W_AC,          // aggregate sums: footprint, Python footprint, copy bytes
     W_IF, W_IP, W_IC,              // inclusive prefixes of the same
-    W_MLO, W_MHI,                  // chain map: entry offsets [lo, hi] that take no sample here
-    W_MCF,                         // chain map: exit offset for every other entry (state 2) or none (1)
-    W_XF,                          // final exit offset (reference minus footprint at the segment end)
+    W_XF,                          // exit offset of the chain at the tile end
     W_BCNT, W_BGM, W_BGR, W_BGP,   // aggregate: samples, best growth footprint (2 = present), its event, its ptr
     W_ICNT, W_IGM, W_IGR, W_IGP,   // inclusive of the same
-    W_LSA,                         // Python footprint at this segment's last sample (2) or no sample (1)
-    W_LSI,                         // Python footprint at the last sample up to this segment's end
+    W_LSA,                         // Python footprint at the tile's last sample (2) or no sample (1)
+    W_LSI,                         // Python footprint at the last sample up to the tile's end
+    NWORD
 };
 
 struct Sample {
@@ -59,7 +81,7 @@ struct Scalars {
     int64_t peak_S;
     uint64_t K;
     uint64_t H;
-    uint32_t err;      // bit 0: malformed event, bit 1: overflow
+    uint32_t err;      // bit 0: malformed event, bit 1: overflow, bits 2-3: internal fault
     uint32_t pad;
     uint64_t reserved[2];
 };
@@ -77,7 +99,11 @@ struct Desc {
     uint32_t pad0;
     uint64_t seg_begin;      // first global segment index of this trace
     uint64_t nseg;
-    uint64_t* status;        // NWORD planes of nseg words (word w of segment j at w * nseg + j)
+    uint64_t tile_begin;     // first global tile index of this trace
+    uint64_t ntile;
+    int64_t* seg;            // NSPLANE planes of nseg values
+    uint64_t* mask;          // NW sample masks per segment
+    uint64_t* tstat;         // NWORD planes of ntile status words
     Sample* samples;         // capacity n + 1
     uint32_t* sample_ptr;    // capacity n + 1, written for tracked samples
     Tracked* tracked;        // capacity n + 1
@@ -219,11 +245,11 @@ __device__ __forceinline__ int64_t unpack(uint64_t w) {
 }
 __device__ __forceinline__ uint32_t wstate(uint64_t w) { return (uint32_t)(w >> 62); }
 
-// The status words of one trace, stored plane by plane so that a wave reading
-// one word of 64 consecutive segments touches four cache lines.
+// The tile status words of one trace, stored plane by plane so that a wave
+// reading one word of 64 consecutive tiles touches four cache lines.
 struct StatusView {
     uint64_t* p;
-    int64_t ns;  // segments in the trace
+    int64_t ns;  // tiles in the trace
     __device__ __forceinline__ uint64_t* at(int word, int64_t seg) const { return p + (int64_t)word * ns + seg; }
 };
 

@@ -13,14 +13,12 @@
 #include "scalene_sampler.h"
 
 namespace smp {
-int sample_grid_limit();
-hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, unsigned long long* ticket, hipStream_t s);
-hipError_t launch_sample(const Desc* desc, int ntraces, uint64_t nseg_total, unsigned long long* ticket, int grid,
-                         hipStream_t s);
+int chain_grid_limit();
+int emit_grid_limit();
+hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, unsigned long long* ctl, hipStream_t s);
+hipError_t launch_pass(int pass, const Desc* desc, int ntraces, uint64_t nseg_total, uint64_t ntile_total,
+                       unsigned long long* ctl, int grid_limit, hipStream_t s);
 hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines, hipStream_t s);
-#ifdef SMP_PHASE_STATS
-int read_lbstat(unsigned long long* out8, bool reset);
-#endif
 }  // namespace smp
 
 using namespace smp;
@@ -35,6 +33,7 @@ constexpr uint64_t ALIGN = 256;
 constexpr int RUN_SLOTS = 8;
 constexpr int MAX_TRACES_PER_RUN = 4096;
 constexpr uint64_t CBLK_WORDS = 1024;
+constexpr int NPASS = 5;  // summarize, resolve, chain, scan, emit
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -80,15 +79,16 @@ bool is_prime_mr(uint64_t n) {
 
 // Byte layout of one trace's region in the workspace.
 struct Layout {
-    uint64_t nseg, words, nblk;
-    uint64_t ev, samples, sample_ptr, tracked;  // offsets
-    uint64_t zero, status, tracked_bits, freed_bits, hist, leak, gates, scal, blk, zero_end;
+    uint64_t nseg, ntile, words, nblk;
+    uint64_t ev, samples, sample_ptr, tracked, seg, mask;  // offsets
+    uint64_t zero, tstat, tracked_bits, freed_bits, hist, leak, gates, scal, blk, zero_end;
     uint64_t total;
 };
 
 Layout make_layout(uint64_t n, uint32_t L, bool ev_copy) {
     Layout y{};
     y.nseg = (n + SEG - 1) / SEG;
+    y.ntile = (y.nseg + TILE - 1) / TILE;
     y.words = (n + 1 + 63) / 64;
     y.nblk = (y.words + CBLK_WORDS - 1) / CBLK_WORDS;
     uint64_t o = 0;
@@ -100,9 +100,13 @@ Layout make_layout(uint64_t n, uint32_t L, bool ev_copy) {
     o = align_up(o + 4 * (n + 1), ALIGN);
     y.tracked = o;
     o = align_up(o + sizeof(Tracked) * (n + 1), ALIGN);
+    y.seg = o;
+    o = align_up(o + 8 * (uint64_t)NSPLANE * y.nseg, ALIGN);
+    y.mask = o;
+    o = align_up(o + 8 * (uint64_t)NW * y.nseg, ALIGN);
     y.zero = o;
-    y.status = o;
-    o += 8 * NWORD * y.nseg;
+    y.tstat = o;
+    o += 8 * (uint64_t)NWORD * y.ntile;
     y.tracked_bits = o;
     o += 8 * y.words;
     y.freed_bits = o;
@@ -149,7 +153,8 @@ struct RunSlot {
     unsigned long long* dev_ticket = nullptr;
     hipStream_t stream = nullptr;  // launches of this slot; ordered after the caller's stream
     hipEvent_t e_ready = nullptr;  // recorded on the caller's stream at run()
-    hipEvent_t e_start = nullptr, e_main0 = nullptr, e_main1 = nullptr, e_end = nullptr;
+    hipEvent_t e_start = nullptr, e_end = nullptr;
+    hipEvent_t e_pass[NPASS + 1] = {};  // around each pass of the sampling kernels
     bool busy = false;
     uint64_t seq = 0;
 };
@@ -169,9 +174,10 @@ struct smp_sampler {
     RunSlot slots[RUN_SLOTS];
     uint64_t next_id = 1;
     uint64_t run_seq = 0;
-    int grid = 0;
+    int grid_chain = 0, grid_emit = 0;
     bool failed = false;
     float last_main_ms = 0, last_total_ms = 0;
+    float last_pass_ms[NPASS] = {};
     uint64_t last_seq = 0;
 };
 
@@ -225,13 +231,15 @@ int fail(smp_sampler* s) {
 int retire_slot(smp_sampler* s, RunSlot& r) {
     if (!r.busy) return SMP_OK;
     HIPCHK(hipEventSynchronize(r.e_end));
-    float a = 0, b = 0;
-    HIPCHK(hipEventElapsedTime(&a, r.e_main0, r.e_main1));
+    float a = 0, b = 0, p[NPASS] = {};
+    HIPCHK(hipEventElapsedTime(&a, r.e_pass[0], r.e_pass[NPASS]));
     HIPCHK(hipEventElapsedTime(&b, r.e_start, r.e_end));
+    for (int i = 0; i < NPASS; ++i) HIPCHK(hipEventElapsedTime(&p[i], r.e_pass[i], r.e_pass[i + 1]));
     if (r.seq >= s->last_seq) {
         s->last_seq = r.seq;
         s->last_main_ms = a;
         s->last_total_ms = b;
+        for (int i = 0; i < NPASS; ++i) s->last_pass_ms[i] = p[i];
     }
     r.busy = false;
     return SMP_OK;
@@ -292,14 +300,20 @@ int sampler_create(int device, void* hip_stream, uint64_t mem_budget, void* work
         if (hipHostMalloc((void**)&r.host_desc, sizeof(Desc) * MAX_TRACES_PER_RUN, hipHostMallocDefault) != hipSuccess ||
             hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&r.e_ready, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreate(&r.e_start) != hipSuccess || hipEventCreate(&r.e_main0) != hipSuccess ||
-            hipEventCreate(&r.e_main1) != hipSuccess || hipEventCreate(&r.e_end) != hipSuccess) {
+            hipEventCreate(&r.e_start) != hipSuccess || hipEventCreate(&r.e_end) != hipSuccess) {
             sampler_destroy(s);
             return SMP_EDEVICE;
         }
+        for (auto& e : r.e_pass) {
+            if (hipEventCreate(&e) != hipSuccess) {
+                sampler_destroy(s);
+                return SMP_EDEVICE;
+            }
+        }
     }
-    s->grid = sample_grid_limit();
-    if (s->grid <= 0) {
+    s->grid_chain = chain_grid_limit();
+    s->grid_emit = emit_grid_limit();
+    if (s->grid_chain <= 0 || s->grid_emit <= 0) {
         sampler_destroy(s);
         return SMP_EDEVICE;
     }
@@ -318,8 +332,8 @@ void sampler_destroy(smp_sampler_t* s) {
         if (r.stream) (void)hipStreamDestroy(r.stream);
         if (r.e_ready) (void)hipEventDestroy(r.e_ready);
         if (r.e_start) (void)hipEventDestroy(r.e_start);
-        if (r.e_main0) (void)hipEventDestroy(r.e_main0);
-        if (r.e_main1) (void)hipEventDestroy(r.e_main1);
+        for (auto& e : r.e_pass)
+            if (e) (void)hipEventDestroy(e);
         if (r.e_end) (void)hipEventDestroy(r.e_end);
     }
     delete s;
@@ -390,7 +404,7 @@ int run(smp_sampler_t* s, int blocking) {
         }
         RunSlot& r = s->slots[si];
         if (int rc = retire_slot(s, r)) return rc;
-        uint64_t seg = 0, blk = 0, zero = 0, lines = 0;
+        uint64_t seg = 0, tile = 0, blk = 0, zero = 0, lines = 0;
         for (size_t k = 0; k < cnt; ++k) {
             TraceRec& t = *pend[done + k];
             Desc& D = r.host_desc[k];
@@ -407,7 +421,11 @@ int run(smp_sampler_t* s, int blocking) {
             if ((D.Tc & (D.Tc - 1)) == 0) D.tc_shift = __builtin_ctzll((uint64_t)D.Tc);
             D.seg_begin = seg;
             D.nseg = t.lay.nseg;
-            D.status = (uint64_t*)(base + t.lay.status);
+            D.tile_begin = tile;
+            D.ntile = t.lay.ntile;
+            D.seg = (int64_t*)(base + t.lay.seg);
+            D.mask = (uint64_t*)(base + t.lay.mask);
+            D.tstat = (uint64_t*)(base + t.lay.tstat);
             D.samples = (Sample*)(base + t.lay.samples);
             D.sample_ptr = (uint32_t*)(base + t.lay.sample_ptr);
             D.tracked = (Tracked*)(base + t.lay.tracked);
@@ -425,6 +443,7 @@ int run(smp_sampler_t* s, int blocking) {
             D.zero_begin = zero;
             D.line_begin = lines;
             seg += D.nseg;
+            tile += D.ntile;
             blk += D.nblk;
             zero += D.zero_bytes;
             lines += D.L;
@@ -439,11 +458,12 @@ int run(smp_sampler_t* s, int blocking) {
         HIPCHK(hipMemcpyAsync(r.dev_desc, r.host_desc, sizeof(Desc) * cnt, hipMemcpyHostToDevice, r.stream));
         HIPCHK(hipEventRecord(r.e_start, r.stream));
         HIPCHK(launch_clear(r.dev_desc, (int)cnt, zero, r.dev_ticket, r.stream));
-        HIPCHK(hipEventRecord(r.e_main0, r.stream));
-        const uint64_t want = (seg + WAVES - 1) / WAVES;
-        const int grid = (int)std::min<uint64_t>(want ? want : 1, (uint64_t)s->grid);
-        HIPCHK(launch_sample(r.dev_desc, (int)cnt, seg, r.dev_ticket, grid, r.stream));
-        HIPCHK(hipEventRecord(r.e_main1, r.stream));
+        for (int p = 0; p < NPASS; ++p) {
+            HIPCHK(hipEventRecord(r.e_pass[p], r.stream));
+            const int lim = p == 2 ? s->grid_chain : s->grid_emit;
+            HIPCHK(launch_pass(p, r.dev_desc, (int)cnt, seg, tile, r.dev_ticket, lim, r.stream));
+        }
+        HIPCHK(hipEventRecord(r.e_pass[NPASS], r.stream));
         HIPCHK(launch_finish(r.dev_desc, (int)cnt, blk, lines, r.stream));
         HIPCHK(hipEventRecord(r.e_end, r.stream));
         r.busy = true;
@@ -534,10 +554,6 @@ int trace_device_results(smp_sampler_t* s, uint64_t trace_id, void** samples, vo
     return SMP_OK;
 }
 
-#ifdef SMP_PHASE_STATS
-SMP_API int sampler_lbstat(uint64_t* out8) { return smp::read_lbstat((unsigned long long*)out8, true); }
-#endif
-
 int sampler_last_counters(smp_sampler_t* s, uint64_t* out32) {
     if (!s || !out32) return SMP_EINVAL;
     if (s->failed) return SMP_EDEVICE;
@@ -557,6 +573,15 @@ int sampler_last_timing(smp_sampler_t* s, float* main_kernel_ms, float* total_ms
         if (int rc = retire_slot(s, r)) return rc;
     if (main_kernel_ms) *main_kernel_ms = s->last_main_ms;
     if (total_ms) *total_ms = s->last_total_ms;
+    return SMP_OK;
+}
+
+int sampler_last_pass_timing(smp_sampler_t* s, float* pass_ms) {
+    if (!s || !pass_ms) return SMP_EINVAL;
+    if (s->failed) return SMP_EDEVICE;
+    for (auto& r : s->slots)
+        if (int rc = retire_slot(s, r)) return rc;
+    for (int i = 0; i < NPASS; ++i) pass_ms[i] = s->last_pass_ms[i];
     return SMP_OK;
 }
 

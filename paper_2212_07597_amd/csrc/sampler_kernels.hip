@@ -13,9 +13,7 @@
 //    form one interval and are shifted by the segment's footprint change; every
 //    other entry starts a chain at a running-maximum or running-minimum node,
 //    and chains that sample at the same node coincide from there on.  When all
-//    of them coincide the segment's exit is known before its entry is, so
-//    segments hand their state on without waiting (a decoupled look-back over
-//    maps instead of sums).
+//    of them coincide the segment's exit is known before its entry is.
 //  * Attribution (section 3.3): each sample goes to the triggering event's
 //    line with the net Python and native bytes since the previous sample.
 //  * Leak rule (section 3.4): a growth sample above the high-water mark of the
@@ -25,33 +23,16 @@
 //    growth footprint, earliest on ties).
 //  * Copy volume (section 3.5) and the timer split (section 2.1) are
 //    per-event histogram updates.
+//
+// Passes of one launch (no pass over the records waits on another segment):
+//   summarize  per segment: sums, prefix extremes, chain map        (records)
+//   resolve    per tile:    exclusive sums, entry offset of each segment
+//   chain      per segment: samples, best growth sample, last sample (records)
+//   scan       per tile:    rank base, high-water mark, last sample before
+//   emit       per segment: samples, per-line histograms, leak bits (records)
 #include "sampler_device.h"
 
-// Optional per-phase cycle counters (diagnostic builds only, -DSMP_PHASE_STATS):
-// each wave accumulates shader-clock cycles per phase and a few event counts,
-// then adds them once to ctl[8 + i] at exit.
-#ifdef SMP_PHASE_STATS
-#define PH_DECL uint64_t ph[16] = {0}; uint64_t ph_t = clock64();
-#define PH_MARK(i) do { const uint64_t _n = clock64(); ph[i] += _n - ph_t; ph_t = _n; } while (0)
-#define PH_COUNT(i, v) ph[i] += (uint64_t)(v)
-#define PH_FLUSH(ctl) do { if (lane_id() == 0) for (int _i = 0; _i < 16; ++_i) atomicAdd(&(ctl)[8 + _i], ph[_i]); } while (0)
-#else
-#define PH_DECL
-#define PH_MARK(i) do {} while (0)
-#define PH_COUNT(i, v) do {} while (0)
-#define PH_FLUSH(ctl) do {} while (0)
-#endif
-
 namespace smp {
-
-#ifdef SMP_PHASE_STATS
-// look-back diagnostics: [0] sums iterations, [1] sums spins, [2] sums lim total,
-// [3] best iterations, [4] best spins, [5] best lim total, [6] ls spins, [7] chain slow path
-__device__ unsigned long long g_lbstat[8];
-#define LB_COUNT(i, v) do { if (lane_id() == 0) atomicAdd(&g_lbstat[i], (unsigned long long)(v)); } while (0)
-#else
-#define LB_COUNT(i, v) do {} while (0)
-#endif
 
 __device__ __forceinline__ int cache_to_hist(int c) {
     switch (c) {
@@ -68,18 +49,19 @@ __device__ __forceinline__ int cache_to_hist(int c) {
     }
 }
 
-struct SegLds {
-    int64_t F[SEG];     // footprint after each event, relative to the segment start
-    int64_t P[SEG];     // Python footprint after each event, relative
-    uint32_t ptr[SEG];  // line ids are re-read from the records at samples
-};
-
 struct HistCache {
     unsigned long long key[NSLOT];  // (trace << 32) | line, or ~0 when empty
     unsigned long long cnt[NSLOT][NCNT];
 };
 
 constexpr unsigned long long EMPTY_KEY = ~0ull;
+
+__device__ __forceinline__ void hist_init(HistCache& hc) {
+    for (int i = threadIdx.x; i < NSLOT; i += blockDim.x) {
+        hc.key[i] = EMPTY_KEY;
+        for (int c = 0; c < NCNT; ++c) hc.cnt[i][c] = 0;
+    }
+}
 
 // Add up to four counters of (trace t, line) through the workgroup's LDS
 // cache; a slot held by another line sends the update to global atomics.
@@ -105,12 +87,374 @@ __device__ __forceinline__ void hist_add(HistCache& hc, const Desc& D, uint32_t 
     }
 }
 
+// Move the cache to the per-line histograms (whole workgroup, after a barrier).
+__device__ __forceinline__ void hist_flush(HistCache& hc, const Desc* desc) {
+    for (int i = threadIdx.x; i < NSLOT; i += blockDim.x) {
+        const unsigned long long key = hc.key[i];
+        if (key == EMPTY_KEY) continue;
+        const Desc& D = desc[(uint32_t)(key >> 32)];
+        const uint32_t line = (uint32_t)key;
+        for (int c = 0; c < NCNT; ++c) {
+            const unsigned long long v = hc.cnt[i][c];
+            if (v) atomicAdd((unsigned long long*)&D.hist[(size_t)cache_to_hist(c) * D.L + line], v);
+        }
+    }
+}
+
+// last trace whose first segment index is <= x
+__device__ __forceinline__ int find_trace_seg(const Desc* desc, int lo, int ntraces, uint64_t x) {
+    int hi = ntraces - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (desc[mid].seg_begin <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// last trace whose first tile index is <= x
+__device__ __forceinline__ int find_trace_tile(const Desc* desc, int ntraces, uint64_t x) {
+    int lo = 0, hi = ntraces - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (desc[mid].tile_begin <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------ event records
+
+// One decoded record (24 bytes: delta i64, ptr u32, line u32, flags u8).
+// Flags: bit 0 native (else Python), bits 1-2 kind (0 memory, 1 copy,
+// 2 timer).  Memory deltas satisfy |delta| < 2^52, copies 0 <= delta < 2^52,
+// timer delays 0 <= delta < 2^32, and line < L; anything else is malformed
+// and contributes nothing.
+struct Ev {
+    int64_t dm;    // footprint delta
+    int64_t dp;    // Python footprint delta
+    int64_t dc;    // copy bytes
+    uint32_t ptr;
+    bool bad;
+    bool aux;      // well-formed copy or timer event
+};
+
+__device__ __forceinline__ Ev decode(uint64_t r0, uint64_t r1, uint64_t r2, bool valid, uint32_t L) {
+    Ev e;
+    const int64_t delta = (int64_t)r0;
+    e.ptr = (uint32_t)r1;
+    const uint32_t line = (uint32_t)(r1 >> 32);
+    const uint32_t flags = (uint32_t)(r2 & 0xFF);
+    const uint32_t kind = (flags >> 1) & 3;
+    const bool py = (flags & 1) == 0;
+    const uint64_t shifted = (uint64_t)delta + (kind == 0 ? (uint64_t)(MAX_ABS_DELTA - 1) : 0ull);
+    const uint64_t span =
+        kind == 0 ? (uint64_t)(2 * MAX_ABS_DELTA - 1) : (kind == 1 ? (uint64_t)MAX_ABS_DELTA : (1ull << 32));
+    e.bad = valid && (kind == 3 || line >= L || shifted >= span);
+    const bool ok = valid && !e.bad;
+    e.dm = (ok && kind == 0) ? delta : 0;
+    e.dp = py ? e.dm : 0;
+    e.dc = (ok && kind == 1) ? delta : 0;
+    e.aux = ok && kind != 0;
+    return e;
+}
+
+struct SegScan {
+    int64_t sumF, sumP, sumC;
+    int64_t mxF, mnF, mxP, mnP;  // extremes of the relative prefixes (EXT only)
+    uint64_t forced_v, free_v;   // lane w < NW: event masks of window w
+    bool any_aux;
+    uint32_t err;
+};
+
+// Load one segment's records (all loads issued before any use), decode them
+// and scan the footprint and Python footprint; the relative prefixes (after
+// each event, segment start = 0) go to F (and P, ptr ids to PT, if asked).
+template <bool STORE_P, bool STORE_PTR, bool EXT>
+__device__ __forceinline__ void load_segment(const Desc& D, int64_t a, int nv, int64_t* F, int64_t* P, uint32_t* PT,
+                                             SegScan& o) {
+    const int l = lane_id();
+    uint64_t q0[NW], q1[NW], q2[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const int k = w * 64 + l;
+        if (k < nv) {
+            const uint64_t* p = (const uint64_t*)(D.ev + (size_t)(a + k) * 24);
+            q0[w] = __builtin_nontemporal_load(p);
+            q1[w] = __builtin_nontemporal_load(p + 1);
+            q2[w] = __builtin_nontemporal_load(p + 2);
+        } else {
+            q0[w] = 0;
+            q1[w] = 0;
+            q2[w] = 0;
+        }
+    }
+    int64_t cF = 0, cP = 0, accC = 0;
+    int64_t mxF = INT64_MIN, mnF = INT64_MAX, mxP = INT64_MIN, mnP = INT64_MAX;
+    uint64_t forced_v = 0, free_v = 0;
+    bool any_aux = false;
+    uint32_t err = 0;
+    // |delta| >= 2T-1 samples whatever the reference was
+    const int64_t two_t = 2 * D.T - 1;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const int k = w * 64 + l;
+        const bool valid = k < nv;
+        const Ev e = decode(q0[w], q1[w], q2[w], valid, D.L);
+        if (ballot(e.bad)) err |= 1u;
+        const uint64_t fm = ballot(e.dm >= two_t || e.dm <= -two_t);
+        const uint64_t frm = ballot(e.dm < 0);
+        if (l == w) {
+            forced_v = fm;
+            free_v = frm;
+        }
+        const int64_t sF = wave_incl_sum(e.dm) + cF;
+        const int64_t sP = wave_incl_sum(e.dp) + cP;
+        cF = readlane64(sF, 63);
+        cP = readlane64(sP, 63);
+        F[k] = sF;
+        if (STORE_P) P[k] = sP;
+        if (STORE_PTR) PT[k] = e.ptr;
+        accC += e.dc;
+        if (ballot(e.aux)) any_aux = true;
+        if (EXT && valid) {
+            mxF = sF > mxF ? sF : mxF;
+            mnF = sF < mnF ? sF : mnF;
+            mxP = sP > mxP ? sP : mxP;
+            mnP = sP < mnP ? sP : mnP;
+        }
+    }
+    o.sumF = cF;
+    o.sumP = cP;
+    o.sumC = wave_sum(accC);
+    if (EXT) {
+        o.mxF = wave_max(mxF);
+        o.mnF = wave_min(mnF);
+        o.mxP = wave_max(mxP);
+        o.mnP = wave_min(mnP);
+    }
+    o.forced_v = forced_v;
+    o.free_v = free_v;
+    o.any_aux = any_aux;
+    o.err = err;
+}
+
+__device__ __forceinline__ int seg_events(const Desc& D, int64_t j) {
+    const uint64_t a = (uint64_t)j * SEG;
+    return (int)((D.n - a) < (uint64_t)SEG ? (D.n - a) : (uint64_t)SEG);
+}
+
+// ------------------------------------------------------------------- chains
+
+// One chain followed through a segment: its reference, sample masks (lane w
+// holds window w's mask), the largest growth-sample footprint (earliest on
+// ties), the largest sampled footprint and the last sample's index.
+struct ChainRun {
+    int64_t ref;
+    uint64_t mvec;
+    int64_t gbest;
+    int gnode;
+    int64_t smax;
+    int lastS;
+};
+
+// Follow cr from window w0 (after lane st0) to the segment end, sampling
+// wherever the footprint is at least T away from the reference (section 3.2).
+template <bool FULL>
+__device__ void run_chain(const int64_t* F, int64_t T, ChainRun& cr, int w0, int st0) {
+    const int l = lane_id();
+    for (int w = w0; w < NW; ++w) {
+        const int64_t f = F[w * 64 + l];
+        int stl = w == w0 ? st0 : -1;
+        uint64_t m = 0;
+        for (;;) {
+            const int64_t d = f - cr.ref;
+            const uint64_t ex = ballot(l > stl && (d >= T || d <= -T));
+            if (!ex) break;
+            const int jj = ctz64(ex);
+            const int64_t fj = readlane64(f, jj);
+            if (FULL) {
+                if (fj > cr.ref && (cr.gnode < 0 || fj > cr.gbest)) {
+                    cr.gbest = fj;
+                    cr.gnode = w * 64 + jj;
+                }
+                if (fj > cr.smax) cr.smax = fj;
+                m |= 1ull << jj;
+                cr.lastS = w * 64 + jj;
+            }
+            cr.ref = fj;
+            stl = jj;
+        }
+        if (FULL && l == w) cr.mvec |= m;
+    }
+}
+
+// Follow one chain through the window held in f (one node per lane), starting
+// after lane st.  U holds the lanes where an earlier chain of this window
+// sampled; reaching one of them means the chains coincide (returns false).
+__device__ __forceinline__ bool follow(int64_t f, int64_t T, int64_t& ref, int st, uint64_t& U) {
+    const int l = lane_id();
+    for (;;) {
+        const int64_t d = f - ref;
+        const uint64_t m = ballot(l > st && (d >= T || d <= -T));
+        if (!m) return true;
+        const int j = ctz64(m);
+        if ((U >> j) & 1) return false;
+        U |= 1ull << j;
+        ref = readlane64(f, j);
+        st = j;
+    }
+}
+
+struct SegMap {
+    int64_t lo, hi, kf;
+    int kind;
+};
+
+// All-entry analysis of one segment (F: relative prefixes in LDS).
+__device__ SegMap analyse_segment(const int64_t* F, int64_t T, uint64_t forced_v, int64_t sumF) {
+    const int l = lane_id();
+    SegMap m;
+    // An event with |delta| >= 2T-1 samples for every entry state, so the
+    // chain from the first such event onwards is the same for all entries.
+    const uint64_t wf = ballot(l < NW && forced_v != 0);
+    if (wf) {
+        const int fwin = ctz64(wf);
+        const int flane = ctz64(readlaneu64(forced_v, fwin));
+        ChainRun r{readlane64(F[fwin * 64 + l], flane), 0, 0, -1, INT64_MIN, -1};
+        run_chain<false>(F, T, r, fwin, flane);
+        m.lo = 1;
+        m.hi = 0;
+        m.kf = r.ref - sumF;
+        m.kind = MAP_TOTAL;
+        return m;
+    }
+    // Entries in [Lo, Hi] have not sampled yet; chain c (lane c < nch) holds
+    // the reference of one distinct chain of the entries that have.
+    int64_t Lo = -T + 1, Hi = T - 1;
+    int nch = 0;
+    bool ovf = false;
+    int64_t chref = 0;
+    for (int w = 0; w < NW; ++w) {
+        const int64_t f = F[w * 64 + l];
+        if (ovf) {
+            if (Lo <= Hi) {
+                const int64_t wmx = wave_max(f), wmn = wave_min(f);
+                Lo = (wmx - T + 1) > Lo ? (wmx - T + 1) : Lo;
+                Hi = (wmn + T - 1) < Hi ? (wmn + T - 1) : Hi;
+            }
+            continue;
+        }
+        uint64_t U = 0;
+        int nal = 0;
+        for (int c = 0; c < nch; ++c) {
+            int64_t ref = readlane64(chref, c);
+            if (follow(f, T, ref, -1, U)) {
+                if (l == nal) chref = ref;
+                ++nal;
+            }
+        }
+        if (Lo <= Hi) {
+            const int64_t im = wave_incl_max(f), in = wave_incl_min(f);
+            const int64_t em = wave_shr1(im, INT64_MIN), en = wave_shr1(in, INT64_MAX);
+            // entries still unsampled just before node l
+            int64_t lob = Lo, hib = Hi;
+            if (l > 0) {
+                lob = (em - T + 1) > Lo ? (em - T + 1) : Lo;
+                hib = (en + T - 1) < Hi ? (en + T - 1) : Hi;
+            }
+            const bool ne = lob <= hib;
+            const bool up = ne && (f - T >= lob);
+            const bool dn = ne && (f + T <= hib);
+            // node c is the first sample of some entries: a chain starts there
+            uint64_t cm = ballot(up || dn);
+            while (cm) {
+                const int c = ctz64(cm);
+                cm &= cm - 1;
+                if ((U >> c) & 1) continue;
+                U |= 1ull << c;
+                int64_t ref = readlane64(f, c);
+                if (follow(f, T, ref, c, U)) {
+                    if (nal >= CHAIN_CAP) {
+                        ovf = true;
+                        break;
+                    }
+                    if (l == nal) chref = ref;
+                    ++nal;
+                }
+            }
+            const int64_t wmx = readlane64(im, 63), wmn = readlane64(in, 63);
+            Lo = (wmx - T + 1) > Lo ? (wmx - T + 1) : Lo;
+            Hi = (wmn + T - 1) < Hi ? (wmn + T - 1) : Hi;
+        }
+        nch = ovf ? 0 : nal;
+    }
+    if (Lo > T) Lo = T;
+    if (Hi < -T) Hi = -T;
+    const bool has_const = !ovf && nch == 1;
+    m.lo = Lo;
+    m.hi = Hi;
+    m.kf = has_const ? readlane64(chref, 0) - sumF : 0;
+    m.kind = has_const ? (Lo > Hi ? MAP_TOTAL : MAP_CONST) : MAP_SIM;
+    return m;
+}
+
+// Exit offset of segment j from entry offset x, following the records
+// (wave-uniform x; used for segments whose chains did not all coincide).
+__device__ int64_t simulate_exit(const Desc& D, int64_t j, int64_t x) {
+    const int l = lane_id();
+    const int64_t a = j * SEG;
+    const int nv = seg_events(D, j);
+    int64_t ref = x, cF = 0;
+    for (int w = 0; w < NW; ++w) {
+        const int k = w * 64 + l;
+        uint64_t r0 = 0, r1 = 0, r2 = 0;
+        if (k < nv) {
+            const uint64_t* p = (const uint64_t*)(D.ev + (size_t)(a + k) * 24);
+            r0 = p[0];
+            r1 = p[1];
+            r2 = p[2];
+        }
+        const Ev e = decode(r0, r1, r2, k < nv, D.L);
+        const int64_t f = wave_incl_sum(e.dm) + cF;
+        cF = readlane64(f, 63);
+        int st = -1;
+        for (;;) {
+            const int64_t d = f - ref;
+            const uint64_t m = ballot(l > st && (d >= D.T || d <= -D.T));
+            if (!m) break;
+            st = ctz64(m);
+            ref = readlane64(f, st);
+        }
+    }
+    return ref - cF;
+}
+
+// Exit offset of segment j (map lo, hi, af, kf, kind) from entry offset x.
+__device__ __forceinline__ int64_t seg_exit(const Desc& D, int64_t j, int64_t x, int64_t lo, int64_t hi, int64_t af,
+                                            int64_t kf, int kind) {
+    if (x >= lo && x <= hi) return x - af;
+    if (kind != MAP_SIM) return kf;
+    return simulate_exit(D, j, x);
+}
+
+// Apply the maps of lanes [from, to) in order from the wave-uniform entry x;
+// lane i's exit goes to ex.  Returns the exit after lane to-1.
+__device__ int64_t resolve_lanes(const Desc& D, int64_t j0, int from, int to, int64_t x, int64_t lo, int64_t hi,
+                                 int64_t af, int64_t kf, int kind, int64_t& ex) {
+    const int l = lane_id();
+    for (int i = from; i < to; ++i) {
+        x = seg_exit(D, j0 + i, x, readlane64(lo, i), readlane64(hi, i), readlane64(af, i), readlane64(kf, i),
+                     readlane32(kind, i));
+        if (l == i) ex = x;
+    }
+    return x;
+}
+
 // ---------------------------------------------------------------- look-backs
 
-// Every wait on another segment's status polls with a budget and an
-// exponential back-off.  Running out of budget (only possible through an
-// internal fault) raises the launch-wide abort word, after which every wait
-// returns at once, so all waves always exit.
+// Every wait on another tile's status polls with a budget and an exponential
+// back-off.  Running out of budget (only possible through an internal fault)
+// raises the launch-wide abort word, after which every wait returns at once,
+// so all waves always exit.
 constexpr uint32_t SPIN_BUDGET = 1u << 24;
 
 struct Spin {
@@ -129,21 +473,28 @@ __device__ __forceinline__ bool spin_abort(unsigned long long* ctl, Spin& sp) {
     return false;
 }
 
-// ------------------------------------------------- decoupled look-backs
-//
-// Segment g looks at its predecessors g-1-l (lane l, nearest first).  It
-// needs the nearest one that has published an inclusive value and the
-// aggregates of all segments after it.  Having them, it can also compute the
-// inclusive values of those intermediate segments, and it publishes them
-// ("helping"): the resolved frontier then advances as fast as aggregates
-// appear instead of one look-back at a time.  Identical values may be
-// written by several waves; a reader sees either copy.
+// Wait until a status word is published (wave-uniform address).
+__device__ bool wait_word(const uint64_t* p, int64_t& v, unsigned long long* ctl) {
+    Spin sp;
+    for (;;) {
+        const uint64_t w = ld_status(p);
+        if (wstate(w)) {
+            v = unpack(w);
+            return true;
+        }
+        if (spin_abort(ctl, sp)) return false;
+    }
+}
 
-// Exclusive (F, P, C) prefix of segment g.  Loads are kept small: the
-// predecessor's inclusive first (three lanes), then one state word per lane to
-// find the nearest published inclusive, then the aggregates of the segments
-// after it; a wait re-reads only the lanes still missing.
-__device__ bool scan_sums(const StatusView& sv, int64_t g, int64_t& oF, int64_t& oP, int64_t& oC, unsigned long long* ctl) {
+// Decoupled look-backs over tiles.  Tile g looks at its predecessors g-1-l
+// (lane l, nearest first): it needs the nearest one that has published an
+// inclusive value and the aggregates of all tiles after it.  Having them, it
+// also publishes the inclusive values of those intermediate tiles
+// ("helping").  Identical values may be written by several waves.
+
+// Exclusive (F, P, C) prefix of tile g.
+__device__ bool scan_sums(const StatusView& sv, int64_t g, int64_t& oF, int64_t& oP, int64_t& oC,
+                          unsigned long long* ctl) {
     const int l = lane_id();
     {
         uint64_t v = 0;
@@ -168,7 +519,7 @@ __device__ bool scan_sums(const StatusView& sv, int64_t g, int64_t& oF, int64_t&
         const int lim = im ? ctz64(im) : __popcll(ballot(in));
         const bool need = in && l < lim;
         const bool at = im && l == lim;
-        uint64_t x0 = 0, x1 = 0, x2 = 0;   // aggregate (need) or inclusive (at) words
+        uint64_t x0 = 0, x1 = 0, x2 = 0;  // aggregate (need) or inclusive (at) words
         bool have = !(need || at);
         for (;;) {
             if (!have) {
@@ -184,15 +535,12 @@ __device__ bool scan_sums(const StatusView& sv, int64_t g, int64_t& oF, int64_t&
                 have = wstate(x0) && wstate(x1) && wstate(x2);
             }
             if (!ballot(!have)) break;
-            LB_COUNT(1, 1);
             if (spin_abort(ctl, sp)) return false;
         }
-        LB_COUNT(0, 1);
-        LB_COUNT(2, lim);
         const int64_t vF = (need || at) ? unpack(x0) : 0;
         const int64_t vP = (need || at) ? unpack(x1) : 0;
         const int64_t vC = (need || at) ? unpack(x2) : 0;
-        // suffix sums toward older segments: S_l = sum over lanes >= l
+        // suffix sums toward older tiles: S_l = sum over lanes >= l
         const int64_t xF = wave_incl_sum(vF), xP = wave_incl_sum(vP), xC = wave_incl_sum(vC);
         const int64_t tF = readlane64(xF, 63), tP = readlane64(xP, 63), tC = readlane64(xC, 63);
         if (first && im && need) {
@@ -229,6 +577,19 @@ __device__ __forceinline__ Best with_baseline(Best b) {
     return b;
 }
 
+// a, then b
+__device__ __forceinline__ Best combine(const Best& a, const Best& b) {
+    Best r = a;
+    r.cnt = a.cnt + b.cnt;
+    if (b.has && (!a.has || b.val > a.val)) {
+        r.has = true;
+        r.val = b.val;
+        r.idx = b.idx;
+        r.ptr = b.ptr;
+    }
+    return r;
+}
+
 // value of lane l + d (lanes past 63 get `fill`)
 __device__ __forceinline__ int64_t lane_down(int64_t x, int d, int64_t fill) {
     const int l = lane_id();
@@ -236,7 +597,7 @@ __device__ __forceinline__ int64_t lane_down(int64_t x, int d, int64_t fill) {
     return l + d < 64 ? y : fill;
 }
 
-// Exclusive Best prefix of segment g (baseline applied), loading as scan_sums.
+// Exclusive Best prefix of tile g (baseline applied), loading as scan_sums.
 __device__ bool scan_best(const StatusView& sv, int64_t g, Best& out, unsigned long long* ctl) {
     const int l = lane_id();
     {
@@ -253,7 +614,7 @@ __device__ bool scan_best(const StatusView& sv, int64_t g, Best& out, unsigned l
             return true;
         }
     }
-    Best acc{0, false, 0, 0, 0};  // later segments combined so far
+    Best acc{0, false, 0, 0, 0};  // later tiles combined so far
     int64_t base = g - 1;
     bool first = true;
     Spin sp;
@@ -284,11 +645,8 @@ __device__ bool scan_best(const StatusView& sv, int64_t g, Best& out, unsigned l
                 have = wstate(c) && wstate(gm) && wstate(gr) && wstate(gp);
             }
             if (!ballot(!have)) break;
-            LB_COUNT(4, 1);
             if (spin_abort(ctl, sp)) return false;
         }
-        LB_COUNT(3, 1);
-        LB_COUNT(5, lim);
         const bool use = need || at;
         const int64_t cnt = use ? unpack(c) : 0;
         const bool has = use && wstate(gm) == 2;
@@ -322,15 +680,7 @@ __device__ bool scan_best(const StatusView& sv, int64_t g, Best& out, unsigned l
         win.val = M0;
         win.idx = (uint32_t)readlane32((int)sidx, 0);
         win.ptr = (uint32_t)readlane32((int)sptr, 0);
-        Best r = win;
-        r.cnt = win.cnt + acc.cnt;
-        if (acc.has && (!win.has || acc.val > win.val)) {
-            r.has = true;
-            r.val = acc.val;
-            r.idx = acc.idx;
-            r.ptr = acc.ptr;
-        }
-        acc = r;
+        acc = combine(win, acc);
         if (im) break;
         base -= 64;
         first = false;
@@ -339,7 +689,7 @@ __device__ bool scan_best(const StatusView& sv, int64_t g, Best& out, unsigned l
     return true;
 }
 
-// Absolute Python footprint at the last sample before segment g (0 if none).
+// Python footprint at the last sample before tile g (0 if none).
 __device__ bool scan_last_sample(const StatusView& sv, int64_t g, int64_t& oP, unsigned long long* ctl) {
     const int l = lane_id();
     int64_t base = g - 1;
@@ -348,18 +698,17 @@ __device__ bool scan_last_sample(const StatusView& sv, int64_t g, int64_t& oP, u
     while (base >= 0) {
         const int64_t jj = base - l;
         const bool in = jj >= 0;
-        uint64_t li = 0, la = 0;
         const int64_t js = in ? jj : 0;
+        uint64_t li = 0, la = 0;
         if (in) {
             li = ld_status(sv.at(W_LSI, js));
             la = ld_status(sv.at(W_LSA, js));
         }
-        // a lane resolves the search if its segment has a sample or a known exit value
+        // a lane resolves the search if its tile has a sample or a known exit value
         const bool hit = in && (wstate(la) == 2 || wstate(li) != 0);
         const uint64_t hm = ballot(hit);
         const int lim = hm ? ctz64(hm) : __popcll(ballot(in));
         if (ballot(in && l < lim && wstate(la) == 0)) {
-            LB_COUNT(6, 1);
             if (spin_abort(ctl, sp)) return false;
             continue;
         }
@@ -377,406 +726,250 @@ __device__ bool scan_last_sample(const StatusView& sv, int64_t g, int64_t& oP, u
     return true;
 }
 
-// Entry reference offset of segment g (relative to its first event).
-__device__ bool lookback_chain(const const StatusView& sv, int64_t g, int64_t& eF, unsigned long long* ctl) {
-    const int l = lane_id();
-    Spin sp;
-    int i0;
-    uint64_t xF;
-    // fast path: the predecessor's exit (published early when its map is total)
-    for (int tries = 0; tries < 3; ++tries) {
-        const uint64_t a = ld_status(sv.at(W_XF, g - 1));
-        if (wstate(a)) {
-            eF = unpack(a);
-            return true;
-        }
-        if (spin_abort(ctl, sp)) return false;
-    }
-    LB_COUNT(7, 1);
-    // nearest predecessor (within 64) that has published its exit
-    for (;;) {
-        const int64_t jj = g - 1 - l;
-        const bool in = jj >= 0;
-        xF = in ? ld_status(sv.at(W_XF, jj)) : 0;
-        const uint64_t xm = ballot(in && wstate(xF));
-        if (xm) {
-            i0 = ctz64(xm);
-            break;
-        }
-        if (spin_abort(ctl, sp)) return false;
-    }
-    int64_t F = unpack(readlaneu64(xF, i0));
-    // apply the maps of the segments after it, oldest first
-    for (int i = i0 - 1; i >= 0; --i) {
-        const int64_t js = g - 1 - i;
-        Spin sp2;
-        for (;;) {
-            const uint64_t x0 = ld_status(sv.at(W_XF, js));
-            if (wstate(x0)) {
-                F = unpack(x0);
-                break;
-            }
-            const uint64_t lo = ld_status(sv.at(W_MLO, js)), hi = ld_status(sv.at(W_MHI, js)), cf = ld_status(sv.at(W_MCF, js));
-            const uint64_t sf = ld_status(sv.at(W_AF, js));
-            if (wstate(lo) && wstate(hi) && wstate(cf) && wstate(sf)) {
-                if (F >= unpack(lo) && F <= unpack(hi)) {
-                    F -= unpack(sf);
-                    break;
-                }
-                if (wstate(cf) == 2) {
-                    F = unpack(cf);
-                    break;
-                }
-            }
-            if (spin_abort(ctl, sp2)) return false;
-        }
-    }
-    eF = F;
-    return true;
-}
+// ------------------------------------------------------------ summary pass
 
-// -------------------------------------------------------- all-entry analysis
-
-// Follow one chain through the window held in f (one node per lane), starting
-// after lane st.  U holds the lanes where an earlier chain of this window
-// sampled; reaching one of them means the chains coincide (returns false).
-__device__ __forceinline__ bool follow(int64_t f, int64_t T, int64_t& ref, int& last, int st, uint64_t& U, int w) {
-    const int l = lane_id();
-    for (;;) {
-        const int64_t d = f - ref;
-        const uint64_t m = ballot(l > st && (d >= T || d <= -T));
-        if (!m) return true;
-        const int j = ctz64(m);
-        if ((U >> j) & 1) return false;
-        U |= 1ull << j;
-        ref = readlane64(f, j);
-        last = w * 64 + j;
-        st = j;
-    }
-}
-
-// One chain followed through a segment: its reference, sample masks (lane w
-// holds window w's mask), the largest growth-sample footprint (earliest on
-// ties), the largest sampled footprint and the last sample's index.
-struct ChainRun {
-    int64_t ref;
-    uint64_t mvec;
-    int64_t gbest;
-    int gnode;
-    int64_t smax;
-    int lastS;
-};
-
-// Follow cr from window w0 (after lane st0) through window wend (below lane
-// stend), sampling wherever the footprint is at least T away from the
-// reference (section 3.2).
-__device__ void run_chain(const int64_t* F, int64_t T, ChainRun& cr, int w0, int st0, int wend, int stend) {
-    const int l = lane_id();
-    for (int w = w0; w <= wend; ++w) {
-        const int64_t f = F[w * 64 + l];
-        int stl = w == w0 ? st0 : -1;
-        const int lim = w == wend ? stend : 64;
-        uint64_t m = 0;
-        for (;;) {
-            const int64_t d = f - cr.ref;
-            const uint64_t ex = ballot(l > stl && l < lim && (d >= T || d <= -T));
-            if (!ex) break;
-            const int jj = ctz64(ex);
-            const int64_t fj = readlane64(f, jj);
-            if (fj > cr.ref && (cr.gnode < 0 || fj > cr.gbest)) {
-                cr.gbest = fj;
-                cr.gnode = w * 64 + jj;
-            }
-            if (fj > cr.smax) cr.smax = fj;
-            cr.ref = fj;
-            m |= 1ull << jj;
-            stl = jj;
-            cr.lastS = w * 64 + jj;
-        }
-        if (l == w) cr.mvec |= m;
-    }
-}
-
-// ------------------------------------------------------------------ main kernel
-
-// last trace whose first segment (or block, line) index is <= x
-__device__ __forceinline__ int find_trace_seg(const Desc* desc, int ntraces, uint64_t x) {
-    int lo = 0, hi = ntraces - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (desc[mid].seg_begin <= x) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total,
-                                                 unsigned long long* ctl) {
-    __shared__ SegLds lds_seg[WAVES];
-    __shared__ HistCache hc;
-
-    for (int i = threadIdx.x; i < NSLOT; i += BLOCK) {
-        hc.key[i] = EMPTY_KEY;
-        for (int c = 0; c < NCNT; ++c) hc.cnt[i][c] = 0;
-    }
-    __syncthreads();
-
+// One wave per segment: sums, extremes of the relative prefixes and the
+// segment's chain map.
+__global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ desc, int ntraces,
+                                                     uint64_t nseg_total) {
+    __shared__ int64_t lF[WAVES][SEG];
     const int wv = threadIdx.x >> 6;
     const int l = lane_id();
-    SegLds& S = lds_seg[wv];
+    const uint64_t g = (uint64_t)blockIdx.x * WAVES + wv;
+    if (g >= nseg_total) return;
+    const Desc& D = desc[find_trace_seg(desc, 0, ntraces, g)];
+    const int64_t j = (int64_t)(g - D.seg_begin);
+    const int64_t a = j * SEG;
+    const int nv = seg_events(D, j);
+    SegScan sc;
+    load_segment<false, false, true>(D, a, nv, lF[wv], nullptr, nullptr, sc);
+    const SegMap m = analyse_segment(lF[wv], D.T, sc.forced_v, sc.sumF);
+    if (l <= SP_KIND) {
+        int64_t v;
+        switch (l) {
+            case SP_AF: v = sc.sumF; break;
+            case SP_AP: v = sc.sumP; break;
+            case SP_AC: v = sc.sumC; break;
+            case SP_MXF: v = sc.mxF; break;
+            case SP_MNF: v = sc.mnF; break;
+            case SP_MXP: v = sc.mxP; break;
+            case SP_MNP: v = sc.mnP; break;
+            case SP_LO: v = m.lo; break;
+            case SP_HI: v = m.hi; break;
+            case SP_KF: v = m.kf; break;
+            default: v = m.kind; break;
+        }
+        D.seg[(int64_t)l * (int64_t)D.nseg + j] = v;
+    }
+    if (sc.err && l == 0) atomicOr(&D.scal->err, sc.err);
+}
 
-    int cur_t = -1;
-    int64_t peakF = 0, peakS = 0;
-    PH_DECL
+// ------------------------------------------------------------ resolve pass
 
-    for (;;) {
-        unsigned long long tk = 0;
-        if (l == 0) tk = atomicAdd(&ctl[0], 1ull);
-        tk = readlaneu64(tk, 0);
-        if (tk >= nseg_total) break;
-        // tickets only grow, so the owning trace only moves forward
-        int tt = cur_t < 0 ? find_trace_seg(desc, ntraces, tk) : cur_t;
-        while (tt + 1 < ntraces && desc[tt + 1].seg_begin <= tk) ++tt;
-        const uint32_t t = (uint32_t)tt;
+// One workgroup per tile of TILE segments (tiles taken in ticket order, so a
+// tile's predecessors are always running or done): exclusive prefix sums and
+// the chain's entry and exit offset of every segment.  Exits that do not
+// depend on the tile's entry (from the first segment with a total map on)
+// are published before the entry is awaited.
+__global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc, int ntraces, uint64_t ntile_total,
+                                                  unsigned long long* ctl) {
+    __shared__ unsigned long long s_tk;
+    __shared__ int64_t w_sum[3][TWAVES];
+    __shared__ int64_t w_exit[TWAVES];
+    __shared__ int w_ft[TWAVES];
+    __shared__ int64_t s_pre[3];
+    __shared__ int64_t s_entry;
+    __shared__ int64_t w_peak[TWAVES];
+    const int tid = threadIdx.x, wv = tid >> 6, l = lane_id();
+    if (tid == 0) s_tk = atomicAdd(&ctl[2], 1ull);
+    __syncthreads();
+    const uint64_t tk = s_tk;
+    if (tk >= ntile_total) return;
+    const Desc& D = desc[find_trace_tile(desc, ntraces, tk)];
+    const int64_t k = (int64_t)(tk - D.tile_begin);
+    const int64_t ns = (int64_t)D.nseg;
+    const int64_t j0 = k * TILE + wv * 64;  // segment of lane 0
+    const int64_t j = j0 + l;
+    const bool valid = j < ns;
+    const StatusView ts{D.tstat, (int64_t)D.ntile};
+    const int64_t* sp = D.seg + (valid ? j : 0);
+    int64_t af = 0, ap = 0, ac = 0, mxf = 0, mnf = 0, mxp = 0, mnp = 0, kf = 0;
+    int64_t lo = INT64_MIN, hi = INT64_MAX;  // past the trace end: the identity map
+    int kind = MAP_CONST;
+    if (valid) {
+        af = sp[SP_AF * ns];
+        ap = sp[SP_AP * ns];
+        ac = sp[SP_AC * ns];
+        mxf = sp[SP_MXF * ns];
+        mnf = sp[SP_MNF * ns];
+        mxp = sp[SP_MXP * ns];
+        mnp = sp[SP_MNP * ns];
+        lo = sp[SP_LO * ns];
+        hi = sp[SP_HI * ns];
+        kf = sp[SP_KF * ns];
+        kind = (int)sp[SP_KIND * ns];
+    }
+    // sums inside the wave
+    const int64_t iF = wave_incl_sum(af), iP = wave_incl_sum(ap), iC = wave_incl_sum(ac);
+    // exits that do not depend on the wave's entry: from the first total map on
+    const uint64_t tot = ballot(kind == MAP_TOTAL);
+    const int ft = tot ? ctz64(tot) : 64;
+    int64_t ex = kf;
+    if (ft < 63) {
+        uint64_t m = ~tot & (~0ull << (ft + 1));
+        int64_t x = 0;
+        int prev = -2;
+        while (m) {
+            const int i = ctz64(m);
+            m &= m - 1;
+            const int64_t xin = prev == i - 1 ? x : readlane64(kf, i - 1);
+            x = seg_exit(D, j0 + i, xin, readlane64(lo, i), readlane64(hi, i), readlane64(af, i), readlane64(kf, i),
+                         readlane32(kind, i));
+            if (l == i) ex = x;
+            prev = i;
+        }
+    }
+    if (l == 63) {
+        w_sum[0][wv] = iF;
+        w_sum[1][wv] = iP;
+        w_sum[2][wv] = iC;
+    }
+    if (l == 0) {
+        w_ft[wv] = ft;
+        w_exit[wv] = readlane64(ex, 63);
+    }
+    __syncthreads();
+    int64_t oF = 0, oP = 0, oC = 0, tF = 0, tP = 0, tC = 0;
+    int lc = -1;
+    for (int w = 0; w < TWAVES; ++w) {
+        if (w == wv) {
+            oF = tF;
+            oP = tP;
+            oC = tC;
+        }
+        tF += w_sum[0][w];
+        tP += w_sum[1][w];
+        tC += w_sum[2][w];
+        if (w_ft[w] < 64) lc = w;
+    }
+    // publish the tile's sums (inclusive right away for the first tile)
+    if (tid < 3) st_status(ts.at(W_AF + tid, k), pack(tid == 0 ? tF : (tid == 1 ? tP : tC), 1));
+    if (k == 0 && tid < 3) st_status(ts.at(W_IF + tid, k), pack(tid == 0 ? tF : (tid == 1 ? tP : tC), 1));
+    // waves after the last one with a total map continue from its exit
+    if (lc >= 0) {
+        for (int w = lc + 1; w < TWAVES; ++w) {
+            if (wv == w) {
+                const int64_t xo = resolve_lanes(D, j0, 0, 64, w_exit[w - 1], lo, hi, af, kf, kind, ex);
+                if (l == 0) w_exit[w] = xo;
+            }
+            __syncthreads();
+        }
+        if (tid == 0) st_status(ts.at(W_XF, k), pack(w_exit[TWAVES - 1], 1));
+    }
+    // the tile's prefix sums and entry offset
+    if (wv == 0) {
+        int64_t pF = 0, pP = 0, pC = 0, e = 0;
+        bool ok = true;
+        if (k > 0) {
+            ok = scan_sums(ts, k, pF, pP, pC, ctl);
+            if (l < 3) st_status(ts.at(W_IF + l, k), pack(l == 0 ? pF + tF : (l == 1 ? pP + tP : pC + tC), 1));
+            if (ok) ok = wait_word(ts.at(W_XF, k - 1), e, ctl);
+        }
+        if (l == 0) {
+            s_pre[0] = pF;
+            s_pre[1] = pP;
+            s_pre[2] = pC;
+            s_entry = e;
+            if (!ok) atomicOr(&D.scal->err, 8u);
+        }
+    }
+    __syncthreads();
+    // segments before each wave's first total map, in order
+    const int last = lc >= 0 ? lc : TWAVES - 1;
+    for (int w = 0; w <= last; ++w) {
+        if (w > 0 && w_ft[w - 1] == 64) __syncthreads();  // its exit is computed in the previous step
+        if (wv == w) {
+            const int64_t xin = w == 0 ? s_entry : w_exit[w - 1];
+            const int to = w_ft[w];
+            const int64_t xo = resolve_lanes(D, j0, 0, to, xin, lo, hi, af, kf, kind, ex);
+            if (to == 64 && l == 0) w_exit[w] = xo;
+        }
+    }
+    __syncthreads();
+    if (lc < 0 && tid == 0) st_status(ts.at(W_XF, k), pack(w_exit[TWAVES - 1], 1));
+    const int64_t ein = wv == 0 ? s_entry : w_exit[wv - 1];
+    const int64_t ef = wave_shr1(ex, ein);
+    const int64_t F0 = s_pre[0] + oF + iF - af;
+    const int64_t P0 = s_pre[1] + oP + iP - ap;
+    const int64_t C0 = s_pre[2] + oC + iC - ac;
+    uint32_t err = 0;
+    int64_t pk = 0;
+    if (valid) {
+        int64_t* o = D.seg + j;
+        o[SP_F0 * ns] = F0;
+        o[SP_P0 * ns] = P0;
+        o[SP_C0 * ns] = C0;
+        o[SP_EF * ns] = ef;
+        o[SP_XF * ns] = ex;
+        if (F0 + mxf >= MAX_ABS_F || F0 + mnf <= -MAX_ABS_F || P0 + mxp >= MAX_ABS_F || P0 + mnp <= -MAX_ABS_F ||
+            C0 + ac >= MAX_ABS_F || F0 >= MAX_ABS_F || F0 <= -MAX_ABS_F)
+            err = 2u;
+        pk = F0 + mxf;
+        if (j == ns - 1) D.scal->final_F = F0 + af;
+    }
+    if (ballot(err != 0) && l == 0) atomicOr(&D.scal->err, 2u);
+    pk = wave_max(pk);
+    if (l == 0) w_peak[wv] = pk;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t p = 0;
+        for (int w = 0; w < TWAVES; ++w) p = w_peak[w] > p ? w_peak[w] : p;
+        if (p > 0) atomicMax((long long*)&D.scal->peak_F, (long long)p);
+    }
+}
+
+// -------------------------------------------------------------- chain pass
+
+// One wave per segment (grid-stride): follow the chain from the segment's
+// entry offset; record its samples, count, best growth sample and the Python
+// footprint at its last sample.  Copy and timer events are counted here.
+__global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
+    __shared__ int64_t lF[WAVES][SEG];
+    __shared__ int64_t lP[WAVES][SEG];
+    __shared__ HistCache hc;
+    hist_init(hc);
+    __syncthreads();
+    const int wv = threadIdx.x >> 6;
+    const int l = lane_id();
+    int cur_t = 0;
+    int64_t peakS = 0;
+    bool have_t = false;
+    for (uint64_t g = (uint64_t)blockIdx.x * WAVES + wv; g < nseg_total; g += (uint64_t)gridDim.x * WAVES) {
+        const int t = find_trace_seg(desc, cur_t, ntraces, g);
+        if (t != cur_t && have_t && l == 0 && peakS > 0)
+            atomicMax((long long*)&desc[cur_t].scal->peak_S, (long long)peakS);
+        if (t != cur_t) peakS = 0;
+        cur_t = t;
+        have_t = true;
         const Desc& D = desc[t];
-        if ((int)t != cur_t) {
-            if (cur_t >= 0 && l == 0) {
-                atomicMax((long long*)&desc[cur_t].scal->peak_F, (long long)peakF);
-                atomicMax((long long*)&desc[cur_t].scal->peak_S, (long long)peakS);
-            }
-            cur_t = (int)t;
-            peakF = 0;
-            peakS = 0;
-        }
-        const int64_t g0 = (int64_t)D.seg_begin;
-        const int64_t g = (int64_t)tk;
-        const int64_t j = g - g0;
+        const int64_t j = (int64_t)(g - D.seg_begin);
+        const int64_t ns = (int64_t)D.nseg;
         const int64_t a = j * SEG;
-        const int nv = (int)((D.n - (uint64_t)a) < (uint64_t)SEG ? (D.n - (uint64_t)a) : (uint64_t)SEG);
+        const int nv = seg_events(D, j);
         const int64_t T = D.T;
-        const uint32_t L = D.L;
-        const StatusView sv{D.status, (int64_t)D.nseg};
+        SegScan sc;
+        load_segment<true, false, false>(D, a, nv, lF[wv], lP[wv], nullptr, sc);
+        int64_t pv = 0;
+        if (l < 5) pv = D.seg[(SP_F0 + l) * ns + j];
+        const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), C0 = readlane64(pv, 2);
+        const int64_t eF = readlane64(pv, 3), xF = readlane64(pv, 4);
         uint32_t err = 0;
-        PH_MARK(0);
-        PH_COUNT(12, 1);
-
-        // ---- P1: load, decode, validate, scan ----------------------------
-        uint64_t q0[NW], q1[NW], q2[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const int k = w * 64 + l;
-            if (k < nv) {
-                const uint64_t* p = (const uint64_t*)(D.ev + (size_t)(a + k) * 24);
-                q0[w] = __builtin_nontemporal_load(p);
-                q1[w] = __builtin_nontemporal_load(p + 1);
-                q2[w] = __builtin_nontemporal_load(p + 2);
-            } else {
-                q0[w] = 0;
-                q1[w] = 0;
-                q2[w] = 0;
-            }
-        }
-        int64_t cF = 0, cP = 0, cC = 0;
-        int64_t mxF = INT64_MIN, mnF = INT64_MAX, mxP = INT64_MIN, mnP = INT64_MAX;
-        uint64_t forced_v = 0, free_v = 0;   // lane w: mask of window w
-        int64_t accC = 0;                     // per-lane copy bytes
-        bool any_aux = false;                 // segment holds copy or timer events
-        const int64_t two_t = 2 * T - 1;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const int k = w * 64 + l;
-            const bool valid = k < nv;
-            const int64_t delta = (int64_t)q0[w];
-            const uint32_t ptr = (uint32_t)q1[w];
-            const uint32_t line = (uint32_t)(q1[w] >> 32);
-            const uint32_t flags = (uint32_t)(q2[w] & 0xFF);
-            const uint32_t kind = (flags >> 1) & 3;
-            const bool py = (flags & 1) == 0;
-            // memory: |delta| < 2^52; copy: 0 <= delta < 2^52; timer: 0 <= delta < 2^32
-            const uint64_t shifted = (uint64_t)delta + (kind == 0 ? (uint64_t)(MAX_ABS_DELTA - 1) : 0ull);
-            const uint64_t span = kind == 0 ? (uint64_t)(2 * MAX_ABS_DELTA - 1)
-                                            : (kind == 1 ? (uint64_t)MAX_ABS_DELTA : (1ull << 32));
-            const bool bad = valid && (kind == 3 || line >= L || shifted >= span);
-            const bool ok = valid && !bad;
-            const int64_t dm = (ok && kind == 0) ? delta : 0;
-            const int64_t dp = py ? dm : 0;
-            const int64_t dc = (ok && kind == 1) ? delta : 0;
-            if (ballot(bad)) err |= 1u;
-            const uint64_t fm = ballot(dm >= two_t || dm <= -two_t);
-            const uint64_t frm = ballot(dm < 0);
-            if (l == w) {
-                forced_v = fm;
-                free_v = frm;
-            }
-            const int64_t sF = wave_incl_sum(dm) + cF;
-            const int64_t sP = wave_incl_sum(dp) + cP;
-            cF = readlane64(sF, 63);
-            cP = readlane64(sP, 63);
-            accC += dc;
-            if (ballot(ok && kind != 0)) any_aux = true;
-            S.F[k] = sF;
-            S.P[k] = sP;
-            S.ptr[k] = ptr;
-            if (valid) {
-                mxF = sF > mxF ? sF : mxF;
-                mnF = sF < mnF ? sF : mnF;
-                mxP = sP > mxP ? sP : mxP;
-                mnP = sP < mnP ? sP : mnP;
-            }
-        }
-        cC = wave_sum(accC);
-        const int64_t sumF = cF, sumP = cP, sumC = cC;
-        if (l < 3) st_status(sv.at(W_AF + l, j), pack(l == 0 ? sumF : (l == 1 ? sumP : sumC), 1));
-        PH_MARK(1);
-
-        // ---- prefix sums from the preceding segments ------------------------
-        int64_t F0 = 0, P0 = 0, C0 = 0;
-        if (j > 0 && !scan_sums(sv, j, F0, P0, C0, ctl)) err |= 8u;
-        if (l < 3) st_status(sv.at(W_IF + l, j), pack(l == 0 ? F0 + sumF : (l == 1 ? P0 + sumP : C0 + sumC), 1));
-        PH_MARK(2);
-
-        // ---- P2: all-entry analysis: the segment's map on entry states --------
-        bool map_total = false;
-        int64_t map_kF = 0;
-        // An event with |delta| >= 2T-1 samples for every entry state, so the
-        // chain from the first such event onwards is the same for all entries.
-        int fwin = -1, flane = -1;
-        ChainRun p2run{0, 0, 0, -1, INT64_MIN, -1};
-        if (j > 0) {
-            const uint64_t wf = ballot(l < NW && forced_v != 0);
-            if (wf) {
-                fwin = ctz64(wf);
-                flane = ctz64(readlaneu64(forced_v, fwin));
-                p2run.ref = readlane64(S.F[fwin * 64 + l], flane);
-                run_chain(S.F, T, p2run, fwin, flane, NW - 1, 64);
-                map_total = true;
-                map_kF = p2run.ref - sumF;
-                if (l == 0) st_status(sv.at(W_MLO, j), pack(1, 1));
-                if (l == 1) st_status(sv.at(W_MHI, j), pack(0, 1));
-                if (l == 2) st_status(sv.at(W_MCF, j), pack(map_kF, 2));
-                if (l == 3) st_status(sv.at(W_XF, j), pack(map_kF, 1));
-                PH_COUNT(13, 1);
-                PH_COUNT(15, 1);
-            }
-        }
-        if (j > 0 && fwin < 0) {
-            int64_t Lo = -T + 1, Hi = T - 1;
-            int nch = 0;
-            bool ovf = false;
-            int64_t chref = 0;
-            int chlast = -1;
-            for (int w = 0; w < NW; ++w) {
-                const int64_t f = S.F[w * 64 + l];
-                uint64_t U = 0;
-                int first_st = -1;
-                if (ovf) {
-                    const uint64_t fm = readlaneu64(forced_v, w);
-                    if (!fm) {
-                        if (Lo <= Hi) {
-                            const int64_t wmx = wave_max(f), wmn = wave_min(f);
-                            Lo = (wmx - T + 1) > Lo ? (wmx - T + 1) : Lo;
-                            Hi = (wmn + T - 1) < Hi ? (wmn + T - 1) : Hi;
-                        }
-                        continue;
-                    }
-                    // every chain samples at a forced event: one chain remains
-                    const int fj = ctz64(fm);
-                    const int64_t r = readlane64(f, fj);
-                    if (l == 0) {
-                        chref = r;
-                        chlast = w * 64 + fj;
-                    }
-                    nch = 1;
-                    ovf = false;
-                    Lo = 1;
-                    Hi = 0;
-                    U = 1ull << fj;
-                    first_st = fj;
-                }
-                int nal = 0;
-                for (int c = 0; c < nch; ++c) {
-                    int64_t ref = readlane64(chref, c);
-                    int last = readlane32(chlast, c);
-                    if (follow(f, T, ref, last, c == 0 ? first_st : -1, U, w)) {
-                        if (l == nal) {
-                            chref = ref;
-                            chlast = last;
-                        }
-                        ++nal;
-                    }
-                }
-                if (Lo <= Hi) {
-                    const int64_t im = wave_incl_max(f), in = wave_incl_min(f);
-                    const int64_t em = wave_shr1(im, INT64_MIN), en = wave_shr1(in, INT64_MAX);
-                    int64_t lob = Lo, hib = Hi;
-                    if (l > 0) {
-                        lob = (em - T + 1) > Lo ? (em - T + 1) : Lo;
-                        hib = (en + T - 1) < Hi ? (en + T - 1) : Hi;
-                    }
-                    const bool ne = lob <= hib;
-                    const bool up = ne && (f - T >= lob);
-                    const bool dn = ne && (f + T <= hib);
-                    uint64_t cm = ballot(up || dn);
-                    while (cm) {
-                        const int c = ctz64(cm);
-                        cm &= cm - 1;
-                        if ((U >> c) & 1) continue;
-                        U |= 1ull << c;
-                        int64_t ref = readlane64(f, c);
-                        int last = w * 64 + c;
-                        if (follow(f, T, ref, last, c, U, w)) {
-                            if (nal >= CHAIN_CAP) {
-                                ovf = true;
-                                break;
-                            }
-                            if (l == nal) {
-                                chref = ref;
-                                chlast = last;
-                            }
-                            ++nal;
-                        }
-                    }
-                    const int64_t wmx = readlane64(im, 63), wmn = readlane64(in, 63);
-                    Lo = (wmx - T + 1) > Lo ? (wmx - T + 1) : Lo;
-                    Hi = (wmn + T - 1) < Hi ? (wmn + T - 1) : Hi;
-                }
-                nch = ovf ? 0 : nal;
-            }
-            if (Lo > T) Lo = T;
-            if (Hi < -T) Hi = -T;
-            bool has_const = !ovf && nch == 1;
-            int64_t kF = 0;
-            if (has_const) kF = readlane64(chref, 0) - sumF;
-            // publish the map
-            if (l == 0) st_status(sv.at(W_MLO, j), pack(Lo, 1));
-            if (l == 1) st_status(sv.at(W_MHI, j), pack(Hi, 1));
-            if (l == 2) st_status(sv.at(W_MCF, j), pack(kF, has_const ? 2 : 1));
-            PH_COUNT(13, has_const ? 1 : 0);
-            PH_COUNT(14, ovf ? 1 : 0);
-            if (has_const && Lo > Hi) {
-                PH_COUNT(15, 1);
-                map_total = true;
-                map_kF = kF;
-                if (l == 0) st_status(sv.at(W_XF, j), pack(kF, 1));
-            }
-        }
-
-        PH_MARK(4);
-
-
-        {
-            const int64_t hiF = wave_max(mxF), loF = wave_min(mnF);
-            const int64_t hiP = wave_max(mxP), loP = wave_min(mnP);
-            if (F0 + hiF >= MAX_ABS_F || F0 + loF <= -MAX_ABS_F || P0 + hiP >= MAX_ABS_F || P0 + loP <= -MAX_ABS_F ||
-                C0 + sumC >= MAX_ABS_F || F0 >= MAX_ABS_F || F0 <= -MAX_ABS_F)
-                err |= 2u;
-            if (nv > 0 && F0 + hiF > peakF) peakF = F0 + hiF;
-        }
 
         // Copy volume (section 3.5: one Tc sample per multiple of Tc crossed by
         // the cumulative copy bytes) and the timer split (section 2.1: Python
         // time += quantum, native time += delay).  Only segments that hold such
         // events re-read their records here.
-        if (any_aux) {
+        if (sc.any_aux) {
             int64_t cc = C0;
             for (int w = 0; w < NW; ++w) {
                 const int k = w * 64 + l;
@@ -790,221 +983,316 @@ __global__ __launch_bounds__(BLOCK) void k_sample(const Desc* __restrict__ desc,
                 const int64_t delta = (int64_t)r0;
                 const uint32_t line = (uint32_t)(r1 >> 32);
                 const uint32_t kind = ((uint32_t)r2 >> 1) & 3;
-                const bool lok = k < nv && line < L;
+                const bool lok = k < nv && line < D.L;
                 const bool cp = lok && kind == 1 && delta >= 0 && delta < MAX_ABS_DELTA;
                 const bool tm = lok && kind == 2 && delta >= 0 && delta <= (int64_t)0xFFFFFFFFll;
                 const int64_t dc = cp ? delta : 0;
-                const int64_t sc = wave_incl_sum(dc) + cc;
-                cc = readlane64(sc, 63);
+                const int64_t sc_ = wave_incl_sum(dc) + cc;
+                cc = readlane64(sc_, 63);
                 if (cp || tm) {
                     int c0 = C_PT, c1 = C_NT;
                     int64_t v0 = D.q, v1 = delta;
                     if (cp) {
-                        const uint64_t cout = (uint64_t)sc, cin = cout - (uint64_t)dc;
-                        uint64_t ns;
+                        const uint64_t cout = (uint64_t)sc_, cin = cout - (uint64_t)dc;
+                        uint64_t nsmp;
                         if (D.tc_shift >= 0)
-                            ns = (cout >> D.tc_shift) - (cin >> D.tc_shift);
+                            nsmp = (cout >> D.tc_shift) - (cin >> D.tc_shift);
                         else
-                            ns = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
+                            nsmp = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
                         c0 = C_CS;
                         c1 = C_CE;
-                        v0 = (int64_t)(ns * (uint64_t)D.Tc);
+                        v0 = (int64_t)(nsmp * (uint64_t)D.Tc);
                         v1 = dc;
                     }
-                    hist_add(hc, D, t, line, c0, v0, c1, v1, -1, 0, -1, 0);
+                    hist_add(hc, D, (uint32_t)t, line, c0, v0, c1, v1, -1, 0, -1, 0);
                 }
             }
         }
 
-        PH_MARK(3);
-
-        // ---- P4: entry state, then the segment's own samples -----------------
-        int64_t eF = 0;
-        if (j > 0 && !lookback_chain(sv, j, eF, ctl)) err |= 8u;
-        PH_MARK(5);
         ChainRun cr{eF, 0, 0, -1, INT64_MIN, -1};
-        if (fwin >= 0) {
-            // entry-dependent samples come only before the forced event
-            run_chain(S.F, T, cr, 0, -1, fwin, flane);
-            const int64_t fc = readlane64(S.F[fwin * 64 + l], flane);
-            if (fc > cr.ref && (cr.gnode < 0 || fc > cr.gbest)) {
-                cr.gbest = fc;
-                cr.gnode = fwin * 64 + flane;
+        run_chain<true>(lF[wv], T, cr, 0, -1);
+        if (cr.ref - sc.sumF != xF) err |= 4u;  // internal: the resolved exit disagrees with the chain
+        const int count = (int)wave_sum(l < NW ? (int64_t)__popcll(cr.mvec) : 0);
+        if (cr.smax != INT64_MIN && F0 + cr.smax > peakS) peakS = F0 + cr.smax;
+        const bool hg = cr.gnode >= 0 && cr.gnode < nv;  // nodes past the trace end never sample
+        uint32_t gptr = 0;
+        if (hg) gptr = ((const uint32_t*)(D.ev + (size_t)(a + cr.gnode) * 24))[2];
+        const int64_t lsv = cr.lastS >= 0 ? P0 + lP[wv][cr.lastS] : 0;
+        if (l < 6) {
+            int64_t v;
+            switch (l) {
+                case 0: v = count; break;
+                case 1: v = hg ? F0 + cr.gbest : 0; break;
+                case 2: v = hg ? a + cr.gnode : 0; break;
+                case 3: v = gptr; break;
+                case 4: v = lsv; break;
+                default: v = (hg ? 1 : 0) | (cr.lastS >= 0 ? 2 : 0); break;
             }
-            if (fc > cr.smax) cr.smax = fc;
-            if (l == fwin) cr.mvec |= 1ull << flane;
-            cr.mvec |= p2run.mvec;
-            if (p2run.gnode >= 0 && (cr.gnode < 0 || p2run.gbest > cr.gbest)) {
-                cr.gbest = p2run.gbest;
-                cr.gnode = p2run.gnode;
-            }
-            if (p2run.smax > cr.smax) cr.smax = p2run.smax;
-            cr.lastS = p2run.lastS >= 0 ? p2run.lastS : fwin * 64 + flane;
-            cr.ref = p2run.ref;
-        } else {
-            run_chain(S.F, T, cr, 0, -1, NW - 1, 64);
+            D.seg[(SP_BCNT + l) * ns + j] = v;
         }
-        const uint64_t smask_v = cr.mvec;
-        const int64_t ref = cr.ref;
-        const int lastS = cr.lastS;
-        const int64_t gbest = cr.gbest;
-        const int gnode = cr.gnode;
-        const int64_t smax = cr.smax;
-        const int64_t xF = ref - sumF;
-        if (!map_total) {
-            if (l == 0) st_status(sv.at(W_XF, j), pack(xF, 1));
-        } else if (xF != map_kF) {
-            err |= 4u;  // internal: the all-entry map disagrees with the simulated chain
-        }
-        const int count = (int)wave_sum(l < NW ? (int64_t)__popcll(smask_v) : 0);
-        if (smax != INT64_MIN && F0 + smax > peakS) peakS = F0 + smax;
-
-        PH_MARK(6);
-        // ---- P5: publish (count, best growth record, last-sample Python footprint) ----
-        {
-            const bool hg = gnode >= 0;
-            const int64_t gval = F0 + gbest;
-            const uint32_t gidx = hg ? (uint32_t)(a + gnode) : 0u;
-            const uint32_t gptr = hg ? S.ptr[gnode] : 0u;
-            if (l == 0) st_status(sv.at(W_BCNT, j), pack(count, 1));
-            if (l == 1) st_status(sv.at(W_BGM, j), pack(hg ? gval : 0, hg ? 2 : 1));
-            if (l == 2) st_status(sv.at(W_BGR, j), pack((int64_t)gidx, 1));
-            if (l == 3) st_status(sv.at(W_BGP, j), pack((int64_t)gptr, 1));
-            const int64_t lsP = lastS >= 0 ? P0 + S.P[lastS] : 0;
-            if (l == 4) st_status(sv.at(W_LSA, j), pack(lsP, lastS >= 0 ? 2 : 1));
-            Best pre{0, false, 0, 0, 0};
-            if (j > 0 && !scan_best(sv, j, pre, ctl)) err |= 8u;
-            {
-                Best inc = pre;
-                inc.cnt += count;
-                if (hg && gval > (pre.has ? pre.val : 0)) {
-                    inc.has = true;
-                    inc.val = gval;
-                    inc.idx = gidx;
-                    inc.ptr = gptr;
-                }
-                if (l == 0) st_status(sv.at(W_ICNT, j), pack(inc.cnt, 1));
-                if (l == 1) st_status(sv.at(W_IGM, j), pack(inc.has ? inc.val : 0, inc.has ? 2 : 1));
-                if (l == 2) st_status(sv.at(W_IGR, j), pack((int64_t)inc.idx, 1));
-                if (l == 3) st_status(sv.at(W_IGP, j), pack((int64_t)inc.ptr, 1));
-            }
-            int64_t eP = 0;
-            if (j > 0 && !scan_last_sample(sv, j, eP, ctl)) err |= 8u;
-            if (l == 0) st_status(sv.at(W_LSI, j), pack(lastS >= 0 ? lsP : eP, 1));
-            int64_t base = pre.cnt, hv = pre.val;
-            bool hh = pre.has;
-            uint32_t hidx = pre.idx, hptr = pre.ptr;
-            PH_MARK(7);
-            if (base < 0 || base > (int64_t)D.n) {  // only reachable after an internal fault
-                err |= 8u;
-                base = 0;
-            }
-            if ((uint64_t)j == D.nseg - 1 && l == 0) {
-                D.scal->K = (uint64_t)(base + count);
-                D.scal->final_F = F0 + sumF;
-            }
-
-            // ---- P7: emit samples, per-line attribution, leak tracking ----
-            int64_t refF = eF, refP = eP - P0;
-            int64_t cnt = 0;
-            bool cur_has = hh;
-            uint32_t cur_ptr = hptr, cur_idx = hidx;
-            int64_t hwm = hh ? hv : 0;
-            for (int w = 0; w < NW; ++w) {
-                const uint64_t m = readlaneu64(smask_v, w);
-                const uint64_t fm = readlaneu64(free_v, w);
-                if (m == 0 && (fm == 0 || !cur_has)) continue;
-                const int k = w * 64 + l;
-                const int64_t f = S.F[k];
-                const int64_t p = S.P[k];
-                const uint32_t pt = S.ptr[k];
-                const uint64_t below = m & lanemask_lt();
-                uint64_t tmask = 0;
-                if (m) {
-                    const int pl = below ? top64(below) : l;
-                    int64_t fprev = shfl64(f, pl), pprev = shfl64(p, pl);
-                    if (!below) {
-                        fprev = refF;
-                        pprev = refP;
-                    }
-                    const bool is_s = (m >> l) & 1;
-                    const int64_t dl = f - fprev;
-                    const int64_t pyb = p - pprev;
-                    const int64_t nat = dl - pyb;
-                    const int64_t Fabs = F0 + f;
-                    const int64_t rank = base + cnt + __popcll(below);
-                    if (is_s && rank < (int64_t)D.n) {
-                        const uint32_t ln = ((const uint32_t*)(D.ev + (size_t)(a + k) * 24))[3];
-                        Sample smp;
-                        smp.event_idx = (uint32_t)(a + k);
-                        smp.line = ln;
-                        smp.F = Fabs;
-                        smp.py = pyb;
-                        smp.nat = nat;
-                        D.samples[rank] = smp;
-                        if (ln < L) {
-                            const bool gr = dl > 0;
-                            hist_add(hc, D, t, ln, C_PY, pyb, C_NAT, nat, gr ? C_GN : C_SN, 1, gr ? C_GB : C_SB,
-                                     gr ? dl : -dl);
-                        }
-                    }
-                    uint64_t cand = ballot(is_s && dl > 0 && Fabs > hwm);
-                    while (cand) {
-                        const int c = ctz64(cand);
-                        cand &= cand - 1;
-                        const int64_t Fc = readlane64(Fabs, c);
-                        if (Fc > hwm) {
-                            hwm = Fc;
-                            tmask |= 1ull << c;
-                        }
-                    }
-                    if (((tmask >> l) & 1) && rank < (int64_t)D.n) {
-                        atomicOr((unsigned long long*)&D.tracked_bits[rank >> 6], 1ull << (rank & 63));
-                        D.sample_ptr[rank] = pt;
-                    }
-                    const int ls = top64(m);
-                    refF = readlane64(f, ls);
-                    refP = readlane64(p, ls);
-                }
-                if (fm && (cur_has || tmask)) {
-                    const uint64_t tb = tmask & lanemask_lt();
-                    const int al = tb ? top64(tb) : l;
-                    const uint32_t sp = (uint32_t)shfl32((int)pt, al);
-                    const uint32_t aptr = tb ? sp : cur_ptr;
-                    const uint32_t aidx = tb ? (uint32_t)(a + w * 64 + al) : cur_idx;
-                    const bool ahas = tb != 0 || cur_has;
-                    if (((fm >> l) & 1) && ahas && pt == aptr && aidx < D.n)
-                        atomicOr((unsigned long long*)&D.freed_bits[aidx >> 6], 1ull << (aidx & 63));
-                }
-                if (tmask) {
-                    const int tl = top64(tmask);
-                    cur_ptr = (uint32_t)readlane32((int)pt, tl);
-                    cur_idx = (uint32_t)(a + w * 64 + tl);
-                    cur_has = true;
-                }
-                cnt += __popcll(m);
-            }
-        }
-        PH_MARK(8);
+        if (l < NW) D.mask[j * NW + l] = cr.mvec;
         if (err && l == 0) atomicOr(&D.scal->err, err);
     }
-    PH_FLUSH(ctl);
-    if (cur_t >= 0 && l == 0) {
-        atomicMax((long long*)&desc[cur_t].scal->peak_F, (long long)peakF);
-        atomicMax((long long*)&desc[cur_t].scal->peak_S, (long long)peakS);
+    if (have_t && l == 0 && peakS > 0) atomicMax((long long*)&desc[cur_t].scal->peak_S, (long long)peakS);
+    __syncthreads();
+    hist_flush(hc, desc);
+}
+
+// --------------------------------------------------------------- scan pass
+
+// (count, best growth record, last-sample Python footprint) of a run of segments.
+struct BItem {
+    Best b;
+    bool lsh;
+    int64_t ls;
+};
+
+__device__ __forceinline__ BItem bcombine(const BItem& a, const BItem& b) {
+    BItem r;
+    r.b = combine(a.b, b.b);
+    r.lsh = a.lsh || b.lsh;
+    r.ls = b.lsh ? b.ls : a.ls;
+    return r;
+}
+
+// One workgroup per tile (ticket order): the state before every segment.
+__global__ __launch_bounds__(TILE) void k_bscan(const Desc* __restrict__ desc, int ntraces, uint64_t ntile_total,
+                                                unsigned long long* ctl) {
+    __shared__ unsigned long long s_tk;
+    __shared__ int64_t w_cnt[TWAVES], w_val[TWAVES], w_ls[TWAVES];
+    __shared__ uint32_t w_idx[TWAVES], w_ptr[TWAVES];
+    __shared__ int w_flags[TWAVES];
+    __shared__ int64_t s_pre_cnt, s_pre_val, s_pre_ls;
+    __shared__ uint32_t s_pre_idx, s_pre_ptr;
+    __shared__ int s_pre_has;
+    const int tid = threadIdx.x, wv = tid >> 6, l = lane_id();
+    if (tid == 0) s_tk = atomicAdd(&ctl[3], 1ull);
+    __syncthreads();
+    const uint64_t tk = s_tk;
+    if (tk >= ntile_total) return;
+    const Desc& D = desc[find_trace_tile(desc, ntraces, tk)];
+    const int64_t k = (int64_t)(tk - D.tile_begin);
+    const int64_t ns = (int64_t)D.nseg;
+    const int64_t j = k * TILE + tid;
+    const bool valid = j < ns;
+    const StatusView ts{D.tstat, (int64_t)D.ntile};
+    int64_t cnt = 0, gv = 0, gi = 0, gp = 0, lsv = 0, fl = 0;
+    if (valid) {
+        const int64_t* sp = D.seg + j;
+        cnt = sp[SP_BCNT * ns];
+        gv = sp[SP_BGV * ns];
+        gi = sp[SP_BGI * ns];
+        gp = sp[SP_BGP * ns];
+        lsv = sp[SP_LSV * ns];
+        fl = sp[SP_BFL * ns];
+    }
+    const bool hg = (fl & 1) != 0, hs = (fl & 2) != 0;
+    // inclusive within the wave
+    const int64_t icnt = wave_incl_sum(cnt);
+    const int64_t M = wave_incl_max(hg ? gv : INT64_MIN);
+    const int64_t Mp = wave_shr1(M, INT64_MIN);
+    const uint64_t le = lanemask_lt() | (1ull << l);
+    const uint64_t bnd = ballot(M != INT64_MIN && M > Mp) & le;  // where the running maximum rises
+    const int src = bnd ? top64(bnd) : l;
+    const uint32_t iidx = (uint32_t)shfl32((int)(uint32_t)gi, src), iptr = (uint32_t)shfl32((int)(uint32_t)gp, src);
+    const uint64_t lsm = ballot(hs) & le;
+    const int lsrc = lsm ? top64(lsm) : l;
+    const int64_t ils = shfl64(lsv, lsrc);
+    if (l == 63) {
+        w_cnt[wv] = icnt;
+        w_val[wv] = M;
+        w_idx[wv] = iidx;
+        w_ptr[wv] = iptr;
+        w_ls[wv] = ils;
+        w_flags[wv] = (M != INT64_MIN ? 1 : 0) | (lsm ? 2 : 0);
     }
     __syncthreads();
-    // flush the LDS histogram cache
-    for (int i = threadIdx.x; i < NSLOT; i += BLOCK) {
-        const unsigned long long key = hc.key[i];
-        if (key == EMPTY_KEY) continue;
-        const Desc& D = desc[(uint32_t)(key >> 32)];
-        const uint32_t line = (uint32_t)key;
-        for (int c = 0; c < NCNT; ++c) {
-            const unsigned long long v = hc.cnt[i][c];
-            if (v) atomicAdd((unsigned long long*)&D.hist[(size_t)cache_to_hist(c) * D.L + line], v);
+    BItem wpre{{0, false, 0, 0, 0}, false, 0}, agg{{0, false, 0, 0, 0}, false, 0};
+    for (int w = 0; w < TWAVES; ++w) {
+        if (w == wv) wpre = agg;
+        const BItem it{{w_cnt[w], (w_flags[w] & 1) != 0, w_val[w], w_idx[w], w_ptr[w]}, (w_flags[w] & 2) != 0, w_ls[w]};
+        agg = bcombine(agg, it);
+    }
+    if (tid == 0) {
+        st_status(ts.at(W_BCNT, k), pack(agg.b.cnt, 1));
+        st_status(ts.at(W_BGM, k), pack(agg.b.has ? agg.b.val : 0, agg.b.has ? 2 : 1));
+        st_status(ts.at(W_BGR, k), pack((int64_t)agg.b.idx, 1));
+        st_status(ts.at(W_BGP, k), pack((int64_t)agg.b.ptr, 1));
+        st_status(ts.at(W_LSA, k), pack(agg.ls, agg.lsh ? 2 : 1));
+    }
+    if (wv == 0) {
+        Best pre{0, false, 0, 0, 0};
+        int64_t eP = 0;
+        bool ok = true;
+        if (k > 0) {
+            ok = scan_best(ts, k, pre, ctl);
+            if (ok) ok = scan_last_sample(ts, k, eP, ctl);
+        }
+        const Best inc = with_baseline(combine(pre, agg.b));
+        if (l == 0) {
+            st_status(ts.at(W_ICNT, k), pack(inc.cnt, 1));
+            st_status(ts.at(W_IGM, k), pack(inc.val, inc.has ? 2 : 1));
+            st_status(ts.at(W_IGR, k), pack((int64_t)inc.idx, 1));
+            st_status(ts.at(W_IGP, k), pack((int64_t)inc.ptr, 1));
+            st_status(ts.at(W_LSI, k), pack(agg.lsh ? agg.ls : eP, 1));
+            s_pre_cnt = pre.cnt;
+            s_pre_has = pre.has ? 1 : 0;
+            s_pre_val = pre.val;
+            s_pre_idx = pre.idx;
+            s_pre_ptr = pre.ptr;
+            s_pre_ls = eP;
+            if (!ok) atomicOr(&D.scal->err, 8u);
         }
     }
+    __syncthreads();
+    // state before this segment: tile prefix, waves before, lanes before
+    const BItem tpre{{s_pre_cnt, s_pre_has != 0, s_pre_val, s_pre_idx, s_pre_ptr}, true, s_pre_ls};
+    const int pl = l > 0 ? l - 1 : 0;
+    const int64_t pcnt = shfl64(icnt, pl);
+    const uint32_t pidx = (uint32_t)shfl32((int)iidx, pl), pptr = (uint32_t)shfl32((int)iptr, pl);
+    const int64_t pls = shfl64(ils, pl);
+    const bool plsh = l > 0 && (lsm & ~(1ull << l)) != 0;
+    BItem lpre{{l > 0 ? pcnt : 0, l > 0 && Mp != INT64_MIN, Mp, pidx, pptr}, plsh, pls};
+    const BItem st = bcombine(bcombine(tpre, wpre), lpre);
+    const Best b = with_baseline(st.b);
+    if (valid) {
+        int64_t* o = D.seg + j;
+        o[SP_XCNT * ns] = b.cnt;
+        o[SP_XHV * ns] = b.val;
+        o[SP_XHI * ns] = b.idx;
+        o[SP_XHP * ns] = b.ptr;
+        o[SP_XFL * ns] = b.has ? 1 : 0;
+        o[SP_XLS * ns] = st.ls;
+        if (j == ns - 1) D.scal->K = (uint64_t)(b.cnt + cnt);
+    }
+}
+
+// --------------------------------------------------------------- emit pass
+
+// One wave per segment (grid-stride): write the segment's samples with their
+// attribution, per-line counters, tracked samples and the frees that reclaim
+// them.
+__global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
+    __shared__ int64_t lF[WAVES][SEG];
+    __shared__ int64_t lP[WAVES][SEG];
+    __shared__ uint32_t lPT[WAVES][SEG];
+    __shared__ HistCache hc;
+    hist_init(hc);
+    __syncthreads();
+    const int wv = threadIdx.x >> 6;
+    const int l = lane_id();
+    int cur_t = 0;
+    for (uint64_t g = (uint64_t)blockIdx.x * WAVES + wv; g < nseg_total; g += (uint64_t)gridDim.x * WAVES) {
+        const int t = find_trace_seg(desc, cur_t, ntraces, g);
+        cur_t = t;
+        const Desc& D = desc[t];
+        const int64_t j = (int64_t)(g - D.seg_begin);
+        const int64_t ns = (int64_t)D.nseg;
+        const int64_t a = j * SEG;
+        const int nv = seg_events(D, j);
+        const uint32_t L = D.L;
+        SegScan sc;
+        load_segment<true, true, false>(D, a, nv, lF[wv], lP[wv], lPT[wv], sc);
+        int64_t pv = 0;
+        if (l < 3) pv = D.seg[(SP_F0 + l) * ns + j];  // F0, P0 (C0 unused)
+        else if (l == 3) pv = D.seg[SP_EF * ns + j];
+        else if (l < 10) pv = D.seg[(SP_XCNT + (l - 4)) * ns + j];
+        const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), eF = readlane64(pv, 3);
+        int64_t base = readlane64(pv, 4);
+        const int64_t hv = readlane64(pv, 5);
+        const uint32_t hidx = (uint32_t)readlane64(pv, 6), hptr = (uint32_t)readlane64(pv, 7);
+        const bool hh = (readlane64(pv, 8) & 1) != 0;
+        const int64_t eP = readlane64(pv, 9);
+        const uint64_t smask_v = l < NW ? D.mask[j * NW + l] : 0;
+        const uint64_t free_v = sc.free_v;
+        uint32_t err = 0;
+        if (base < 0 || base > (int64_t)D.n) {  // only reachable after an internal fault
+            err |= 8u;
+            base = 0;
+        }
+        int64_t refF = eF, refP = eP - P0;
+        int64_t cnt = 0;
+        bool cur_has = hh;
+        uint32_t cur_ptr = hptr, cur_idx = hidx;
+        int64_t hwm = hh ? hv : 0;
+        for (int w = 0; w < NW; ++w) {
+            const uint64_t m = readlaneu64(smask_v, w);
+            const uint64_t fm = readlaneu64(free_v, w);
+            if (m == 0 && (fm == 0 || !cur_has)) continue;
+            const int k = w * 64 + l;
+            const int64_t f = lF[wv][k];
+            const int64_t p = lP[wv][k];
+            const uint32_t pt = lPT[wv][k];
+            const uint64_t below = m & lanemask_lt();
+            uint64_t tmask = 0;
+            if (m) {
+                const int pl = below ? top64(below) : l;
+                int64_t fprev = shfl64(f, pl), pprev = shfl64(p, pl);
+                if (!below) {
+                    fprev = refF;
+                    pprev = refP;
+                }
+                const bool is_s = ((m >> l) & 1) && k < nv;
+                const int64_t dl = f - fprev;
+                const int64_t pyb = p - pprev;
+                const int64_t nat = dl - pyb;
+                const int64_t Fabs = F0 + f;
+                const int64_t rank = base + cnt + __popcll(below);
+                if (is_s && rank < (int64_t)D.n) {
+                    const uint32_t ln = ((const uint32_t*)(D.ev + (size_t)(a + k) * 24))[3];
+                    Sample smp;
+                    smp.event_idx = (uint32_t)(a + k);
+                    smp.line = ln;
+                    smp.F = Fabs;
+                    smp.py = pyb;
+                    smp.nat = nat;
+                    D.samples[rank] = smp;
+                    if (ln < L) {
+                        const bool gr = dl > 0;
+                        hist_add(hc, D, (uint32_t)t, ln, C_PY, pyb, C_NAT, nat, gr ? C_GN : C_SN, 1,
+                                 gr ? C_GB : C_SB, gr ? dl : -dl);
+                    }
+                }
+                uint64_t cand = ballot(is_s && dl > 0 && Fabs > hwm);
+                while (cand) {
+                    const int c = ctz64(cand);
+                    cand &= cand - 1;
+                    const int64_t Fc = readlane64(Fabs, c);
+                    if (Fc > hwm) {
+                        hwm = Fc;
+                        tmask |= 1ull << c;
+                    }
+                }
+                if (((tmask >> l) & 1) && rank < (int64_t)D.n) {
+                    atomicOr((unsigned long long*)&D.tracked_bits[rank >> 6], 1ull << (rank & 63));
+                    D.sample_ptr[rank] = pt;
+                }
+                const int ls = top64(m);
+                refF = readlane64(f, ls);
+                refP = readlane64(p, ls);
+            }
+            if (fm && (cur_has || tmask)) {
+                const uint64_t tb = tmask & lanemask_lt();
+                const int al = tb ? top64(tb) : l;
+                const uint32_t spt = (uint32_t)shfl32((int)pt, al);
+                const uint32_t aptr = tb ? spt : cur_ptr;
+                const uint32_t aidx = tb ? (uint32_t)(a + w * 64 + al) : cur_idx;
+                const bool ahas = tb != 0 || cur_has;
+                if (((fm >> l) & 1) && ahas && pt == aptr && aidx < D.n)
+                    atomicOr((unsigned long long*)&D.freed_bits[aidx >> 6], 1ull << (aidx & 63));
+            }
+            if (tmask) {
+                const int tl = top64(tmask);
+                cur_ptr = (uint32_t)readlane32((int)pt, tl);
+                cur_idx = (uint32_t)(a + w * 64 + tl);
+                cur_has = true;
+            }
+            cnt += __popcll(m);
+        }
+        if (err && l == 0) atomicOr(&D.scal->err, err);
+    }
+    __syncthreads();
+    hist_flush(hc, desc);
 }
 
 // ----------------------------------------------------------------- clearing
@@ -1202,36 +1490,35 @@ __global__ void k_leak_finalize(const Desc* __restrict__ desc, int ntraces, uint
 
 // ------------------------------------------------------------ launchers
 
-#ifdef SMP_PHASE_STATS
-int read_lbstat(unsigned long long* out8, bool reset) {
-    if (hipMemcpyFromSymbol(out8, HIP_SYMBOL(g_lbstat), 8 * sizeof(unsigned long long)) != hipSuccess) return -1;
-    if (reset) {
-        unsigned long long z[8] = {0};
-        if (hipMemcpyToSymbol(HIP_SYMBOL(g_lbstat), z, sizeof(z)) != hipSuccess) return -1;
-    }
-    return 0;
-}
-#endif
-
-int sample_grid_limit() {
+static int occupancy_grid(const void* fn, int block) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sample, BLOCK, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, block, 0) != hipSuccess) return 0;
     return cus * (per > 0 ? per : 1);
 }
 
-hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, unsigned long long* ticket,
-                        hipStream_t s) {
+int chain_grid_limit() { return occupancy_grid((const void*)k_chain, BLOCK); }
+int emit_grid_limit() { return occupancy_grid((const void*)k_emit, BLOCK); }
+
+hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, unsigned long long* ctl, hipStream_t s) {
     const uint64_t blocks = (total_bytes + (1ull << 16) - 1) >> 16;
-    k_clear<<<dim3((unsigned)(blocks ? blocks : 1)), dim3(256), 0, s>>>(desc, ntraces, total_bytes, ticket);
+    k_clear<<<dim3((unsigned)(blocks ? blocks : 1)), dim3(256), 0, s>>>(desc, ntraces, total_bytes, ctl);
     return hipGetLastError();
 }
 
-hipError_t launch_sample(const Desc* desc, int ntraces, uint64_t nseg_total, unsigned long long* ticket, int grid,
-                         hipStream_t s) {
+hipError_t launch_pass(int pass, const Desc* desc, int ntraces, uint64_t nseg_total, uint64_t ntile_total,
+                       unsigned long long* ctl, int grid_limit, hipStream_t s) {
     if (nseg_total == 0) return hipSuccess;
-    k_sample<<<dim3((unsigned)grid), dim3(BLOCK), 0, s>>>(desc, ntraces, nseg_total, ticket);
+    const uint64_t wgs = (nseg_total + WAVES - 1) / WAVES;
+    const unsigned pgrid = (unsigned)(wgs < (uint64_t)grid_limit ? wgs : (uint64_t)grid_limit);
+    switch (pass) {
+        case 0: k_summarize<<<dim3((unsigned)wgs), dim3(BLOCK), 0, s>>>(desc, ntraces, nseg_total); break;
+        case 1: k_resolve<<<dim3((unsigned)ntile_total), dim3(TILE), 0, s>>>(desc, ntraces, ntile_total, ctl); break;
+        case 2: k_chain<<<dim3(pgrid), dim3(BLOCK), 0, s>>>(desc, ntraces, nseg_total); break;
+        case 3: k_bscan<<<dim3((unsigned)ntile_total), dim3(TILE), 0, s>>>(desc, ntraces, ntile_total, ctl); break;
+        default: k_emit<<<dim3(pgrid), dim3(BLOCK), 0, s>>>(desc, ntraces, nseg_total); break;
+    }
     return hipGetLastError();
 }
 

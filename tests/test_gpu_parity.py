@@ -197,6 +197,41 @@ def test_adversarial(sampler):
     check_batch(sampler, adversarial_cases())
 
 
+def multi_tile_cases():
+    """Traces longer than one tile of 1024 segments (524,288 events) whose
+    segment maps are rarely or never total, so that chain states travel
+    serially across waves and tiles, and segments whose chains do not all
+    coincide have to be followed from their actual entry."""
+    out = []
+    n = 3 * 1024 * 512 + 777
+    mono = np.zeros(n, dtype=tg.EVENT_DTYPE)
+    mono["delta"] = 1
+    mono["ptr"] = np.arange(1, n + 1)
+    mono["line"] = np.arange(n) % 3
+    for T in (10 ** 9, 700, 1023, 100_000):
+        out.append((f"mono3t T{T}", mono, dict(threshold=T, num_lines=3)))
+    rng = np.random.default_rng(17)
+    drift = np.zeros(2 * 1024 * 512 + 5, dtype=tg.EVENT_DTYPE)
+    drift["delta"] = rng.integers(-100, 101, drift.shape[0])
+    drift["ptr"] = np.arange(1, drift.shape[0] + 1)
+    drift["line"] = rng.integers(0, 5, drift.shape[0])
+    drift["flags"] = (rng.random(drift.shape[0]) < 0.3).astype(np.uint8)
+    for T in (300, 2_000, 30_000, 10 ** 7):
+        out.append((f"drift2t T{T}", drift, dict(threshold=T, num_lines=5)))
+    for nseg in (1024, 1025, 2048):
+        for extra in (0, 1):
+            m = nseg * 512 - (1 - extra) * 3
+            out.append((f"edge n{m}", mono[:m], dict(threshold=5000, num_lines=3)))
+    return out
+
+
+def test_multi_tile_chains(sampler):
+    say("multi-tile traces with unresolved chains")
+    cases = multi_tile_cases()
+    for i in range(0, len(cases), 4):
+        check_batch(sampler, cases[i:i + 4])
+
+
 def test_copy_and_timer_mix(sampler):
     say("copy + timer mix")
     ev = tg.mix(9, 300_000, num_lines=1000, zipf_s=1.05, copy_frac=0.10, timer_frac=0.01)
