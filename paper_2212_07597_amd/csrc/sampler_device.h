@@ -17,7 +17,7 @@ constexpr int WAVES = 4;                 // wavefronts per workgroup of the per-
 constexpr int BLOCK = 64 * WAVES;
 constexpr int TILE = 1024;               // segments per tile
 constexpr int TWAVES = TILE / 64;
-constexpr int NSLOT = 128;               // LDS histogram cache slots per workgroup
+constexpr int NSLOT = 32;                // LDS histogram cache slots per workgroup
 constexpr int NCNT = 10;                 // counters cached per slot
 constexpr int CHAIN_CAP = 32;            // chains followed by the all-entry analysis
 
@@ -36,8 +36,13 @@ enum { MAP_SIM = 0, MAP_CONST = 1, MAP_TOTAL = 2 };
 // Per-segment values, one int64 plane each (plane p of segment j at
 // seg[p * nseg + j]), written once per run by the pass named.
 enum {
-    // summary pass: sums, extremes of the relative prefixes, chain map
-    SP_AF = 0, SP_AP, SP_AC, SP_MXF, SP_MNF, SP_MXP, SP_MNP, SP_LO, SP_HI, SP_KF, SP_KIND,
+    // summary pass: sums, extremes of the relative prefixes, chain map (SP_FLG: kind in bits 0-1,
+    // bit 2 = copy or timer events present), and the chain after the first forced sample, which is
+    // the same for every entry: its node (-1 if none), samples after it, best growth sample after
+    // it (value, node or -1), largest sampled footprint after it, last sample node after it (or -1)
+    // and the Python footprint there (relative values)
+    SP_AF = 0, SP_AP, SP_AC, SP_MXF, SP_MNF, SP_MXP, SP_MNP, SP_LO, SP_HI, SP_KF, SP_FLG,
+    SP_FN, SP_ACNT, SP_AGV, SP_AGN, SP_ASMX, SP_ALS, SP_ALP,
     // resolve pass: exclusive prefixes, entry and exit offsets of the chain
     SP_F0, SP_P0, SP_C0, SP_EF, SP_XF,
     // chain pass: samples, best growth sample (value, event, ptr), Python footprint at the last sample, flags

@@ -167,16 +167,17 @@ struct SegScan {
 
 // Load one segment's records (all loads issued before any use), decode them
 // and scan the footprint and Python footprint; the relative prefixes (after
-// each event, segment start = 0) go to F (and P, ptr ids to PT, if asked).
-template <bool STORE_P, bool STORE_PTR, bool EXT>
-__device__ __forceinline__ void load_segment(const Desc& D, int64_t a, int nv, int64_t* F, int64_t* P, uint32_t* PT,
-                                             SegScan& o) {
+// each event, segment start = 0) go to F (and P, and (line << 32 | ptr id) to
+// PL, if asked).  Only the first nwin windows are read.
+template <bool STORE_P, bool STORE_PL, bool EXT>
+__device__ __forceinline__ void load_segment(const Desc& D, int64_t a, int nv, int64_t* F, int64_t* P, uint64_t* PL,
+                                             SegScan& o, int nwin = NW) {
     const int l = lane_id();
     uint64_t q0[NW], q1[NW], q2[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         const int k = w * 64 + l;
-        if (k < nv) {
+        if (w < nwin && k < nv) {
             const uint64_t* p = (const uint64_t*)(D.ev + (size_t)(a + k) * 24);
             q0[w] = __builtin_nontemporal_load(p);
             q1[w] = __builtin_nontemporal_load(p + 1);
@@ -196,6 +197,7 @@ __device__ __forceinline__ void load_segment(const Desc& D, int64_t a, int nv, i
     const int64_t two_t = 2 * D.T - 1;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
+        if (w >= nwin) break;
         const int k = w * 64 + l;
         const bool valid = k < nv;
         const Ev e = decode(q0[w], q1[w], q2[w], valid, D.L);
@@ -212,7 +214,7 @@ __device__ __forceinline__ void load_segment(const Desc& D, int64_t a, int nv, i
         cP = readlane64(sP, 63);
         F[k] = sF;
         if (STORE_P) P[k] = sP;
-        if (STORE_PTR) PT[k] = e.ptr;
+        if (STORE_PL) PL[k] = q1[w];
         accC += e.dc;
         if (ballot(e.aux)) any_aux = true;
         if (EXT && valid) {
@@ -256,12 +258,12 @@ struct ChainRun {
     int lastS;
 };
 
-// Follow cr from window w0 (after lane st0) to the segment end, sampling
+// Follow cr from window w0 (after lane st0) through window wend, sampling
 // wherever the footprint is at least T away from the reference (section 3.2).
 template <bool FULL>
-__device__ void run_chain(const int64_t* F, int64_t T, ChainRun& cr, int w0, int st0) {
+__device__ void run_chain(const int64_t* F, int64_t T, ChainRun& cr, int w0, int st0, int wend = NW - 1) {
     const int l = lane_id();
-    for (int w = w0; w < NW; ++w) {
+    for (int w = w0; w <= wend; ++w) {
         const int64_t f = F[w * 64 + l];
         int stl = w == w0 ? st0 : -1;
         uint64_t m = 0;
@@ -307,6 +309,8 @@ __device__ __forceinline__ bool follow(int64_t f, int64_t T, int64_t& ref, int s
 struct SegMap {
     int64_t lo, hi, kf;
     int kind;
+    int fnode;     // first forced event (-1 if none)
+    ChainRun after;  // the chain after it (samples strictly after fnode)
 };
 
 // All-entry analysis of one segment (F: relative prefixes in LDS).
@@ -320,11 +324,13 @@ __device__ SegMap analyse_segment(const int64_t* F, int64_t T, uint64_t forced_v
         const int fwin = ctz64(wf);
         const int flane = ctz64(readlaneu64(forced_v, fwin));
         ChainRun r{readlane64(F[fwin * 64 + l], flane), 0, 0, -1, INT64_MIN, -1};
-        run_chain<false>(F, T, r, fwin, flane);
+        run_chain<true>(F, T, r, fwin, flane);
         m.lo = 1;
         m.hi = 0;
         m.kf = r.ref - sumF;
         m.kind = MAP_TOTAL;
+        m.fnode = fwin * 64 + flane;
+        m.after = r;
         return m;
     }
     // Entries in [Lo, Hi] have not sampled yet; chain c (lane c < nch) holds
@@ -390,6 +396,8 @@ __device__ SegMap analyse_segment(const int64_t* F, int64_t T, uint64_t forced_v
     if (Lo > T) Lo = T;
     if (Hi < -T) Hi = -T;
     const bool has_const = !ovf && nch == 1;
+    m.fnode = -1;
+    m.after = ChainRun{0, 0, 0, -1, INT64_MIN, -1};
     m.lo = Lo;
     m.hi = Hi;
     m.kf = has_const ? readlane64(chref, 0) - sumF : 0;
@@ -733,6 +741,7 @@ __device__ bool scan_last_sample(const StatusView& sv, int64_t g, int64_t& oP, u
 __global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ desc, int ntraces,
                                                      uint64_t nseg_total) {
     __shared__ int64_t lF[WAVES][SEG];
+    __shared__ int64_t lP[WAVES][SEG];
     const int wv = threadIdx.x >> 6;
     const int l = lane_id();
     const uint64_t g = (uint64_t)blockIdx.x * WAVES + wv;
@@ -742,9 +751,12 @@ __global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ de
     const int64_t a = j * SEG;
     const int nv = seg_events(D, j);
     SegScan sc;
-    load_segment<false, false, true>(D, a, nv, lF[wv], nullptr, nullptr, sc);
+    load_segment<true, false, true>(D, a, nv, lF[wv], lP[wv], nullptr, sc);
     const SegMap m = analyse_segment(lF[wv], D.T, sc.forced_v, sc.sumF);
-    if (l <= SP_KIND) {
+    const ChainRun& r = m.after;
+    const int64_t acnt = wave_sum(l < NW ? (int64_t)__popcll(r.mvec) : 0);
+    const int64_t alp = r.lastS >= 0 ? lP[wv][r.lastS] : 0;
+    if (l <= SP_ALP) {
         int64_t v;
         switch (l) {
             case SP_AF: v = sc.sumF; break;
@@ -757,10 +769,18 @@ __global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ de
             case SP_LO: v = m.lo; break;
             case SP_HI: v = m.hi; break;
             case SP_KF: v = m.kf; break;
-            default: v = m.kind; break;
+            case SP_FLG: v = m.kind | (sc.any_aux ? 4 : 0); break;
+            case SP_FN: v = m.fnode; break;
+            case SP_ACNT: v = acnt; break;
+            case SP_AGV: v = r.gbest; break;
+            case SP_AGN: v = r.gnode; break;
+            case SP_ASMX: v = r.smax; break;
+            case SP_ALS: v = r.lastS; break;
+            default: v = alp; break;
         }
         D.seg[(int64_t)l * (int64_t)D.nseg + j] = v;
     }
+    if (m.fnode >= 0 && l < NW) D.mask[j * NW + l] = r.mvec;
     if (sc.err && l == 0) atomicOr(&D.scal->err, sc.err);
 }
 
@@ -807,7 +827,7 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
         lo = sp[SP_LO * ns];
         hi = sp[SP_HI * ns];
         kf = sp[SP_KF * ns];
-        kind = (int)sp[SP_KIND * ns];
+        kind = (int)(sp[SP_FLG * ns] & 3);
     }
     // sums inside the wave
     const int64_t iF = wave_incl_sum(af), iP = wave_incl_sum(ap), iC = wave_incl_sum(ac);
@@ -957,19 +977,28 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         const int64_t a = j * SEG;
         const int nv = seg_events(D, j);
         const int64_t T = D.T;
-        SegScan sc;
-        load_segment<true, false, false>(D, a, nv, lF[wv], lP[wv], nullptr, sc);
+        // lanes 0-4: prefixes, entry and exit from the resolve pass; lanes 5-12: flags
+        // and the chain after the first forced sample from the summary pass
         int64_t pv = 0;
         if (l < 5) pv = D.seg[(SP_F0 + l) * ns + j];
+        else if (l == 5) pv = D.seg[SP_FLG * ns + j];
+        else if (l < 13) pv = D.seg[(SP_FN + (l - 6)) * ns + j];
         const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), C0 = readlane64(pv, 2);
         const int64_t eF = readlane64(pv, 3), xF = readlane64(pv, 4);
+        const int64_t flg = readlane64(pv, 5);
+        const int fn = (int)readlane64(pv, 6);
+        // From a forced sample on the chain is the one the summary pass followed,
+        // so only the events up to it are read again.
+        const int fwin = fn >= 0 ? fn >> 6 : NW - 1;
+        SegScan sc;
+        load_segment<true, false, false>(D, a, fn >= 0 ? fn + 1 : nv, lF[wv], lP[wv], nullptr, sc, fwin + 1);
         uint32_t err = 0;
 
         // Copy volume (section 3.5: one Tc sample per multiple of Tc crossed by
         // the cumulative copy bytes) and the timer split (section 2.1: Python
         // time += quantum, native time += delay).  Only segments that hold such
         // events re-read their records here.
-        if (sc.any_aux) {
+        if (flg & 4) {
             int64_t cc = C0;
             for (int w = 0; w < NW; ++w) {
                 const int k = w * 64 + l;
@@ -1010,27 +1039,49 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         }
 
         ChainRun cr{eF, 0, 0, -1, INT64_MIN, -1};
-        run_chain<true>(lF[wv], T, cr, 0, -1);
-        if (cr.ref - sc.sumF != xF) err |= 4u;  // internal: the resolved exit disagrees with the chain
-        const int count = (int)wave_sum(l < NW ? (int64_t)__popcll(cr.mvec) : 0);
-        if (cr.smax != INT64_MIN && F0 + cr.smax > peakS) peakS = F0 + cr.smax;
-        const bool hg = cr.gnode >= 0 && cr.gnode < nv;  // nodes past the trace end never sample
+        run_chain<true>(lF[wv], T, cr, 0, -1, fwin);
+        int64_t count = wave_sum(l < NW ? (int64_t)__popcll(cr.mvec) : 0);
+        int64_t gbest = cr.gbest, smax = cr.smax, lsrel = 0;
+        int gnode = cr.gnode, lastS = cr.lastS;
+        if (fn >= 0) {
+            if (lastS != fn) err |= 4u;  // internal: every entry samples at a forced event
+            count += readlane64(pv, 7);
+            const int64_t agv = readlane64(pv, 8), asmx = readlane64(pv, 10);
+            const int agn = (int)readlane64(pv, 9), als = (int)readlane64(pv, 11);
+            if (agn >= 0 && (gnode < 0 || agv > gbest)) {
+                gbest = agv;
+                gnode = agn;
+            }
+            if (asmx > smax) smax = asmx;
+            if (als >= 0) {
+                lastS = als;
+                lsrel = readlane64(pv, 12);
+            } else {
+                lsrel = lP[wv][fn];
+            }
+        } else {
+            if (cr.ref - sc.sumF != xF) err |= 4u;  // internal: the resolved exit disagrees with the chain
+            if (lastS >= 0) lsrel = lP[wv][lastS];
+        }
+        if (smax != INT64_MIN && F0 + smax > peakS) peakS = F0 + smax;
+        const bool hg = gnode >= 0 && gnode < nv;  // nodes past the trace end never sample
         uint32_t gptr = 0;
-        if (hg) gptr = ((const uint32_t*)(D.ev + (size_t)(a + cr.gnode) * 24))[2];
-        const int64_t lsv = cr.lastS >= 0 ? P0 + lP[wv][cr.lastS] : 0;
+        if (hg) gptr = ((const uint32_t*)(D.ev + (size_t)(a + gnode) * 24))[2];
+        const int64_t lsv = lastS >= 0 ? P0 + lsrel : 0;
         if (l < 6) {
             int64_t v;
             switch (l) {
                 case 0: v = count; break;
-                case 1: v = hg ? F0 + cr.gbest : 0; break;
-                case 2: v = hg ? a + cr.gnode : 0; break;
+                case 1: v = hg ? F0 + gbest : 0; break;
+                case 2: v = hg ? a + gnode : 0; break;
                 case 3: v = gptr; break;
                 case 4: v = lsv; break;
-                default: v = (hg ? 1 : 0) | (cr.lastS >= 0 ? 2 : 0); break;
+                default: v = (hg ? 1 : 0) | (lastS >= 0 ? 2 : 0); break;
             }
             D.seg[(SP_BCNT + l) * ns + j] = v;
         }
-        if (l < NW) D.mask[j * NW + l] = cr.mvec;
+        // windows after the forced sample's keep the summary pass's masks
+        if (l < NW && l <= fwin) D.mask[j * NW + l] = cr.mvec | (fn >= 0 && l == fwin ? D.mask[j * NW + l] : 0ull);
         if (err && l == 0) atomicOr(&D.scal->err, err);
     }
     if (have_t && l == 0 && peakS > 0) atomicMax((long long*)&desc[cur_t].scal->peak_S, (long long)peakS);
@@ -1175,7 +1226,7 @@ __global__ __launch_bounds__(TILE) void k_bscan(const Desc* __restrict__ desc, i
 __global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
     __shared__ int64_t lF[WAVES][SEG];
     __shared__ int64_t lP[WAVES][SEG];
-    __shared__ uint32_t lPT[WAVES][SEG];
+    __shared__ uint64_t lPL[WAVES][SEG];
     __shared__ HistCache hc;
     hist_init(hc);
     __syncthreads();
@@ -1192,7 +1243,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, i
         const int nv = seg_events(D, j);
         const uint32_t L = D.L;
         SegScan sc;
-        load_segment<true, true, false>(D, a, nv, lF[wv], lP[wv], lPT[wv], sc);
+        load_segment<true, true, false>(D, a, nv, lF[wv], lP[wv], lPL[wv], sc);
         int64_t pv = 0;
         if (l < 3) pv = D.seg[(SP_F0 + l) * ns + j];  // F0, P0 (C0 unused)
         else if (l == 3) pv = D.seg[SP_EF * ns + j];
@@ -1222,7 +1273,8 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, i
             const int k = w * 64 + l;
             const int64_t f = lF[wv][k];
             const int64_t p = lP[wv][k];
-            const uint32_t pt = lPT[wv][k];
+            const uint64_t plw = lPL[wv][k];
+            const uint32_t pt = (uint32_t)plw;
             const uint64_t below = m & lanemask_lt();
             uint64_t tmask = 0;
             if (m) {
@@ -1239,7 +1291,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, i
                 const int64_t Fabs = F0 + f;
                 const int64_t rank = base + cnt + __popcll(below);
                 if (is_s && rank < (int64_t)D.n) {
-                    const uint32_t ln = ((const uint32_t*)(D.ev + (size_t)(a + k) * 24))[3];
+                    const uint32_t ln = (uint32_t)(plw >> 32);
                     Sample smp;
                     smp.event_idx = (uint32_t)(a + k);
                     smp.line = ln;
