@@ -157,6 +157,13 @@ __device__ __forceinline__ Ev decode(uint64_t r0, uint64_t r1, uint64_t r2, bool
     return e;
 }
 
+// Global-memory view of the records (the descriptor's generic pointer would
+// otherwise compile to flat loads).
+typedef const __attribute__((address_space(1))) uint64_t gu64_t;
+typedef const __attribute__((address_space(1))) uint8_t gu8_t;
+
+__device__ __forceinline__ gu64_t* record(const Desc& D, int64_t i) { return (gu64_t*)(D.ev + (size_t)i * 24); }
+
 struct SegScan {
     int64_t sumF, sumP, sumC;
     int64_t mxF, mnF, mxP, mnP;  // extremes of the relative prefixes (EXT only)
@@ -165,29 +172,33 @@ struct SegScan {
     uint32_t err;
 };
 
-// Load one segment's records (all loads issued before any use), decode them
-// and scan the footprint and Python footprint; the relative prefixes (after
-// each event, segment start = 0) go to F (and P, and (line << 32 | ptr id) to
-// PL, if asked).  Only the first nwin windows are read.
+// Load one segment's first nv (>= 1) records, decode them and scan the
+// footprint and Python footprint; the relative prefixes (after each event,
+// segment start = 0) go to F (and P, and (line << 32 | ptr id) to PL, if
+// asked).  Only the first nwin windows are scanned.  Every lane issues all
+// of its loads before the first use; lanes past nv re-read record nv-1 (a
+// line already fetched) and are masked out.
 template <bool STORE_P, bool STORE_PL, bool EXT>
 __device__ __forceinline__ void load_segment(const Desc& D, int64_t a, int nv, int64_t* F, int64_t* P, uint64_t* PL,
                                              SegScan& o, int nwin = NW) {
     const int l = lane_id();
     uint64_t q0[NW], q1[NW], q2[NW];
+    gu8_t* base = (gu8_t*)(D.ev + (size_t)a * 24);  // wave-uniform
+    gu64_t* ptrs[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         const int k = w * 64 + l;
-        if (w < nwin && k < nv) {
-            const uint64_t* p = (const uint64_t*)(D.ev + (size_t)(a + k) * 24);
-            q0[w] = __builtin_nontemporal_load(p);
-            q1[w] = __builtin_nontemporal_load(p + 1);
-            q2[w] = __builtin_nontemporal_load(p + 2);
-        } else {
-            q0[w] = 0;
-            q1[w] = 0;
-            q2[w] = 0;
-        }
+        ptrs[w] = (gu64_t*)(base + (uint32_t)((k < nv ? k : nv - 1) * 24));
     }
+    // addresses first, so that no load's destination is reused before all are issued
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        q0[w] = __builtin_nontemporal_load(ptrs[w]);
+        q1[w] = __builtin_nontemporal_load(ptrs[w] + 1);
+        q2[w] = __builtin_nontemporal_load(ptrs[w] + 2);
+    }
+    __builtin_amdgcn_sched_barrier(0);
     int64_t cF = 0, cP = 0, accC = 0;
     int64_t mxF = INT64_MIN, mnF = INT64_MAX, mxP = INT64_MIN, mnP = INT64_MAX;
     uint64_t forced_v = 0, free_v = 0;
@@ -742,11 +753,11 @@ __global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ de
                                                      uint64_t nseg_total) {
     __shared__ int64_t lF[WAVES][SEG];
     __shared__ int64_t lP[WAVES][SEG];
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int l = lane_id();
     const uint64_t g = (uint64_t)blockIdx.x * WAVES + wv;
     if (g >= nseg_total) return;
-    const Desc& D = desc[find_trace_seg(desc, 0, ntraces, g)];
+    const Desc& D = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g))];
     const int64_t j = (int64_t)(g - D.seg_begin);
     const int64_t a = j * SEG;
     const int nv = seg_events(D, j);
@@ -959,13 +970,13 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
     __shared__ HistCache hc;
     hist_init(hc);
     __syncthreads();
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int l = lane_id();
     int cur_t = 0;
     int64_t peakS = 0;
     bool have_t = false;
     for (uint64_t g = (uint64_t)blockIdx.x * WAVES + wv; g < nseg_total; g += (uint64_t)gridDim.x * WAVES) {
-        const int t = find_trace_seg(desc, cur_t, ntraces, g);
+        const int t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, cur_t, ntraces, g));
         if (t != cur_t && have_t && l == 0 && peakS > 0)
             atomicMax((long long*)&desc[cur_t].scal->peak_S, (long long)peakS);
         if (t != cur_t) peakS = 0;
@@ -1230,11 +1241,11 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, i
     __shared__ HistCache hc;
     hist_init(hc);
     __syncthreads();
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int l = lane_id();
     int cur_t = 0;
     for (uint64_t g = (uint64_t)blockIdx.x * WAVES + wv; g < nseg_total; g += (uint64_t)gridDim.x * WAVES) {
-        const int t = find_trace_seg(desc, cur_t, ntraces, g);
+        const int t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, cur_t, ntraces, g));
         cur_t = t;
         const Desc& D = desc[t];
         const int64_t j = (int64_t)(g - D.seg_begin);
