@@ -162,7 +162,14 @@ __device__ __forceinline__ Ev decode(uint64_t r0, uint64_t r1, uint64_t r2, bool
 typedef const __attribute__((address_space(1))) uint64_t gu64_t;
 typedef const __attribute__((address_space(1))) uint8_t gu8_t;
 
+typedef const __attribute__((address_space(1))) int64_t gi64_t;
+
 __device__ __forceinline__ gu64_t* record(const Desc& D, int64_t i) { return (gu64_t*)(D.ev + (size_t)i * 24); }
+
+// Value p of segment j (any lane-varying p; global loads, never flat).
+__device__ __forceinline__ int64_t seg_val(const Desc& D, int p, int64_t j) {
+    return ((gi64_t*)D.seg)[(int64_t)p * (int64_t)D.nseg + j];
+}
 
 struct SegScan {
     int64_t sumF, sumP, sumC;
@@ -172,17 +179,16 @@ struct SegScan {
     uint32_t err;
 };
 
-// Load one segment's first nv (>= 1) records, decode them and scan the
-// footprint and Python footprint; the relative prefixes (after each event,
-// segment start = 0) go to F (and P, and (line << 32 | ptr id) to PL, if
-// asked).  Only the first nwin windows are scanned.  Every lane issues all
-// of its loads before the first use; lanes past nv re-read record nv-1 (a
-// line already fetched) and are masked out.
-template <bool STORE_P, bool STORE_PL, bool EXT>
-__device__ __forceinline__ void load_segment(const Desc& D, int64_t a, int nv, int64_t* F, int64_t* P, uint64_t* PL,
-                                             SegScan& o, int nwin = NW) {
-    const int l = lane_id();
+// A segment's records in registers: lane l holds records 64w + l.
+struct SegRecs {
     uint64_t q0[NW], q1[NW], q2[NW];
+};
+
+// Issue the loads of one segment's first nv (>= 1) records; lanes past nv
+// re-read record nv-1 (a line already fetched).  All addresses are formed
+// before the first load so that the loads leave back to back.
+__device__ __forceinline__ void fetch_segment(const Desc& D, int64_t a, int nv, SegRecs& r) {
+    const int l = lane_id();
     gu8_t* base = (gu8_t*)(D.ev + (size_t)a * 24);  // wave-uniform
     gu64_t* ptrs[NW];
 #pragma unroll
@@ -190,15 +196,32 @@ __device__ __forceinline__ void load_segment(const Desc& D, int64_t a, int nv, i
         const int k = w * 64 + l;
         ptrs[w] = (gu64_t*)(base + (uint32_t)((k < nv ? k : nv - 1) * 24));
     }
-    // addresses first, so that no load's destination is reused before all are issued
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        q0[w] = __builtin_nontemporal_load(ptrs[w]);
-        q1[w] = __builtin_nontemporal_load(ptrs[w] + 1);
-        q2[w] = __builtin_nontemporal_load(ptrs[w] + 2);
+        r.q0[w] = __builtin_nontemporal_load(ptrs[w]);
+        r.q1[w] = __builtin_nontemporal_load(ptrs[w] + 1);
+        r.q2[w] = __builtin_nontemporal_load(ptrs[w] + 2);
     }
     __builtin_amdgcn_sched_barrier(0);
+}
+
+// What a pass takes from a segment's records.
+enum ScanMode {
+    SCAN_SUMMARY,  // validate; forced events; copy/timer presence; sums; extremes
+    SCAN_CHAIN,    // footprint and Python footprint prefixes
+    SCAN_EMIT,     // the same, plus (line << 32 | ptr id) and the frees
+};
+
+// Decode and scan the first nwin windows of a fetched segment of nv events;
+// the relative prefixes (after each event, segment start = 0) go to F and P,
+// record words to PL.  Only the summary pass validates records: a malformed
+// event fails the whole trace, so the other passes decode memory deltas
+// without range checks and never index memory with unchecked fields.
+template <int MODE>
+__device__ __forceinline__ void scan_segment(const Desc& D, int nv, const SegRecs& r, int64_t* F, int64_t* P,
+                                             uint64_t* PL, SegScan& o, int nwin = NW) {
+    const int l = lane_id();
     int64_t cF = 0, cP = 0, accC = 0;
     int64_t mxF = INT64_MIN, mnF = INT64_MAX, mxP = INT64_MIN, mnP = INT64_MAX;
     uint64_t forced_v = 0, free_v = 0;
@@ -211,24 +234,33 @@ __device__ __forceinline__ void load_segment(const Desc& D, int64_t a, int nv, i
         if (w >= nwin) break;
         const int k = w * 64 + l;
         const bool valid = k < nv;
-        const Ev e = decode(q0[w], q1[w], q2[w], valid, D.L);
-        if (ballot(e.bad)) err |= 1u;
-        const uint64_t fm = ballot(e.dm >= two_t || e.dm <= -two_t);
-        const uint64_t frm = ballot(e.dm < 0);
-        if (l == w) {
-            forced_v = fm;
-            free_v = frm;
+        int64_t dm, dp;
+        if (MODE == SCAN_SUMMARY) {
+            const Ev e = decode(r.q0[w], r.q1[w], r.q2[w], valid, D.L);
+            if (ballot(e.bad)) err |= 1u;
+            const uint64_t fm = ballot(e.dm >= two_t || e.dm <= -two_t);
+            if (l == w) forced_v = fm;
+            accC += e.dc;
+            if (ballot(e.aux)) any_aux = true;
+            dm = e.dm;
+            dp = e.dp;
+        } else {
+            const uint32_t fl = (uint32_t)r.q2[w];
+            dm = (valid && (fl & 6u) == 0) ? (int64_t)r.q0[w] : 0;
+            dp = (fl & 1u) ? 0 : dm;
+            if (MODE == SCAN_EMIT) {
+                const uint64_t frm = ballot(dm < 0);
+                if (l == w) free_v = frm;
+            }
         }
-        const int64_t sF = wave_incl_sum(e.dm) + cF;
-        const int64_t sP = wave_incl_sum(e.dp) + cP;
+        const int64_t sF = wave_incl_sum(dm) + cF;
+        const int64_t sP = wave_incl_sum(dp) + cP;
         cF = readlane64(sF, 63);
         cP = readlane64(sP, 63);
         F[k] = sF;
-        if (STORE_P) P[k] = sP;
-        if (STORE_PL) PL[k] = q1[w];
-        accC += e.dc;
-        if (ballot(e.aux)) any_aux = true;
-        if (EXT && valid) {
+        P[k] = sP;
+        if (MODE == SCAN_EMIT) PL[k] = r.q1[w];
+        if (MODE == SCAN_SUMMARY && valid) {
             mxF = sF > mxF ? sF : mxF;
             mnF = sF < mnF ? sF : mnF;
             mxP = sP > mxP ? sP : mxP;
@@ -237,8 +269,8 @@ __device__ __forceinline__ void load_segment(const Desc& D, int64_t a, int nv, i
     }
     o.sumF = cF;
     o.sumP = cP;
-    o.sumC = wave_sum(accC);
-    if (EXT) {
+    if (MODE == SCAN_SUMMARY) {
+        o.sumC = wave_sum(accC);
         o.mxF = wave_max(mxF);
         o.mnF = wave_min(mnF);
         o.mxP = wave_max(mxP);
@@ -761,8 +793,10 @@ __global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ de
     const int64_t j = (int64_t)(g - D.seg_begin);
     const int64_t a = j * SEG;
     const int nv = seg_events(D, j);
+    SegRecs rr;
+    fetch_segment(D, a, nv, rr);
     SegScan sc;
-    load_segment<true, false, true>(D, a, nv, lF[wv], lP[wv], nullptr, sc);
+    scan_segment<SCAN_SUMMARY>(D, nv, rr, lF[wv], lP[wv], nullptr, sc);
     const SegMap m = analyse_segment(lF[wv], D.T, sc.forced_v, sc.sumF);
     const ChainRun& r = m.after;
     const int64_t acnt = wave_sum(l < NW ? (int64_t)__popcll(r.mvec) : 0);
@@ -990,10 +1024,8 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         const int64_t T = D.T;
         // lanes 0-4: prefixes, entry and exit from the resolve pass; lanes 5-12: flags
         // and the chain after the first forced sample from the summary pass
-        int64_t pv = 0;
-        if (l < 5) pv = D.seg[(SP_F0 + l) * ns + j];
-        else if (l == 5) pv = D.seg[SP_FLG * ns + j];
-        else if (l < 13) pv = D.seg[(SP_FN + (l - 6)) * ns + j];
+        const int pl_ = l < 5 ? SP_F0 + l : (l == 5 ? SP_FLG : (l < 13 ? SP_FN + (l - 6) : SP_F0));
+        const int64_t pv = seg_val(D, pl_, j);
         const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), C0 = readlane64(pv, 2);
         const int64_t eF = readlane64(pv, 3), xF = readlane64(pv, 4);
         const int64_t flg = readlane64(pv, 5);
@@ -1001,8 +1033,11 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         // From a forced sample on the chain is the one the summary pass followed,
         // so only the events up to it are read again.
         const int fwin = fn >= 0 ? fn >> 6 : NW - 1;
+        const int nlim = fn >= 0 ? fn + 1 : nv;
+        SegRecs rr;
+        fetch_segment(D, a, nlim, rr);
         SegScan sc;
-        load_segment<true, false, false>(D, a, fn >= 0 ? fn + 1 : nv, lF[wv], lP[wv], nullptr, sc, fwin + 1);
+        scan_segment<SCAN_CHAIN>(D, nlim, rr, lF[wv], lP[wv], nullptr, sc, fwin + 1);
         uint32_t err = 0;
 
         // Copy volume (section 3.5: one Tc sample per multiple of Tc crossed by
@@ -1234,6 +1269,129 @@ __global__ __launch_bounds__(TILE) void k_bscan(const Desc* __restrict__ desc, i
 // One wave per segment (grid-stride): write the segment's samples with their
 // attribution, per-line counters, tracked samples and the frees that reclaim
 // them.
+// Emit one segment g of trace t from its fetched records cur, after issuing
+// the fetch of the wave's next segment into nx (its trace index to tn).
+__device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total,
+                                             uint64_t g, uint64_t stride, int t, int& tn, const SegRecs& cur,
+                                             SegRecs& nx, int64_t* lF_, int64_t* lP_, uint64_t* lPL_,
+                                             HistCache& hc) {
+    const int l = lane_id();
+    const Desc& D = desc[t];
+    const int64_t j = (int64_t)(g - D.seg_begin);
+    const int64_t ns = (int64_t)D.nseg;
+    const int64_t a = j * SEG;
+    const int nv = seg_events(D, j);
+    const uint32_t L = D.L;
+    // lanes 0-3: F0, P0, C0 (unused), entry offset; lanes 4-9: state before the segment
+    const int pl_ = l < 4 ? SP_F0 + (l == 3 ? SP_EF - SP_F0 : l) : (l < 10 ? SP_XCNT + (l - 4) : SP_F0);
+    const int64_t pv = seg_val(D, pl_, j);
+    const uint64_t smask_v = ((gu64_t*)D.mask)[j * NW + (l & (NW - 1))];
+    // the next segment's records, before this one's work (past the last
+    // segment, this one's again: no branch, so no wait at a join)
+    const uint64_t gn = g + stride < nseg_total ? g + stride : g;
+    tn = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, t, ntraces, gn));
+    {
+        const Desc& Dn = desc[tn];
+        const int64_t jn = (int64_t)(gn - Dn.seg_begin);
+        fetch_segment(Dn, jn * SEG, seg_events(Dn, jn), nx);
+    }
+    SegScan sc;
+    scan_segment<SCAN_EMIT>(D, nv, cur, lF_, lP_, lPL_, sc);
+    const uint64_t free_v = sc.free_v;
+    const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), eF = readlane64(pv, 3);
+    int64_t base = readlane64(pv, 4);
+    const int64_t hv = readlane64(pv, 5);
+    const uint32_t hidx = (uint32_t)readlane64(pv, 6), hptr = (uint32_t)readlane64(pv, 7);
+    const bool hh = (readlane64(pv, 8) & 1) != 0;
+    const int64_t eP = readlane64(pv, 9);
+    uint32_t err = 0;
+    if (base < 0 || base > (int64_t)D.n) {  // only reachable after an internal fault
+        err |= 8u;
+        base = 0;
+    }
+    int64_t refF = eF, refP = eP - P0;
+    int64_t cnt = 0;
+    bool cur_has = hh;
+    uint32_t cur_ptr = hptr, cur_idx = hidx;
+    int64_t hwm = hh ? hv : 0;
+    for (int w = 0; w < NW; ++w) {
+        const uint64_t m = readlaneu64(smask_v, w);
+        const uint64_t fm = readlaneu64(free_v, w);
+        if (m == 0 && (fm == 0 || !cur_has)) continue;
+        const int k = w * 64 + l;
+        const int64_t f = lF_[k];
+        const int64_t p = lP_[k];
+        const uint64_t plw = lPL_[k];
+        const uint32_t pt = (uint32_t)plw;
+        const uint64_t below = m & lanemask_lt();
+        uint64_t tmask = 0;
+        if (m) {
+            const int pl = below ? top64(below) : l;
+            int64_t fprev = shfl64(f, pl), pprev = shfl64(p, pl);
+            if (!below) {
+                fprev = refF;
+                pprev = refP;
+            }
+            const bool is_s = ((m >> l) & 1) && k < nv;
+            const int64_t dl = f - fprev;
+            const int64_t pyb = p - pprev;
+            const int64_t nat = dl - pyb;
+            const int64_t Fabs = F0 + f;
+            const int64_t rank = base + cnt + __popcll(below);
+            if (is_s && rank < (int64_t)D.n) {
+                const uint32_t ln = (uint32_t)(plw >> 32);
+                Sample smp;
+                smp.event_idx = (uint32_t)(a + k);
+                smp.line = ln;
+                smp.F = Fabs;
+                smp.py = pyb;
+                smp.nat = nat;
+                D.samples[rank] = smp;
+                if (ln < L) {
+                    const bool gr = dl > 0;
+                    hist_add(hc, D, (uint32_t)t, ln, C_PY, pyb, C_NAT, nat, gr ? C_GN : C_SN, 1,
+                             gr ? C_GB : C_SB, gr ? dl : -dl);
+                }
+            }
+            uint64_t cand = ballot(is_s && dl > 0 && Fabs > hwm);
+            while (cand) {
+                const int c = ctz64(cand);
+                cand &= cand - 1;
+                const int64_t Fc = readlane64(Fabs, c);
+                if (Fc > hwm) {
+                    hwm = Fc;
+                    tmask |= 1ull << c;
+                }
+            }
+            if (((tmask >> l) & 1) && rank < (int64_t)D.n) {
+                atomicOr((unsigned long long*)&D.tracked_bits[rank >> 6], 1ull << (rank & 63));
+                D.sample_ptr[rank] = pt;
+            }
+            const int ls = top64(m);
+            refF = readlane64(f, ls);
+            refP = readlane64(p, ls);
+        }
+        if (fm && (cur_has || tmask)) {
+            const uint64_t tb = tmask & lanemask_lt();
+            const int al = tb ? top64(tb) : l;
+            const uint32_t spt = (uint32_t)shfl32((int)pt, al);
+            const uint32_t aptr = tb ? spt : cur_ptr;
+            const uint32_t aidx = tb ? (uint32_t)(a + w * 64 + al) : cur_idx;
+            const bool ahas = tb != 0 || cur_has;
+            if (((fm >> l) & 1) && ahas && pt == aptr && aidx < D.n)
+                atomicOr((unsigned long long*)&D.freed_bits[aidx >> 6], 1ull << (aidx & 63));
+        }
+        if (tmask) {
+            const int tl = top64(tmask);
+            cur_ptr = (uint32_t)readlane32((int)pt, tl);
+            cur_idx = (uint32_t)(a + w * 64 + tl);
+            cur_has = true;
+        }
+        cnt += __popcll(m);
+    }
+    if (err && l == 0) atomicOr(&D.scal->err, err);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
     __shared__ int64_t lF[WAVES][SEG];
     __shared__ int64_t lP[WAVES][SEG];
@@ -1242,117 +1400,29 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, i
     hist_init(hc);
     __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    const int l = lane_id();
-    int cur_t = 0;
-    for (uint64_t g = (uint64_t)blockIdx.x * WAVES + wv; g < nseg_total; g += (uint64_t)gridDim.x * WAVES) {
-        const int t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, cur_t, ntraces, g));
-        cur_t = t;
-        const Desc& D = desc[t];
-        const int64_t j = (int64_t)(g - D.seg_begin);
-        const int64_t ns = (int64_t)D.nseg;
-        const int64_t a = j * SEG;
-        const int nv = seg_events(D, j);
-        const uint32_t L = D.L;
-        SegScan sc;
-        load_segment<true, true, false>(D, a, nv, lF[wv], lP[wv], lPL[wv], sc);
-        int64_t pv = 0;
-        if (l < 3) pv = D.seg[(SP_F0 + l) * ns + j];  // F0, P0 (C0 unused)
-        else if (l == 3) pv = D.seg[SP_EF * ns + j];
-        else if (l < 10) pv = D.seg[(SP_XCNT + (l - 4)) * ns + j];
-        const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), eF = readlane64(pv, 3);
-        int64_t base = readlane64(pv, 4);
-        const int64_t hv = readlane64(pv, 5);
-        const uint32_t hidx = (uint32_t)readlane64(pv, 6), hptr = (uint32_t)readlane64(pv, 7);
-        const bool hh = (readlane64(pv, 8) & 1) != 0;
-        const int64_t eP = readlane64(pv, 9);
-        const uint64_t smask_v = l < NW ? D.mask[j * NW + l] : 0;
-        const uint64_t free_v = sc.free_v;
-        uint32_t err = 0;
-        if (base < 0 || base > (int64_t)D.n) {  // only reachable after an internal fault
-            err |= 8u;
-            base = 0;
-        }
-        int64_t refF = eF, refP = eP - P0;
-        int64_t cnt = 0;
-        bool cur_has = hh;
-        uint32_t cur_ptr = hptr, cur_idx = hidx;
-        int64_t hwm = hh ? hv : 0;
-        for (int w = 0; w < NW; ++w) {
-            const uint64_t m = readlaneu64(smask_v, w);
-            const uint64_t fm = readlaneu64(free_v, w);
-            if (m == 0 && (fm == 0 || !cur_has)) continue;
-            const int k = w * 64 + l;
-            const int64_t f = lF[wv][k];
-            const int64_t p = lP[wv][k];
-            const uint64_t plw = lPL[wv][k];
-            const uint32_t pt = (uint32_t)plw;
-            const uint64_t below = m & lanemask_lt();
-            uint64_t tmask = 0;
-            if (m) {
-                const int pl = below ? top64(below) : l;
-                int64_t fprev = shfl64(f, pl), pprev = shfl64(p, pl);
-                if (!below) {
-                    fprev = refF;
-                    pprev = refP;
-                }
-                const bool is_s = ((m >> l) & 1) && k < nv;
-                const int64_t dl = f - fprev;
-                const int64_t pyb = p - pprev;
-                const int64_t nat = dl - pyb;
-                const int64_t Fabs = F0 + f;
-                const int64_t rank = base + cnt + __popcll(below);
-                if (is_s && rank < (int64_t)D.n) {
-                    const uint32_t ln = (uint32_t)(plw >> 32);
-                    Sample smp;
-                    smp.event_idx = (uint32_t)(a + k);
-                    smp.line = ln;
-                    smp.F = Fabs;
-                    smp.py = pyb;
-                    smp.nat = nat;
-                    D.samples[rank] = smp;
-                    if (ln < L) {
-                        const bool gr = dl > 0;
-                        hist_add(hc, D, (uint32_t)t, ln, C_PY, pyb, C_NAT, nat, gr ? C_GN : C_SN, 1,
-                                 gr ? C_GB : C_SB, gr ? dl : -dl);
-                    }
-                }
-                uint64_t cand = ballot(is_s && dl > 0 && Fabs > hwm);
-                while (cand) {
-                    const int c = ctz64(cand);
-                    cand &= cand - 1;
-                    const int64_t Fc = readlane64(Fabs, c);
-                    if (Fc > hwm) {
-                        hwm = Fc;
-                        tmask |= 1ull << c;
-                    }
-                }
-                if (((tmask >> l) & 1) && rank < (int64_t)D.n) {
-                    atomicOr((unsigned long long*)&D.tracked_bits[rank >> 6], 1ull << (rank & 63));
-                    D.sample_ptr[rank] = pt;
-                }
-                const int ls = top64(m);
-                refF = readlane64(f, ls);
-                refP = readlane64(p, ls);
-            }
-            if (fm && (cur_has || tmask)) {
-                const uint64_t tb = tmask & lanemask_lt();
-                const int al = tb ? top64(tb) : l;
-                const uint32_t spt = (uint32_t)shfl32((int)pt, al);
-                const uint32_t aptr = tb ? spt : cur_ptr;
-                const uint32_t aidx = tb ? (uint32_t)(a + w * 64 + al) : cur_idx;
-                const bool ahas = tb != 0 || cur_has;
-                if (((fm >> l) & 1) && ahas && pt == aptr && aidx < D.n)
-                    atomicOr((unsigned long long*)&D.freed_bits[aidx >> 6], 1ull << (aidx & 63));
-            }
-            if (tmask) {
-                const int tl = top64(tmask);
-                cur_ptr = (uint32_t)readlane32((int)pt, tl);
-                cur_idx = (uint32_t)(a + w * 64 + tl);
-                cur_has = true;
-            }
-            cnt += __popcll(m);
-        }
-        if (err && l == 0) atomicOr(&D.scal->err, err);
+    // Segments are taken grid-stride.  Each wave fetches the records of its
+    // next segment before it works on the current one, alternating between
+    // two register buffers.
+    const uint64_t stride = (uint64_t)gridDim.x * WAVES;
+    uint64_t g = (uint64_t)blockIdx.x * WAVES + wv;
+    int t = 0, tn = 0;
+    SegRecs ra, rb;
+    if (g < nseg_total) {
+        t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g));
+        const Desc& D0 = desc[t];
+        const int64_t j0 = (int64_t)(g - D0.seg_begin);
+        fetch_segment(D0, j0 * SEG, seg_events(D0, j0), ra);
+    }
+    for (;;) {
+        if (g >= nseg_total) break;
+        tn = t;
+        emit_segment(desc, ntraces, nseg_total, g, stride, t, tn, ra, rb, lF[wv], lP[wv], lPL[wv], hc);
+        g += stride;
+        t = tn;
+        if (g >= nseg_total) break;
+        emit_segment(desc, ntraces, nseg_total, g, stride, t, tn, rb, ra, lF[wv], lP[wv], lPL[wv], hc);
+        g += stride;
+        t = tn;
     }
     __syncthreads();
     hist_flush(hc, desc);
