@@ -16,6 +16,7 @@ timed on the host as a baseline.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +32,29 @@ BYTES_PER_EVENT = 24
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` on this workload, from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated against a
+    plain copy), or None if that summary was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "config2_hbm_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    kv = {}
+    for line in text.splitlines():
+        key, sep, val = line.partition(": ")
+        if sep and key in ("kernel", "traffic_bytes_per_launch", "kernel_sources_sha256"):
+            kv[key] = val.strip()
+    h = hashlib.sha256()
+    for f in ("sampler_kernels.hip", "sampler_device.h"):
+        with open(os.path.join(ROOT, "paper_2212_07597_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if kv.get("kernel") != kernel or kv.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    return int(kv["traffic_bytes_per_launch"])
 
 
 def main():
@@ -155,7 +179,9 @@ def main():
                    "kernel_ms": round(main_ms, 4), "launch_sequence_ms": round(launch_ms, 4),
                    "pass_ms": {k: round(v, 4) for k, v in passes.items()}},
         "roofline": {"bound": "hbm", "kernel": "k_" + dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("k_" + dominant), "traffic_unit": "HBM bytes per launch",
+                     "algorithmic_bytes": BYTES_PER_EVENT * n},
         "cpu_baseline": cpu,
     }
     out.update(extras)
