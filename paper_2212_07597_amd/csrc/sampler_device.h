@@ -17,7 +17,8 @@ constexpr int WAVES = 4;                 // wavefronts per workgroup of the per-
 constexpr int BLOCK = 64 * WAVES;
 constexpr int TILE = 1024;               // segments per tile
 constexpr int TWAVES = TILE / 64;
-constexpr int NSLOT = 32;                // LDS histogram cache slots per workgroup
+constexpr int CHAIN_SLOTS = 32;          // LDS histogram cache slots per workgroup: chain pass (copy, timer)
+constexpr int EMIT_SLOTS = 128;          // and emit pass (samples)
 constexpr int NCNT = 10;                 // counters cached per slot
 constexpr int CHAIN_CAP = 32;            // chains followed by the all-entry analysis
 

@@ -49,15 +49,18 @@ __device__ __forceinline__ int cache_to_hist(int c) {
     }
 }
 
+// Per-workgroup LDS cache of per-line counters, NS slots (a power of two <= 256).
+template <int NS>
 struct HistCache {
-    unsigned long long key[NSLOT];  // (trace << 32) | line, or ~0 when empty
-    unsigned long long cnt[NSLOT][NCNT];
+    unsigned long long key[NS];  // (trace << 32) | line, or ~0 when empty
+    unsigned long long cnt[NS][NCNT];
 };
 
 constexpr unsigned long long EMPTY_KEY = ~0ull;
 
-__device__ __forceinline__ void hist_init(HistCache& hc) {
-    for (int i = threadIdx.x; i < NSLOT; i += blockDim.x) {
+template <int NS>
+__device__ __forceinline__ void hist_init(HistCache<NS>& hc) {
+    for (int i = threadIdx.x; i < NS; i += blockDim.x) {
         hc.key[i] = EMPTY_KEY;
         for (int c = 0; c < NCNT; ++c) hc.cnt[i][c] = 0;
     }
@@ -65,11 +68,12 @@ __device__ __forceinline__ void hist_init(HistCache& hc) {
 
 // Add up to four counters of (trace t, line) through the workgroup's LDS
 // cache; a slot held by another line sends the update to global atomics.
-__device__ __forceinline__ void hist_add(HistCache& hc, const Desc& D, uint32_t t, uint32_t line, int c0, int64_t v0,
-                                         int c1, int64_t v1, int c2, int64_t v2, int c3, int64_t v3) {
+template <int NS>
+__device__ __forceinline__ void hist_add(HistCache<NS>& hc, const Desc& D, uint32_t t, uint32_t line, int c0,
+                                         int64_t v0, int c1, int64_t v1, int c2, int64_t v2, int c3, int64_t v3) {
     const unsigned long long key = ((unsigned long long)t << 32) | line;
     const uint32_t h = (line * 2654435761u) ^ (t * 0x9E3779B9u);
-    const int slot = (int)(h >> (32 - 7)) & (NSLOT - 1);
+    const int slot = (int)(h >> 24) & (NS - 1);
     unsigned long long k = hc.key[slot];
     if (k == EMPTY_KEY) k = atomicCAS(&hc.key[slot], EMPTY_KEY, key);
     const int cs[4] = {c0, c1, c2, c3};
@@ -88,8 +92,9 @@ __device__ __forceinline__ void hist_add(HistCache& hc, const Desc& D, uint32_t 
 }
 
 // Move the cache to the per-line histograms (whole workgroup, after a barrier).
-__device__ __forceinline__ void hist_flush(HistCache& hc, const Desc* desc) {
-    for (int i = threadIdx.x; i < NSLOT; i += blockDim.x) {
+template <int NS>
+__device__ __forceinline__ void hist_flush(HistCache<NS>& hc, const Desc* desc) {
+    for (int i = threadIdx.x; i < NS; i += blockDim.x) {
         const unsigned long long key = hc.key[i];
         if (key == EMPTY_KEY) continue;
         const Desc& D = desc[(uint32_t)(key >> 32)];
@@ -779,28 +784,20 @@ __device__ bool scan_last_sample(const StatusView& sv, int64_t g, int64_t& oP, u
 
 // ------------------------------------------------------------ summary pass
 
-// One wave per segment: sums, extremes of the relative prefixes and the
-// segment's chain map.
-__global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ desc, int ntraces,
-                                                     uint64_t nseg_total) {
-    __shared__ int64_t lF[WAVES][SEG];
-    __shared__ int64_t lP[WAVES][SEG];
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+// Sums, extremes of the relative prefixes and the chain map of segment g.
+__device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int64_t* lF_, int64_t* lP_) {
     const int l = lane_id();
-    const uint64_t g = (uint64_t)blockIdx.x * WAVES + wv;
-    if (g >= nseg_total) return;
-    const Desc& D = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g))];
     const int64_t j = (int64_t)(g - D.seg_begin);
     const int64_t a = j * SEG;
     const int nv = seg_events(D, j);
     SegRecs rr;
     fetch_segment(D, a, nv, rr);
     SegScan sc;
-    scan_segment<SCAN_SUMMARY>(D, nv, rr, lF[wv], lP[wv], nullptr, sc);
-    const SegMap m = analyse_segment(lF[wv], D.T, sc.forced_v, sc.sumF);
+    scan_segment<SCAN_SUMMARY>(D, nv, rr, lF_, lP_, nullptr, sc);
+    const SegMap m = analyse_segment(lF_, D.T, sc.forced_v, sc.sumF);
     const ChainRun& r = m.after;
     const int64_t acnt = wave_sum(l < NW ? (int64_t)__popcll(r.mvec) : 0);
-    const int64_t alp = r.lastS >= 0 ? lP[wv][r.lastS] : 0;
+    const int64_t alp = r.lastS >= 0 ? lP_[r.lastS] : 0;
     if (l <= SP_ALP) {
         int64_t v;
         switch (l) {
@@ -827,6 +824,19 @@ __global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ de
     }
     if (m.fnode >= 0 && l < NW) D.mask[j * NW + l] = r.mvec;
     if (sc.err && l == 0) atomicOr(&D.scal->err, sc.err);
+}
+
+// One wave per segment, one launch wave per segment (measured faster here
+// than a grid-stride loop: the hardware starts a new wave's loads while
+// others compute).
+__global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ desc, int ntraces,
+                                                     uint64_t nseg_total) {
+    __shared__ int64_t lF[WAVES][SEG];
+    __shared__ int64_t lP[WAVES][SEG];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const uint64_t g = (uint64_t)blockIdx.x * WAVES + wv;
+    if (g >= nseg_total) return;
+    summarize_segment(desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g))], g, lF[wv], lP[wv]);
 }
 
 // ------------------------------------------------------------ resolve pass
@@ -1001,7 +1011,7 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
 __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
     __shared__ int64_t lF[WAVES][SEG];
     __shared__ int64_t lP[WAVES][SEG];
-    __shared__ HistCache hc;
+    __shared__ HistCache<CHAIN_SLOTS> hc;
     hist_init(hc);
     __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -1269,12 +1279,29 @@ __global__ __launch_bounds__(TILE) void k_bscan(const Desc* __restrict__ desc, i
 // One wave per segment (grid-stride): write the segment's samples with their
 // attribution, per-line counters, tracked samples and the frees that reclaim
 // them.
+constexpr int STAGE = 128;  // staged sample records per wave
+
+// Write staged samples [0, cnt) (cnt <= 64) to ranks r0.. and add them to
+// their lines' counters, one sample per lane.
+__device__ __forceinline__ void flush_stage(const Desc& D, uint32_t t, const Sample* stg, int cnt, int64_t r0,
+                                            HistCache<EMIT_SLOTS>& hc) {
+    const int l = lane_id();
+    if (l < cnt && r0 + l < (int64_t)D.n) {
+        const Sample smp = stg[l];
+        D.samples[r0 + l] = smp;
+        if (smp.line < D.L) {
+            const int64_t dl = smp.py + smp.nat;
+            const bool gr = dl > 0;
+            hist_add(hc, D, t, smp.line, C_PY, smp.py, C_NAT, smp.nat, gr ? C_GN : C_SN, 1, gr ? C_GB : C_SB,
+                     gr ? dl : -dl);
+        }
+    }
+}
+
 // Emit one segment g of trace t from its fetched records cur, after issuing
 // the fetch of the wave's next segment into nx (its trace index to tn).
-__device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total,
-                                             uint64_t g, uint64_t stride, int t, int& tn, const SegRecs& cur,
-                                             SegRecs& nx, int64_t* lF_, int64_t* lP_, uint64_t* lPL_,
-                                             HistCache& hc) {
+__device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, uint64_t g, int t,
+                                             HistCache<EMIT_SLOTS>& hc, Sample* stg) {
     const int l = lane_id();
     const Desc& D = desc[t];
     const int64_t j = (int64_t)(g - D.seg_begin);
@@ -1286,18 +1313,8 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, int 
     const int pl_ = l < 4 ? SP_F0 + (l == 3 ? SP_EF - SP_F0 : l) : (l < 10 ? SP_XCNT + (l - 4) : SP_F0);
     const int64_t pv = seg_val(D, pl_, j);
     const uint64_t smask_v = ((gu64_t*)D.mask)[j * NW + (l & (NW - 1))];
-    // the next segment's records, before this one's work (past the last
-    // segment, this one's again: no branch, so no wait at a join)
-    const uint64_t gn = g + stride < nseg_total ? g + stride : g;
-    tn = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, t, ntraces, gn));
-    {
-        const Desc& Dn = desc[tn];
-        const int64_t jn = (int64_t)(gn - Dn.seg_begin);
-        fetch_segment(Dn, jn * SEG, seg_events(Dn, jn), nx);
-    }
-    SegScan sc;
-    scan_segment<SCAN_EMIT>(D, nv, cur, lF_, lP_, lPL_, sc);
-    const uint64_t free_v = sc.free_v;
+    SegRecs cur;
+    fetch_segment(D, a, nv, cur);
     const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), eF = readlane64(pv, 3);
     int64_t base = readlane64(pv, 4);
     const int64_t hv = readlane64(pv, 5);
@@ -1314,14 +1331,27 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, int 
     bool cur_has = hh;
     uint32_t cur_ptr = hptr, cur_idx = hidx;
     int64_t hwm = hh ? hv : 0;
+    int64_t cF = 0, cP = 0;
+    // Sample records are staged in LDS in rank order and written (with their
+    // per-line counters) 64 at a time, all lanes busy.
+    int staged = 0;
+    int64_t stage_rank = base;
+    // Window by window: decode and scan (prefixes stay in registers), then
+    // the window's samples and frees.
+#pragma unroll
     for (int w = 0; w < NW; ++w) {
-        const uint64_t m = readlaneu64(smask_v, w);
-        const uint64_t fm = readlaneu64(free_v, w);
-        if (m == 0 && (fm == 0 || !cur_has)) continue;
         const int k = w * 64 + l;
-        const int64_t f = lF_[k];
-        const int64_t p = lP_[k];
-        const uint64_t plw = lPL_[k];
+        const uint32_t fl = (uint32_t)cur.q2[w];
+        const int64_t dm = (k < nv && (fl & 6u) == 0) ? (int64_t)cur.q0[w] : 0;
+        const int64_t dp = (fl & 1u) ? 0 : dm;
+        const int64_t f = wave_incl_sum(dm) + cF;
+        const int64_t p = wave_incl_sum(dp) + cP;
+        cF = readlane64(f, 63);
+        cP = readlane64(p, 63);
+        const uint64_t fm = ballot(dm < 0);
+        const uint64_t m = readlaneu64(smask_v, w);
+        if (m == 0 && (fm == 0 || !cur_has)) continue;
+        const uint64_t plw = cur.q1[w];
         const uint32_t pt = (uint32_t)plw;
         const uint64_t below = m & lanemask_lt();
         uint64_t tmask = 0;
@@ -1338,20 +1368,14 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, int 
             const int64_t nat = dl - pyb;
             const int64_t Fabs = F0 + f;
             const int64_t rank = base + cnt + __popcll(below);
-            if (is_s && rank < (int64_t)D.n) {
-                const uint32_t ln = (uint32_t)(plw >> 32);
+            if (is_s) {
                 Sample smp;
                 smp.event_idx = (uint32_t)(a + k);
-                smp.line = ln;
+                smp.line = (uint32_t)(plw >> 32);
                 smp.F = Fabs;
                 smp.py = pyb;
                 smp.nat = nat;
-                D.samples[rank] = smp;
-                if (ln < L) {
-                    const bool gr = dl > 0;
-                    hist_add(hc, D, (uint32_t)t, ln, C_PY, pyb, C_NAT, nat, gr ? C_GN : C_SN, 1,
-                             gr ? C_GB : C_SB, gr ? dl : -dl);
-                }
+                stg[staged + __popcll(below)] = smp;
             }
             uint64_t cand = ballot(is_s && dl > 0 && Fabs > hwm);
             while (cand) {
@@ -1388,41 +1412,31 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, int 
             cur_has = true;
         }
         cnt += __popcll(m);
+        staged += __popcll(m);
+        if (staged >= 64) {
+            flush_stage(D, (uint32_t)t, stg, 64, stage_rank, hc);
+            stage_rank += 64;
+            staged -= 64;
+            Sample rest;
+            if (l < staged) rest = stg[64 + l];
+            if (l < staged) stg[l] = rest;
+        }
     }
+    if (staged) flush_stage(D, (uint32_t)t, stg, staged, stage_rank, hc);
     if (err && l == 0) atomicOr(&D.scal->err, err);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
-    __shared__ int64_t lF[WAVES][SEG];
-    __shared__ int64_t lP[WAVES][SEG];
-    __shared__ uint64_t lPL[WAVES][SEG];
-    __shared__ HistCache hc;
+    __shared__ HistCache<EMIT_SLOTS> hc;
+    __shared__ Sample stage[WAVES][STAGE];
     hist_init(hc);
     __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    // Segments are taken grid-stride.  Each wave fetches the records of its
-    // next segment before it works on the current one, alternating between
-    // two register buffers.
-    const uint64_t stride = (uint64_t)gridDim.x * WAVES;
-    uint64_t g = (uint64_t)blockIdx.x * WAVES + wv;
-    int t = 0, tn = 0;
-    SegRecs ra, rb;
-    if (g < nseg_total) {
-        t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g));
-        const Desc& D0 = desc[t];
-        const int64_t j0 = (int64_t)(g - D0.seg_begin);
-        fetch_segment(D0, j0 * SEG, seg_events(D0, j0), ra);
-    }
-    for (;;) {
-        if (g >= nseg_total) break;
-        tn = t;
-        emit_segment(desc, ntraces, nseg_total, g, stride, t, tn, ra, rb, lF[wv], lP[wv], lPL[wv], hc);
-        g += stride;
-        t = tn;
-        if (g >= nseg_total) break;
-        emit_segment(desc, ntraces, nseg_total, g, stride, t, tn, rb, ra, lF[wv], lP[wv], lPL[wv], hc);
-        g += stride;
-        t = tn;
+    // Segments are taken grid-stride (consecutive waves, consecutive segments).
+    int t = 0;
+    for (uint64_t g = (uint64_t)blockIdx.x * WAVES + wv; g < nseg_total; g += (uint64_t)gridDim.x * WAVES) {
+        t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, t, ntraces, g));
+        emit_segment(desc, g, t, hc, stage[wv]);
     }
     __syncthreads();
     hist_flush(hc, desc);
