@@ -41,9 +41,9 @@ enum {
     // bit 2 = copy or timer events present), and the chain after the first forced sample, which is
     // the same for every entry: its node (-1 if none), samples after it, best growth sample after
     // it (value, node or -1), largest sampled footprint after it, last sample node after it (or -1)
-    // and the Python footprint there (relative values)
+    // and the Python footprint there (relative values), and the forced window's sample mask after it
     SP_AF = 0, SP_AP, SP_AC, SP_MXF, SP_MNF, SP_MXP, SP_MNP, SP_LO, SP_HI, SP_KF, SP_FLG,
-    SP_FN, SP_ACNT, SP_AGV, SP_AGN, SP_ASMX, SP_ALS, SP_ALP,
+    SP_FN, SP_ACNT, SP_AGV, SP_AGN, SP_ASMX, SP_ALS, SP_ALP, SP_AMF,
     // resolve pass: exclusive prefixes, entry and exit offsets of the chain
     SP_F0, SP_P0, SP_C0, SP_EF, SP_XF,
     // chain pass: samples, best growth sample (value, event, ptr), Python footprint at the last sample, flags

@@ -176,10 +176,10 @@ __device__ __forceinline__ int64_t seg_val(const Desc& D, int p, int64_t j) {
     return ((gi64_t*)D.seg)[(int64_t)p * (int64_t)D.nseg + j];
 }
 
+// What the summary pass takes from a segment's records.
 struct SegScan {
     int64_t sumF, sumP, sumC;
-    int64_t mxF, mnF, mxP, mnP;  // extremes of the relative prefixes (EXT only)
-    uint64_t forced_v, free_v;   // lane w < NW: event masks of window w
+    int64_t mxF, mnF, mxP, mnP;  // extremes of the relative prefixes
     bool any_aux;
     uint32_t err;
 };
@@ -211,82 +211,6 @@ __device__ __forceinline__ void fetch_segment(const Desc& D, int64_t a, int nv, 
     __builtin_amdgcn_sched_barrier(0);
 }
 
-// What a pass takes from a segment's records.
-enum ScanMode {
-    SCAN_SUMMARY,  // validate; forced events; copy/timer presence; sums; extremes
-    SCAN_CHAIN,    // footprint and Python footprint prefixes
-    SCAN_EMIT,     // the same, plus (line << 32 | ptr id) and the frees
-};
-
-// Decode and scan the first nwin windows of a fetched segment of nv events;
-// the relative prefixes (after each event, segment start = 0) go to F and P,
-// record words to PL.  Only the summary pass validates records: a malformed
-// event fails the whole trace, so the other passes decode memory deltas
-// without range checks and never index memory with unchecked fields.
-template <int MODE>
-__device__ __forceinline__ void scan_segment(const Desc& D, int nv, const SegRecs& r, int64_t* F, int64_t* P,
-                                             uint64_t* PL, SegScan& o, int nwin = NW) {
-    const int l = lane_id();
-    int64_t cF = 0, cP = 0, accC = 0;
-    int64_t mxF = INT64_MIN, mnF = INT64_MAX, mxP = INT64_MIN, mnP = INT64_MAX;
-    uint64_t forced_v = 0, free_v = 0;
-    bool any_aux = false;
-    uint32_t err = 0;
-    // |delta| >= 2T-1 samples whatever the reference was
-    const int64_t two_t = 2 * D.T - 1;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        if (w >= nwin) break;
-        const int k = w * 64 + l;
-        const bool valid = k < nv;
-        int64_t dm, dp;
-        if (MODE == SCAN_SUMMARY) {
-            const Ev e = decode(r.q0[w], r.q1[w], r.q2[w], valid, D.L);
-            if (ballot(e.bad)) err |= 1u;
-            const uint64_t fm = ballot(e.dm >= two_t || e.dm <= -two_t);
-            if (l == w) forced_v = fm;
-            accC += e.dc;
-            if (ballot(e.aux)) any_aux = true;
-            dm = e.dm;
-            dp = e.dp;
-        } else {
-            const uint32_t fl = (uint32_t)r.q2[w];
-            dm = (valid && (fl & 6u) == 0) ? (int64_t)r.q0[w] : 0;
-            dp = (fl & 1u) ? 0 : dm;
-            if (MODE == SCAN_EMIT) {
-                const uint64_t frm = ballot(dm < 0);
-                if (l == w) free_v = frm;
-            }
-        }
-        const int64_t sF = wave_incl_sum(dm) + cF;
-        const int64_t sP = wave_incl_sum(dp) + cP;
-        cF = readlane64(sF, 63);
-        cP = readlane64(sP, 63);
-        F[k] = sF;
-        P[k] = sP;
-        if (MODE == SCAN_EMIT) PL[k] = r.q1[w];
-        if (MODE == SCAN_SUMMARY && valid) {
-            mxF = sF > mxF ? sF : mxF;
-            mnF = sF < mnF ? sF : mnF;
-            mxP = sP > mxP ? sP : mxP;
-            mnP = sP < mnP ? sP : mnP;
-        }
-    }
-    o.sumF = cF;
-    o.sumP = cP;
-    if (MODE == SCAN_SUMMARY) {
-        o.sumC = wave_sum(accC);
-        o.mxF = wave_max(mxF);
-        o.mnF = wave_min(mnF);
-        o.mxP = wave_max(mxP);
-        o.mnP = wave_min(mnP);
-    }
-    o.forced_v = forced_v;
-    o.free_v = free_v;
-    o.any_aux = any_aux;
-    o.err = err;
-}
-
 __device__ __forceinline__ int seg_events(const Desc& D, int64_t j) {
     const uint64_t a = (uint64_t)j * SEG;
     return (int)((D.n - a) < (uint64_t)SEG ? (D.n - a) : (uint64_t)SEG);
@@ -306,34 +230,37 @@ struct ChainRun {
     int lastS;
 };
 
-// Follow cr from window w0 (after lane st0) through window wend, sampling
-// wherever the footprint is at least T away from the reference (section 3.2).
+// Advance cr through one window whose footprint prefixes f (and Python
+// footprint prefixes p) are in registers, after lane st.  FULL also records
+// the window's sample mask (lane w), the best growth sample, the largest
+// sampled footprint, the last sample node and, in lsp, the Python footprint
+// at the last sample.
 template <bool FULL>
-__device__ void run_chain(const int64_t* F, int64_t T, ChainRun& cr, int w0, int st0, int wend = NW - 1) {
+__device__ __forceinline__ void chain_window(int64_t f, int64_t p, int64_t T, ChainRun& cr, int64_t& lsp, int w,
+                                             int st) {
     const int l = lane_id();
-    for (int w = w0; w <= wend; ++w) {
-        const int64_t f = F[w * 64 + l];
-        int stl = w == w0 ? st0 : -1;
-        uint64_t m = 0;
-        for (;;) {
-            const int64_t d = f - cr.ref;
-            const uint64_t ex = ballot(l > stl && (d >= T || d <= -T));
-            if (!ex) break;
-            const int jj = ctz64(ex);
-            const int64_t fj = readlane64(f, jj);
-            if (FULL) {
-                if (fj > cr.ref && (cr.gnode < 0 || fj > cr.gbest)) {
-                    cr.gbest = fj;
-                    cr.gnode = w * 64 + jj;
-                }
-                if (fj > cr.smax) cr.smax = fj;
-                m |= 1ull << jj;
-                cr.lastS = w * 64 + jj;
+    uint64_t m = 0;
+    for (;;) {
+        const int64_t d = f - cr.ref;
+        const uint64_t ex = ballot(l > st && (d >= T || d <= -T));
+        if (!ex) break;
+        const int jj = ctz64(ex);
+        const int64_t fj = readlane64(f, jj);
+        if (FULL) {
+            if (fj > cr.ref && (cr.gnode < 0 || fj > cr.gbest)) {
+                cr.gbest = fj;
+                cr.gnode = w * 64 + jj;
             }
-            cr.ref = fj;
-            stl = jj;
+            if (fj > cr.smax) cr.smax = fj;
+            m |= 1ull << jj;
+            cr.lastS = w * 64 + jj;
         }
-        if (FULL && l == w) cr.mvec |= m;
+        cr.ref = fj;
+        st = jj;
+    }
+    if (FULL && m) {
+        lsp = readlane64(p, top64(m));
+        if (l == w) cr.mvec |= m;
     }
 }
 
@@ -357,30 +284,14 @@ __device__ __forceinline__ bool follow(int64_t f, int64_t T, int64_t& ref, int s
 struct SegMap {
     int64_t lo, hi, kf;
     int kind;
-    int fnode;     // first forced event (-1 if none)
-    ChainRun after;  // the chain after it (samples strictly after fnode)
+    int fnode;  // first forced event (-1 if none)
 };
 
-// All-entry analysis of one segment (F: relative prefixes in LDS).
-__device__ SegMap analyse_segment(const int64_t* F, int64_t T, uint64_t forced_v, int64_t sumF) {
+// All-entry analysis of a segment without forced events (F: relative
+// prefixes in LDS).
+__device__ SegMap analyse_segment(const int64_t* F, int64_t T, int64_t sumF) {
     const int l = lane_id();
     SegMap m;
-    // An event with |delta| >= 2T-1 samples for every entry state, so the
-    // chain from the first such event onwards is the same for all entries.
-    const uint64_t wf = ballot(l < NW && forced_v != 0);
-    if (wf) {
-        const int fwin = ctz64(wf);
-        const int flane = ctz64(readlaneu64(forced_v, fwin));
-        ChainRun r{readlane64(F[fwin * 64 + l], flane), 0, 0, -1, INT64_MIN, -1};
-        run_chain<true>(F, T, r, fwin, flane);
-        m.lo = 1;
-        m.hi = 0;
-        m.kf = r.ref - sumF;
-        m.kind = MAP_TOTAL;
-        m.fnode = fwin * 64 + flane;
-        m.after = r;
-        return m;
-    }
     // Entries in [Lo, Hi] have not sampled yet; chain c (lane c < nch) holds
     // the reference of one distinct chain of the entries that have.
     int64_t Lo = -T + 1, Hi = T - 1;
@@ -445,7 +356,6 @@ __device__ SegMap analyse_segment(const int64_t* F, int64_t T, uint64_t forced_v
     if (Hi < -T) Hi = -T;
     const bool has_const = !ovf && nch == 1;
     m.fnode = -1;
-    m.after = ChainRun{0, 0, 0, -1, INT64_MIN, -1};
     m.lo = Lo;
     m.hi = Hi;
     m.kf = has_const ? readlane64(chref, 0) - sumF : 0;
@@ -785,20 +695,79 @@ __device__ bool scan_last_sample(const StatusView& sv, int64_t g, int64_t& oP, u
 // ------------------------------------------------------------ summary pass
 
 // Sums, extremes of the relative prefixes and the chain map of segment g.
-__device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int64_t* lF_, int64_t* lP_) {
+// An event with |delta| >= 2T-1 samples for every entry state, so from the
+// first such event on the chain is the same for all entries: it is followed
+// here, window by window while scanning, with its samples recorded for the
+// chain and emit passes.  Segments without one get the all-entry analysis
+// over the prefixes kept in LDS.
+__device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int64_t* lF_) {
     const int l = lane_id();
     const int64_t j = (int64_t)(g - D.seg_begin);
     const int64_t a = j * SEG;
     const int nv = seg_events(D, j);
     SegRecs rr;
     fetch_segment(D, a, nv, rr);
+    const int64_t T = D.T;
+    const int64_t two_t = 2 * T - 1;
+    int64_t cF = 0, cP = 0, accC = 0;
+    int64_t mxF = INT64_MIN, mnF = INT64_MAX, mxP = INT64_MIN, mnP = INT64_MAX;
+    bool any_aux = false;
+    uint32_t err = 0;
+    int fnode = -1;
+    ChainRun r{0, 0, 0, -1, INT64_MIN, -1};
+    int64_t alp = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const int k = w * 64 + l;
+        const bool valid = k < nv;
+        const Ev e = decode(rr.q0[w], rr.q1[w], rr.q2[w], valid, D.L);
+        if (ballot(e.bad)) err |= 1u;
+        const uint64_t fm = ballot(e.dm >= two_t || e.dm <= -two_t);
+        accC += e.dc;
+        if (ballot(e.aux)) any_aux = true;
+        const int64_t f = wave_incl_sum(e.dm) + cF;
+        const int64_t p = wave_incl_sum(e.dp) + cP;
+        cF = readlane64(f, 63);
+        cP = readlane64(p, 63);
+        lF_[k] = f;
+        if (valid) {
+            mxF = f > mxF ? f : mxF;
+            mnF = f < mnF ? f : mnF;
+            mxP = p > mxP ? p : mxP;
+            mnP = p < mnP ? p : mnP;
+        }
+        if (fnode >= 0) {
+            chain_window<true>(f, p, T, r, alp, w, -1);
+        } else if (fm) {
+            const int fl = ctz64(fm);
+            fnode = w * 64 + fl;
+            r.ref = readlane64(f, fl);
+            chain_window<true>(f, p, T, r, alp, w, fl);
+        }
+    }
     SegScan sc;
-    scan_segment<SCAN_SUMMARY>(D, nv, rr, lF_, lP_, nullptr, sc);
-    const SegMap m = analyse_segment(lF_, D.T, sc.forced_v, sc.sumF);
-    const ChainRun& r = m.after;
+    sc.sumF = cF;
+    sc.sumP = cP;
+    sc.sumC = wave_sum(accC);
+    sc.mxF = wave_max(mxF);
+    sc.mnF = wave_min(mnF);
+    sc.mxP = wave_max(mxP);
+    sc.mnP = wave_min(mnP);
+    sc.any_aux = any_aux;
+    sc.err = err;
+    SegMap m;
+    if (fnode >= 0) {
+        m.lo = 1;
+        m.hi = 0;
+        m.kf = r.ref - cF;
+        m.kind = MAP_TOTAL;
+        m.fnode = fnode;
+    } else {
+        m = analyse_segment(lF_, T, cF);
+    }
     const int64_t acnt = wave_sum(l < NW ? (int64_t)__popcll(r.mvec) : 0);
-    const int64_t alp = r.lastS >= 0 ? lP_[r.lastS] : 0;
-    if (l <= SP_ALP) {
+    const int64_t amf = fnode >= 0 ? (int64_t)readlaneu64(r.mvec, fnode >> 6) : 0;
+    if (l <= SP_AMF) {
         int64_t v;
         switch (l) {
             case SP_AF: v = sc.sumF; break;
@@ -818,11 +787,12 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
             case SP_AGN: v = r.gnode; break;
             case SP_ASMX: v = r.smax; break;
             case SP_ALS: v = r.lastS; break;
-            default: v = alp; break;
+            case SP_ALP: v = r.lastS >= 0 ? alp : 0; break;
+            default: v = amf; break;
         }
         D.seg[(int64_t)l * (int64_t)D.nseg + j] = v;
     }
-    if (m.fnode >= 0 && l < NW) D.mask[j * NW + l] = r.mvec;
+    if (fnode >= 0 && l < NW) D.mask[j * NW + l] = r.mvec;
     if (sc.err && l == 0) atomicOr(&D.scal->err, sc.err);
 }
 
@@ -832,11 +802,10 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
 __global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ desc, int ntraces,
                                                      uint64_t nseg_total) {
     __shared__ int64_t lF[WAVES][SEG];
-    __shared__ int64_t lP[WAVES][SEG];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const uint64_t g = (uint64_t)blockIdx.x * WAVES + wv;
     if (g >= nseg_total) return;
-    summarize_segment(desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g))], g, lF[wv], lP[wv]);
+    summarize_segment(desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g))], g, lF[wv]);
 }
 
 // ------------------------------------------------------------ resolve pass
@@ -1009,8 +978,6 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
 // entry offset; record its samples, count, best growth sample and the Python
 // footprint at its last sample.  Copy and timer events are counted here.
 __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
-    __shared__ int64_t lF[WAVES][SEG];
-    __shared__ int64_t lP[WAVES][SEG];
     __shared__ HistCache<CHAIN_SLOTS> hc;
     hist_init(hc);
     __syncthreads();
@@ -1019,7 +986,18 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
     int cur_t = 0;
     int64_t peakS = 0;
     bool have_t = false;
-    for (uint64_t g = (uint64_t)blockIdx.x * WAVES + wv; g < nseg_total; g += (uint64_t)gridDim.x * WAVES) {
+    // lanes 0-4: prefixes, entry and exit from the resolve pass; lanes 5-13:
+    // flags and the chain after the first forced sample from the summary
+    // pass.  Each wave reads them one segment ahead.
+    const int pl_ = l < 5 ? SP_F0 + l : (l == 5 ? SP_FLG : (l < 14 ? SP_FN + (l - 6) : SP_F0));
+    const uint64_t stride = (uint64_t)gridDim.x * WAVES;
+    uint64_t g = (uint64_t)blockIdx.x * WAVES + wv;
+    int64_t pv_next = 0;
+    if (g < nseg_total) {
+        const Desc& D0 = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g))];
+        pv_next = seg_val(D0, pl_, (int64_t)(g - D0.seg_begin));
+    }
+    for (; g < nseg_total; g += stride) {
         const int t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, cur_t, ntraces, g));
         if (t != cur_t && have_t && l == 0 && peakS > 0)
             atomicMax((long long*)&desc[cur_t].scal->peak_S, (long long)peakS);
@@ -1032,10 +1010,13 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         const int64_t a = j * SEG;
         const int nv = seg_events(D, j);
         const int64_t T = D.T;
-        // lanes 0-4: prefixes, entry and exit from the resolve pass; lanes 5-12: flags
-        // and the chain after the first forced sample from the summary pass
-        const int pl_ = l < 5 ? SP_F0 + l : (l == 5 ? SP_FLG : (l < 13 ? SP_FN + (l - 6) : SP_F0));
-        const int64_t pv = seg_val(D, pl_, j);
+        const int64_t pv = pv_next;
+        {
+            // past the last segment, this one's again (no branch)
+            const uint64_t gn = g + stride < nseg_total ? g + stride : g;
+            const Desc& Dn = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, t, ntraces, gn))];
+            pv_next = seg_val(Dn, pl_, (int64_t)(gn - Dn.seg_begin));
+        }
         const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), C0 = readlane64(pv, 2);
         const int64_t eF = readlane64(pv, 3), xF = readlane64(pv, 4);
         const int64_t flg = readlane64(pv, 5);
@@ -1046,9 +1027,23 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         const int nlim = fn >= 0 ? fn + 1 : nv;
         SegRecs rr;
         fetch_segment(D, a, nlim, rr);
-        SegScan sc;
-        scan_segment<SCAN_CHAIN>(D, nlim, rr, lF[wv], lP[wv], nullptr, sc, fwin + 1);
         uint32_t err = 0;
+        // the chain from the entry, window by window while scanning (prefixes in registers)
+        ChainRun cr{eF, 0, 0, -1, INT64_MIN, -1};
+        int64_t lsp = 0, cF = 0, cP = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if (w > fwin) break;
+            const int k = w * 64 + l;
+            const uint32_t fl = (uint32_t)rr.q2[w];
+            const int64_t dm = (k < nlim && (fl & 6u) == 0) ? (int64_t)rr.q0[w] : 0;
+            const int64_t dp = (fl & 1u) ? 0 : dm;
+            const int64_t f = wave_incl_sum(dm) + cF;
+            const int64_t p = wave_incl_sum(dp) + cP;
+            cF = readlane64(f, 63);
+            cP = readlane64(p, 63);
+            chain_window<true>(f, p, T, cr, lsp, w, -1);
+        }
 
         // Copy volume (section 3.5: one Tc sample per multiple of Tc crossed by
         // the cumulative copy bytes) and the timer split (section 2.1: Python
@@ -1094,8 +1089,6 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
             }
         }
 
-        ChainRun cr{eF, 0, 0, -1, INT64_MIN, -1};
-        run_chain<true>(lF[wv], T, cr, 0, -1, fwin);
         int64_t count = wave_sum(l < NW ? (int64_t)__popcll(cr.mvec) : 0);
         int64_t gbest = cr.gbest, smax = cr.smax, lsrel = 0;
         int gnode = cr.gnode, lastS = cr.lastS;
@@ -1113,11 +1106,11 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
                 lastS = als;
                 lsrel = readlane64(pv, 12);
             } else {
-                lsrel = lP[wv][fn];
+                lsrel = lsp;  // the forced sample is the prefix's last
             }
         } else {
-            if (cr.ref - sc.sumF != xF) err |= 4u;  // internal: the resolved exit disagrees with the chain
-            if (lastS >= 0) lsrel = lP[wv][lastS];
+            if (cr.ref - cF != xF) err |= 4u;  // internal: the resolved exit disagrees with the chain
+            if (lastS >= 0) lsrel = lsp;
         }
         if (smax != INT64_MIN && F0 + smax > peakS) peakS = F0 + smax;
         const bool hg = gnode >= 0 && gnode < nv;  // nodes past the trace end never sample
@@ -1137,7 +1130,8 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
             D.seg[(SP_BCNT + l) * ns + j] = v;
         }
         // windows after the forced sample's keep the summary pass's masks
-        if (l < NW && l <= fwin) D.mask[j * NW + l] = cr.mvec | (fn >= 0 && l == fwin ? D.mask[j * NW + l] : 0ull);
+        const uint64_t amf = fn >= 0 ? (uint64_t)readlane64(pv, 13) : 0ull;
+        if (l < NW && l <= fwin) D.mask[j * NW + l] = cr.mvec | (l == fwin ? amf : 0ull);
         if (err && l == 0) atomicOr(&D.scal->err, err);
     }
     if (have_t && l == 0 && peakS > 0) atomicMax((long long*)&desc[cur_t].scal->peak_S, (long long)peakS);
