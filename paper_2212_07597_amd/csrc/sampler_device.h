@@ -259,11 +259,64 @@ struct StatusView {
     __device__ __forceinline__ uint64_t* at(int word, int64_t seg) const { return p + (int64_t)word * ns + seg; }
 };
 
+// ---- global memory through global-address-space pointers ------------------
+// Descriptor fields are generic pointers; accessed as such they compile to
+// flat instructions, which also count against the LDS wait counter, so every
+// wait for an LDS result would also wait for outstanding flat stores.
+#define SMP_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ SMP_GLOBAL T* gp(T* p) {
+    return (SMP_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ const SMP_GLOBAL T* gp(const T* p) {
+    return (const SMP_GLOBAL T*)p;
+}
+
+// relaxed agent-scope atomics on global memory
+__device__ __forceinline__ void g_add(uint64_t* p, uint64_t v) {
+    __hip_atomic_fetch_add(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t g_add_rtn(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_add(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_or(uint64_t* p, uint64_t v) {
+    __hip_atomic_fetch_or(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_or32(uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_or(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_max(int64_t* p, int64_t v) {
+    __hip_atomic_fetch_max(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint64_t ld_status(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_status(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A sample record as four 64-bit words (struct assignment has no overload
+// for global-address-space objects).
+__device__ __forceinline__ void store_sample(Sample* dst, const Sample& s) {
+    SMP_GLOBAL uint64_t* q = (SMP_GLOBAL uint64_t*)dst;
+    q[0] = (uint64_t)s.event_idx | ((uint64_t)s.line << 32);
+    q[1] = (uint64_t)s.F;
+    q[2] = (uint64_t)s.py;
+    q[3] = (uint64_t)s.nat;
+}
+__device__ __forceinline__ Sample load_sample(const Sample* src) {
+    const SMP_GLOBAL uint64_t* q = (const SMP_GLOBAL uint64_t*)src;
+    const uint64_t w0 = q[0];
+    Sample s;
+    s.event_idx = (uint32_t)w0;
+    s.line = (uint32_t)(w0 >> 32);
+    s.F = (int64_t)q[1];
+    s.py = (int64_t)q[2];
+    s.nat = (int64_t)q[3];
+    return s;
 }
 
 }  // namespace smp

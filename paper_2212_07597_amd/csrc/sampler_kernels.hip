@@ -86,8 +86,7 @@ __device__ __forceinline__ void hist_add(HistCache<NS>& hc, const Desc& D, uint3
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             if (cs[i] >= 0 && vs[i] != 0)
-                atomicAdd((unsigned long long*)&D.hist[(size_t)cache_to_hist(cs[i]) * D.L + line],
-                          (unsigned long long)vs[i]);
+                g_add((uint64_t*)&D.hist[(size_t)cache_to_hist(cs[i]) * D.L + line], (uint64_t)vs[i]);
     }
 }
 
@@ -101,7 +100,7 @@ __device__ __forceinline__ void hist_flush(HistCache<NS>& hc, const Desc* desc) 
         const uint32_t line = (uint32_t)key;
         for (int c = 0; c < NCNT; ++c) {
             const unsigned long long v = hc.cnt[i][c];
-            if (v) atomicAdd((unsigned long long*)&D.hist[(size_t)cache_to_hist(c) * D.L + line], v);
+            if (v) g_add((uint64_t*)&D.hist[(size_t)cache_to_hist(c) * D.L + line], v);
         }
     }
 }
@@ -374,7 +373,7 @@ __device__ int64_t simulate_exit(const Desc& D, int64_t j, int64_t x) {
         const int k = w * 64 + l;
         uint64_t r0 = 0, r1 = 0, r2 = 0;
         if (k < nv) {
-            const uint64_t* p = (const uint64_t*)(D.ev + (size_t)(a + k) * 24);
+            gu64_t* p = record(D, a + k);
             r0 = p[0];
             r1 = p[1];
             r2 = p[2];
@@ -790,10 +789,10 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
             case SP_ALP: v = r.lastS >= 0 ? alp : 0; break;
             default: v = amf; break;
         }
-        D.seg[(int64_t)l * (int64_t)D.nseg + j] = v;
+        gp(D.seg)[(int64_t)l * (int64_t)D.nseg + j] = v;
     }
-    if (fnode >= 0 && l < NW) D.mask[j * NW + l] = r.mvec;
-    if (sc.err && l == 0) atomicOr(&D.scal->err, sc.err);
+    if (fnode >= 0 && l < NW) gp(D.mask)[j * NW + l] = r.mvec;
+    if (sc.err && l == 0) g_or32(&D.scal->err, sc.err);
 }
 
 // One wave per segment, one launch wave per segment (measured faster here
@@ -825,7 +824,7 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     __shared__ int64_t s_entry;
     __shared__ int64_t w_peak[TWAVES];
     const int tid = threadIdx.x, wv = tid >> 6, l = lane_id();
-    if (tid == 0) s_tk = atomicAdd(&ctl[2], 1ull);
+    if (tid == 0) s_tk = g_add_rtn((uint64_t*)&ctl[2], 1ull);
     __syncthreads();
     const uint64_t tk = s_tk;
     if (tk >= ntile_total) return;
@@ -836,7 +835,7 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     const int64_t j = j0 + l;
     const bool valid = j < ns;
     const StatusView ts{D.tstat, (int64_t)D.ntile};
-    const int64_t* sp = D.seg + (valid ? j : 0);
+    const SMP_GLOBAL int64_t* sp = gp(D.seg) + (valid ? j : 0);
     int64_t af = 0, ap = 0, ac = 0, mxf = 0, mnf = 0, mxp = 0, mnp = 0, kf = 0;
     int64_t lo = INT64_MIN, hi = INT64_MAX;  // past the trace end: the identity map
     int kind = MAP_CONST;
@@ -924,7 +923,7 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
             s_pre[1] = pP;
             s_pre[2] = pC;
             s_entry = e;
-            if (!ok) atomicOr(&D.scal->err, 8u);
+            if (!ok) g_or32(&D.scal->err, 8u);
         }
     }
     __syncthreads();
@@ -949,7 +948,7 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     uint32_t err = 0;
     int64_t pk = 0;
     if (valid) {
-        int64_t* o = D.seg + j;
+        SMP_GLOBAL int64_t* o = gp(D.seg) + j;
         o[SP_F0 * ns] = F0;
         o[SP_P0 * ns] = P0;
         o[SP_C0 * ns] = C0;
@@ -959,16 +958,16 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
             C0 + ac >= MAX_ABS_F || F0 >= MAX_ABS_F || F0 <= -MAX_ABS_F)
             err = 2u;
         pk = F0 + mxf;
-        if (j == ns - 1) D.scal->final_F = F0 + af;
+        if (j == ns - 1) *gp(&D.scal->final_F) = F0 + af;
     }
-    if (ballot(err != 0) && l == 0) atomicOr(&D.scal->err, 2u);
+    if (ballot(err != 0) && l == 0) g_or32(&D.scal->err, 2u);
     pk = wave_max(pk);
     if (l == 0) w_peak[wv] = pk;
     __syncthreads();
     if (tid == 0) {
         int64_t p = 0;
         for (int w = 0; w < TWAVES; ++w) p = w_peak[w] > p ? w_peak[w] : p;
-        if (p > 0) atomicMax((long long*)&D.scal->peak_F, (long long)p);
+        if (p > 0) g_max(&D.scal->peak_F, (int64_t)p);
     }
 }
 
@@ -1000,7 +999,7 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
     for (; g < nseg_total; g += stride) {
         const int t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, cur_t, ntraces, g));
         if (t != cur_t && have_t && l == 0 && peakS > 0)
-            atomicMax((long long*)&desc[cur_t].scal->peak_S, (long long)peakS);
+            g_max(&desc[cur_t].scal->peak_S, (int64_t)peakS);
         if (t != cur_t) peakS = 0;
         cur_t = t;
         have_t = true;
@@ -1055,7 +1054,7 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
                 const int k = w * 64 + l;
                 uint64_t r0 = 0, r1 = 0, r2 = 0;
                 if (k < nv) {
-                    const uint64_t* rp = (const uint64_t*)(D.ev + (size_t)(a + k) * 24);
+                    gu64_t* rp = record(D, a + k);
                     r0 = rp[0];
                     r1 = rp[1];
                     r2 = rp[2];
@@ -1115,7 +1114,7 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         if (smax != INT64_MIN && F0 + smax > peakS) peakS = F0 + smax;
         const bool hg = gnode >= 0 && gnode < nv;  // nodes past the trace end never sample
         uint32_t gptr = 0;
-        if (hg) gptr = ((const uint32_t*)(D.ev + (size_t)(a + gnode) * 24))[2];
+        if (hg) gptr = (uint32_t)record(D, a + gnode)[1];
         const int64_t lsv = lastS >= 0 ? P0 + lsrel : 0;
         if (l < 6) {
             int64_t v;
@@ -1127,14 +1126,14 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
                 case 4: v = lsv; break;
                 default: v = (hg ? 1 : 0) | (lastS >= 0 ? 2 : 0); break;
             }
-            D.seg[(SP_BCNT + l) * ns + j] = v;
+            gp(D.seg)[(SP_BCNT + l) * ns + j] = v;
         }
         // windows after the forced sample's keep the summary pass's masks
         const uint64_t amf = fn >= 0 ? (uint64_t)readlane64(pv, 13) : 0ull;
-        if (l < NW && l <= fwin) D.mask[j * NW + l] = cr.mvec | (l == fwin ? amf : 0ull);
-        if (err && l == 0) atomicOr(&D.scal->err, err);
+        if (l < NW && l <= fwin) gp(D.mask)[j * NW + l] = cr.mvec | (l == fwin ? amf : 0ull);
+        if (err && l == 0) g_or32(&D.scal->err, err);
     }
-    if (have_t && l == 0 && peakS > 0) atomicMax((long long*)&desc[cur_t].scal->peak_S, (long long)peakS);
+    if (have_t && l == 0 && peakS > 0) g_max(&desc[cur_t].scal->peak_S, (int64_t)peakS);
     __syncthreads();
     hist_flush(hc, desc);
 }
@@ -1167,7 +1166,7 @@ __global__ __launch_bounds__(TILE) void k_bscan(const Desc* __restrict__ desc, i
     __shared__ uint32_t s_pre_idx, s_pre_ptr;
     __shared__ int s_pre_has;
     const int tid = threadIdx.x, wv = tid >> 6, l = lane_id();
-    if (tid == 0) s_tk = atomicAdd(&ctl[3], 1ull);
+    if (tid == 0) s_tk = g_add_rtn((uint64_t*)&ctl[3], 1ull);
     __syncthreads();
     const uint64_t tk = s_tk;
     if (tk >= ntile_total) return;
@@ -1177,13 +1176,13 @@ __global__ __launch_bounds__(TILE) void k_bscan(const Desc* __restrict__ desc, i
     const int64_t j = k * TILE + tid;
     const bool valid = j < ns;
     const StatusView ts{D.tstat, (int64_t)D.ntile};
-    int64_t cnt = 0, gv = 0, gi = 0, gp = 0, lsv = 0, fl = 0;
+    int64_t cnt = 0, gv = 0, gi = 0, gpt = 0, lsv = 0, fl = 0;
     if (valid) {
-        const int64_t* sp = D.seg + j;
+        const SMP_GLOBAL int64_t* sp = gp(D.seg) + j;
         cnt = sp[SP_BCNT * ns];
         gv = sp[SP_BGV * ns];
         gi = sp[SP_BGI * ns];
-        gp = sp[SP_BGP * ns];
+        gpt = sp[SP_BGP * ns];
         lsv = sp[SP_LSV * ns];
         fl = sp[SP_BFL * ns];
     }
@@ -1195,7 +1194,7 @@ __global__ __launch_bounds__(TILE) void k_bscan(const Desc* __restrict__ desc, i
     const uint64_t le = lanemask_lt() | (1ull << l);
     const uint64_t bnd = ballot(M != INT64_MIN && M > Mp) & le;  // where the running maximum rises
     const int src = bnd ? top64(bnd) : l;
-    const uint32_t iidx = (uint32_t)shfl32((int)(uint32_t)gi, src), iptr = (uint32_t)shfl32((int)(uint32_t)gp, src);
+    const uint32_t iidx = (uint32_t)shfl32((int)(uint32_t)gi, src), iptr = (uint32_t)shfl32((int)(uint32_t)gpt, src);
     const uint64_t lsm = ballot(hs) & le;
     const int lsrc = lsm ? top64(lsm) : l;
     const int64_t ils = shfl64(lsv, lsrc);
@@ -1242,7 +1241,7 @@ __global__ __launch_bounds__(TILE) void k_bscan(const Desc* __restrict__ desc, i
             s_pre_idx = pre.idx;
             s_pre_ptr = pre.ptr;
             s_pre_ls = eP;
-            if (!ok) atomicOr(&D.scal->err, 8u);
+            if (!ok) g_or32(&D.scal->err, 8u);
         }
     }
     __syncthreads();
@@ -1257,14 +1256,14 @@ __global__ __launch_bounds__(TILE) void k_bscan(const Desc* __restrict__ desc, i
     const BItem st = bcombine(bcombine(tpre, wpre), lpre);
     const Best b = with_baseline(st.b);
     if (valid) {
-        int64_t* o = D.seg + j;
+        SMP_GLOBAL int64_t* o = gp(D.seg) + j;
         o[SP_XCNT * ns] = b.cnt;
         o[SP_XHV * ns] = b.val;
         o[SP_XHI * ns] = b.idx;
         o[SP_XHP * ns] = b.ptr;
         o[SP_XFL * ns] = b.has ? 1 : 0;
         o[SP_XLS * ns] = st.ls;
-        if (j == ns - 1) D.scal->K = (uint64_t)(b.cnt + cnt);
+        if (j == ns - 1) *gp(&D.scal->K) = (uint64_t)(b.cnt + cnt);
     }
 }
 
@@ -1282,7 +1281,7 @@ __device__ __forceinline__ void flush_stage(const Desc& D, uint32_t t, const Sam
     const int l = lane_id();
     if (l < cnt && r0 + l < (int64_t)D.n) {
         const Sample smp = stg[l];
-        D.samples[r0 + l] = smp;
+        store_sample(D.samples + r0 + l, smp);
         if (smp.line < D.L) {
             const int64_t dl = smp.py + smp.nat;
             const bool gr = dl > 0;
@@ -1382,8 +1381,8 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, uint
                 }
             }
             if (((tmask >> l) & 1) && rank < (int64_t)D.n) {
-                atomicOr((unsigned long long*)&D.tracked_bits[rank >> 6], 1ull << (rank & 63));
-                D.sample_ptr[rank] = pt;
+                g_or(&D.tracked_bits[rank >> 6], 1ull << (rank & 63));
+                gp(D.sample_ptr)[rank] = pt;
             }
             const int ls = top64(m);
             refF = readlane64(f, ls);
@@ -1397,7 +1396,7 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, uint
             const uint32_t aidx = tb ? (uint32_t)(a + w * 64 + al) : cur_idx;
             const bool ahas = tb != 0 || cur_has;
             if (((fm >> l) & 1) && ahas && pt == aptr && aidx < D.n)
-                atomicOr((unsigned long long*)&D.freed_bits[aidx >> 6], 1ull << (aidx & 63));
+                g_or(&D.freed_bits[aidx >> 6], 1ull << (aidx & 63));
         }
         if (tmask) {
             const int tl = top64(tmask);
@@ -1417,7 +1416,7 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, uint
         }
     }
     if (staged) flush_stage(D, (uint32_t)t, stg, staged, stage_rank, hc);
-    if (err && l == 0) atomicOr(&D.scal->err, err);
+    if (err && l == 0) g_or32(&D.scal->err, err);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
@@ -1441,7 +1440,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, i
 __global__ void k_clear(const Desc* __restrict__ desc, int ntraces, uint64_t total_bytes, unsigned long long* ctl) {
     const uint64_t chunk = 1ull << 16;
     const uint64_t begin = (uint64_t)blockIdx.x * chunk;
-    if (blockIdx.x == 0 && threadIdx.x < 32) ctl[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 32) gp(ctl)[threadIdx.x] = 0;
     if (begin >= total_bytes) return;
     const uint64_t end = begin + chunk < total_bytes ? begin + chunk : total_bytes;
     // traces overlapping [begin, end)
@@ -1456,7 +1455,7 @@ __global__ void k_clear(const Desc* __restrict__ desc, int ntraces, uint64_t tot
         const uint64_t s = D.zero_begin > begin ? D.zero_begin : begin;
         const uint64_t e = (D.zero_begin + D.zero_bytes) < end ? (D.zero_begin + D.zero_bytes) : end;
         if (s >= e) continue;
-        uint64_t* p = (uint64_t*)(D.zero_ptr + (s - D.zero_begin));
+        SMP_GLOBAL uint64_t* p = gp((uint64_t*)(D.zero_ptr + (s - D.zero_begin)));
         const uint64_t nw = (e - s) >> 3;
         for (uint64_t i = threadIdx.x; i < nw; i += blockDim.x) p[i] = 0;
     }
@@ -1480,12 +1479,13 @@ __global__ void k_track_count(const Desc* __restrict__ desc, int ntraces, uint64
     if (b >= nblk_total) return;
     const Desc& D = desc[find_trace_blk(desc, ntraces, b)];
     const uint64_t lb = b - D.blk_begin;
-    const uint64_t K = D.scal->K < D.n ? D.scal->K : D.n;
+    const uint64_t Kr = *gp(&D.scal->K);
+    const uint64_t K = Kr < D.n ? Kr : D.n;
     const uint64_t nwords = (K + 63) >> 6;
     const uint64_t w0 = lb * CBLK_WORDS;
     uint64_t c = 0;
     for (uint64_t i = threadIdx.x; i < CBLK_WORDS; i += blockDim.x)
-        if (w0 + i < nwords) c += __popcll(D.tracked_bits[w0 + i]);
+        if (w0 + i < nwords) c += __popcll(gp(D.tracked_bits)[w0 + i]);
     __shared__ uint64_t red[256];
     red[threadIdx.x] = c;
     __syncthreads();
@@ -1493,7 +1493,7 @@ __global__ void k_track_count(const Desc* __restrict__ desc, int ntraces, uint64
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) D.blk[lb] = red[0];
+    if (threadIdx.x == 0) gp(D.blk)[lb] = red[0];
 }
 
 __global__ void k_track_scan(const Desc* __restrict__ desc) {
@@ -1504,7 +1504,7 @@ __global__ void k_track_scan(const Desc* __restrict__ desc) {
     __syncthreads();
     for (uint64_t b0 = 0; b0 < D.nblk; b0 += blockDim.x) {
         const uint64_t i = b0 + threadIdx.x;
-        const uint64_t v = i < D.nblk ? D.blk[i] : 0;
+        const uint64_t v = i < D.nblk ? gp(D.blk)[i] : 0;
         part[threadIdx.x] = v;
         __syncthreads();
         for (int s = 1; s < (int)blockDim.x; s <<= 1) {
@@ -1513,12 +1513,12 @@ __global__ void k_track_scan(const Desc* __restrict__ desc) {
             part[threadIdx.x] += x;
             __syncthreads();
         }
-        if (i < D.nblk) D.blk[i] = carry + part[threadIdx.x] - v;  // exclusive
+        if (i < D.nblk) gp(D.blk)[i] = carry + part[threadIdx.x] - v;  // exclusive
         __syncthreads();
         if (threadIdx.x == blockDim.x - 1) carry += part[threadIdx.x];
         __syncthreads();
     }
-    if (threadIdx.x == 0) D.scal->H = carry;
+    if (threadIdx.x == 0) *gp(&D.scal->H) = carry;
 }
 
 __global__ void k_track_emit(const Desc* __restrict__ desc, int ntraces, uint64_t nblk_total) {
@@ -1526,18 +1526,19 @@ __global__ void k_track_emit(const Desc* __restrict__ desc, int ntraces, uint64_
     if (b >= nblk_total) return;
     const Desc& D = desc[find_trace_blk(desc, ntraces, b)];
     const uint64_t lb = b - D.blk_begin;
-    const uint64_t K = D.scal->K < D.n ? D.scal->K : D.n;
+    const uint64_t Kr = *gp(&D.scal->K);
+    const uint64_t K = Kr < D.n ? Kr : D.n;
     const uint64_t nwords = (K + 63) >> 6;
     const uint64_t w0 = lb * CBLK_WORDS;
     if (w0 >= nwords) return;
-    const uint64_t H = D.scal->H;
+    const uint64_t H = *gp(&D.scal->H);
     // each thread owns 4 consecutive words
     constexpr int PER = CBLK_WORDS / 256;
     uint64_t words[PER];
     uint64_t c = 0;
     for (int i = 0; i < PER; ++i) {
         const uint64_t wi = w0 + threadIdx.x * PER + i;
-        words[i] = wi < nwords ? D.tracked_bits[wi] : 0;
+        words[i] = wi < nwords ? gp(D.tracked_bits)[wi] : 0;
         c += __popcll(words[i]);
     }
     __shared__ uint64_t part[256];
@@ -1549,7 +1550,7 @@ __global__ void k_track_emit(const Desc* __restrict__ desc, int ntraces, uint64_
         part[threadIdx.x] += x;
         __syncthreads();
     }
-    uint64_t h = D.blk[lb] + part[threadIdx.x] - c;
+    uint64_t h = gp(D.blk)[lb] + part[threadIdx.x] - c;
     const bool resolve_last = (D.options & 2u) != 0;
     for (int i = 0; i < PER; ++i) {
         uint64_t m = words[i];
@@ -1559,19 +1560,23 @@ __global__ void k_track_emit(const Desc* __restrict__ desc, int ntraces, uint64_
             m &= m - 1;
             const uint64_t r = wi * 64 + bit;
             if (r >= K || h >= H) break;  // only reachable after an internal fault
-            const Sample s = D.samples[r];
+            const Sample s = load_sample(D.samples + r);
             const uint32_t freed =
-                s.event_idx < D.n ? (uint32_t)((D.freed_bits[s.event_idx >> 6] >> (s.event_idx & 63)) & 1) : 0u;
+                s.event_idx < D.n ? (uint32_t)((gp(D.freed_bits)[s.event_idx >> 6] >> (s.event_idx & 63)) & 1) : 0u;
             Tracked tr;
             tr.event_idx = s.event_idx;
             tr.line = s.line;
-            tr.ptr = D.sample_ptr[r];
+            tr.ptr = gp(D.sample_ptr)[r];
             tr.freed = freed;
-            D.tracked[h] = tr;
+            SMP_GLOBAL uint32_t* tq = (SMP_GLOBAL uint32_t*)(D.tracked + h);
+            tq[0] = tr.event_idx;
+            tq[1] = tr.line;
+            tq[2] = tr.ptr;
+            tq[3] = tr.freed;
             if (s.line < D.L) {
-                atomicAdd((unsigned long long*)&D.hist[(size_t)H_LEAK_M * D.L + s.line], 1ull);
+                g_add((uint64_t*)&D.hist[(size_t)H_LEAK_M * D.L + s.line], 1ull);
                 if (freed && (h + 1 < H || resolve_last))
-                    atomicAdd((unsigned long long*)&D.hist[(size_t)H_LEAK_F * D.L + s.line], 1ull);
+                    g_add((uint64_t*)&D.hist[(size_t)H_LEAK_F * D.L + s.line], 1ull);
             }
             ++h;
         }
@@ -1603,16 +1608,17 @@ __global__ void k_leak_finalize(const Desc* __restrict__ desc, int ntraces, uint
     const Desc& D = desc[lo];
     const uint64_t line = i - D.line_begin;
     if (line >= D.L) return;
-    const int64_t m = D.hist[(size_t)H_LEAK_M * D.L + line];
-    const int64_t f = D.hist[(size_t)H_LEAK_F * D.L + line];
-    int64_t* out = D.leak;
+    const int64_t m = gp(D.hist)[(size_t)H_LEAK_M * D.L + line];
+    const int64_t f = gp(D.hist)[(size_t)H_LEAK_F * D.L + line];
+    SMP_GLOBAL int64_t* out = gp(D.leak);
+    SMP_GLOBAL uint8_t* gates = gp(D.gates);
     if (m <= 0) {
         out[line] = 0;
         out[D.L + line] = 0;
         out[2 * (size_t)D.L + line] = 0;
         out[3 * (size_t)D.L + line] = 0;
-        D.gates[line] = 0;
-        D.gates[D.L + line] = 0;
+        gates[line] = 0;
+        gates[D.L + line] = 0;
         return;
     }
     int64_t n1 = m - f + 1, d1 = m + 2;
@@ -1625,8 +1631,8 @@ __global__ void k_leak_finalize(const Desc* __restrict__ desc, int ntraces, uint
     out[D.L + line] = d1;
     out[2 * (size_t)D.L + line] = n2;
     out[3 * (size_t)D.L + line] = d2;
-    D.gates[line] = g1;
-    D.gates[D.L + line] = g2;
+    gates[line] = g1;
+    gates[D.L + line] = g2;
 }
 
 // ------------------------------------------------------------ launchers
