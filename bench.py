@@ -200,10 +200,13 @@ def bench_batched(smp, tg, torch, np, steps=3):
     need = sum(smp.workspace_bytes(len(ev), p) for (ev, _), p in zip(traces, params))
     s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + need + (64 << 20))
 
+    pass_runs = []
+
     def batched():
         ids = [s.submit_trace(d, p) for d, p in zip(devs, params)]
         s.run(blocking=True)
         km, _ = s.last_timing()
+        pass_runs.append(s.last_pass_timing())
         for i in ids:
             s.release(i)
         return km
@@ -231,6 +234,8 @@ def bench_batched(smp, tg, torch, np, steps=3):
     return {"workload": "config3: 1024 traces, lengths 10^(3+3u), config-1 mix, 1000 lines, T in {256K,1M,10M}",
             "events": total, "batched_events_per_s": round(total / tb, 1), "batched_ms": round(tb * 1e3, 3),
             "batched_kernel_ms": round(kms_avg, 3),
+            "batched_pass_ms": {k: round(sum(r[k] for r in pass_runs[1:]) / max(len(pass_runs) - 1, 1), 4)
+                                for k in smp.PASS_NAMES},
             "batched_kernel_hbm_gbs": round(BYTES_PER_EVENT * total / (kms_avg * 1e-3) / 1e9, 1),
             "plain_events_per_s": round(total / tp, 1), "plain_ms": round(tp * 1e3, 3),
             "speedup_vs_plain": round(tp / tb, 2)}

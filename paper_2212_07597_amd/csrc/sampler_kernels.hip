@@ -366,31 +366,20 @@ __device__ SegMap analyse_segment(const int64_t* F, int64_t T, int64_t sumF) {
 // (wave-uniform x; used for segments whose chains did not all coincide).
 __device__ int64_t simulate_exit(const Desc& D, int64_t j, int64_t x) {
     const int l = lane_id();
-    const int64_t a = j * SEG;
     const int nv = seg_events(D, j);
-    int64_t ref = x, cF = 0;
+    SegRecs rr;
+    fetch_segment(D, j * SEG, nv, rr);
+    int64_t cF = 0, lsp = 0;
+    ChainRun cr{x, 0, 0, -1, INT64_MIN, -1};
+#pragma unroll
     for (int w = 0; w < NW; ++w) {
         const int k = w * 64 + l;
-        uint64_t r0 = 0, r1 = 0, r2 = 0;
-        if (k < nv) {
-            gu64_t* p = record(D, a + k);
-            r0 = p[0];
-            r1 = p[1];
-            r2 = p[2];
-        }
-        const Ev e = decode(r0, r1, r2, k < nv, D.L);
+        const Ev e = decode(rr.q0[w], rr.q1[w], rr.q2[w], k < nv, D.L);
         const int64_t f = wave_incl_sum(e.dm) + cF;
         cF = readlane64(f, 63);
-        int st = -1;
-        for (;;) {
-            const int64_t d = f - ref;
-            const uint64_t m = ballot(l > st && (d >= D.T || d <= -D.T));
-            if (!m) break;
-            st = ctz64(m);
-            ref = readlane64(f, st);
-        }
+        chain_window<false>(f, 0, D.T, cr, lsp, w, -1);
     }
-    return ref - cF;
+    return cr.ref - cF;
 }
 
 // Exit offset of segment j (map lo, hi, af, kf, kind) from entry offset x.
