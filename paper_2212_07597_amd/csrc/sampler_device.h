@@ -18,8 +18,9 @@ constexpr int BLOCK = 64 * WAVES;
 constexpr int TILE = 1024;               // segments per tile
 constexpr int TWAVES = TILE / 64;
 constexpr int CHAIN_SLOTS = 32;          // LDS histogram cache slots per workgroup: chain pass (copy, timer)
-constexpr int EMIT_SLOTS = 128;          // and emit pass (samples)
-constexpr int NCNT = 10;                 // counters cached per slot
+constexpr int EMIT_SLOTS = 128;          // emit pass (samples)
+constexpr int TRACK_SLOTS = 64;          // and tracked-list pass (mallocs, frees)
+constexpr int NCNT = 12;                 // counters cached per slot
 constexpr int CHAIN_CAP = 32;            // chains followed by the all-entry analysis
 
 constexpr int64_t MAX_ABS_DELTA = (int64_t)1 << 52;
@@ -27,7 +28,7 @@ constexpr int64_t MAX_ABS_F = (int64_t)1 << 61;
 
 // per-line histogram indices (same order as the public SMP_H_* enum)
 enum { H_PY = 0, H_NAT, H_GN, H_SN, H_GB, H_SB, H_LEAK_M, H_LEAK_F, H_CS, H_CE, H_PT, H_NT, H_COUNT };
-enum { C_PY = 0, C_NAT, C_GN, C_SN, C_GB, C_SB, C_CS, C_CE, C_PT, C_NT };
+enum { C_PY = 0, C_NAT, C_GN, C_SN, C_GB, C_SB, C_CS, C_CE, C_PT, C_NT, C_LM, C_LF };
 
 // Chain map of a segment over entry offsets: entries in [lo, hi] take no
 // sample; every other entry ends at one exit offset (CONST; TOTAL when the

@@ -19,6 +19,7 @@ hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, uns
 hipError_t launch_pass(int pass, const Desc* desc, int ntraces, uint64_t nseg_total, uint64_t ntile_total,
                        unsigned long long* ctl, int grid_limit, hipStream_t s);
 hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines, hipStream_t s);
+hipError_t launch_gather_scalars(const Desc* desc, int ntraces, Scalars* out, hipStream_t s);
 }  // namespace smp
 
 using namespace smp;
@@ -26,6 +27,7 @@ using namespace smp;
 static_assert(sizeof(smp_event_t) == 24, "event record layout");
 static_assert(sizeof(smp_sample_t) == sizeof(Sample), "sample layout");
 static_assert(sizeof(smp_tracked_t) == sizeof(Tracked), "tracked layout");
+static_assert(sizeof(Scalars) == 64, "scalars are gathered as 8 words");
 
 namespace {
 
@@ -145,11 +147,16 @@ struct TraceRec {
     const uint8_t* ev = nullptr;
     int slot = -1;
     uint64_t run_seq = 0;
+    bool have_scal = false;  // scalars copied to the host when its launch retired
+    Scalars scal{};
 };
 
 struct RunSlot {
     Desc* host_desc = nullptr;   // pinned staging
     Desc* dev_desc = nullptr;
+    Scalars* dev_scal = nullptr;   // every trace's scalars, gathered after the launch
+    Scalars* host_scal = nullptr;  // pinned copy of dev_scal
+    std::vector<uint64_t> ids;     // the launch's traces, in descriptor order
     unsigned long long* dev_ticket = nullptr;
     hipStream_t stream = nullptr;  // launches of this slot; ordered after the caller's stream
     hipEvent_t e_ready = nullptr;  // recorded on the caller's stream at run()
@@ -183,9 +190,13 @@ struct smp_sampler {
 
 namespace {
 
-uint64_t fixed_bytes() {
-    return align_up((uint64_t)RUN_SLOTS * (align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN) + ALIGN), ALIGN);
+// Per run slot: descriptors, 32 control words, gathered scalars.
+uint64_t slot_bytes() {
+    return align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN) + ALIGN +
+           align_up(sizeof(Scalars) * MAX_TRACES_PER_RUN, ALIGN);
 }
+
+uint64_t fixed_bytes() { return align_up((uint64_t)RUN_SLOTS * slot_bytes(), ALIGN); }
 
 bool arena_alloc(smp_sampler* s, uint64_t bytes, uint64_t* off) {
     for (auto it = s->free_list.begin(); it != s->free_list.end(); ++it) {
@@ -241,6 +252,13 @@ int retire_slot(smp_sampler* s, RunSlot& r) {
         s->last_total_ms = b;
         for (int i = 0; i < NPASS; ++i) s->last_pass_ms[i] = p[i];
     }
+    for (size_t k = 0; k < r.ids.size(); ++k) {
+        auto it = s->traces.find(r.ids[k]);
+        if (it != s->traces.end() && it->second.run_seq == r.seq) {
+            it->second.scal = r.host_scal[k];
+            it->second.have_scal = true;
+        }
+    }
     r.busy = false;
     return SMP_OK;
 }
@@ -292,12 +310,14 @@ int sampler_create(int device, void* hip_stream, uint64_t mem_budget, void* work
         delete s;
         return SMP_EDEVICE;
     }
-    const uint64_t slot_bytes = align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN) + ALIGN;
     for (int i = 0; i < RUN_SLOTS; ++i) {
         RunSlot& r = s->slots[i];
-        r.dev_desc = (Desc*)(s->ws + i * slot_bytes);
-        r.dev_ticket = (unsigned long long*)(s->ws + i * slot_bytes + align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN));
+        uint8_t* base = s->ws + i * slot_bytes();
+        r.dev_desc = (Desc*)base;
+        r.dev_ticket = (unsigned long long*)(base + align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN));
+        r.dev_scal = (Scalars*)(base + align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN) + ALIGN);
         if (hipHostMalloc((void**)&r.host_desc, sizeof(Desc) * MAX_TRACES_PER_RUN, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&r.host_scal, sizeof(Scalars) * MAX_TRACES_PER_RUN, hipHostMallocDefault) != hipSuccess ||
             hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&r.e_ready, hipEventDisableTiming) != hipSuccess ||
             hipEventCreate(&r.e_start) != hipSuccess || hipEventCreate(&r.e_end) != hipSuccess) {
@@ -329,6 +349,7 @@ void sampler_destroy(smp_sampler_t* s) {
     }
     for (auto& r : s->slots) {
         if (r.host_desc) (void)hipHostFree(r.host_desc);
+        if (r.host_scal) (void)hipHostFree(r.host_scal);
         if (r.stream) (void)hipStreamDestroy(r.stream);
         if (r.e_ready) (void)hipEventDestroy(r.e_ready);
         if (r.e_start) (void)hipEventDestroy(r.e_start);
@@ -405,6 +426,7 @@ int run(smp_sampler_t* s, int blocking) {
         RunSlot& r = s->slots[si];
         if (int rc = retire_slot(s, r)) return rc;
         uint64_t seg = 0, tile = 0, blk = 0, zero = 0, lines = 0;
+        r.ids.clear();
         for (size_t k = 0; k < cnt; ++k) {
             TraceRec& t = *pend[done + k];
             Desc& D = r.host_desc[k];
@@ -449,6 +471,8 @@ int run(smp_sampler_t* s, int blocking) {
             lines += D.L;
             t.state = LAUNCHED;
             t.slot = si;
+            t.have_scal = false;
+            r.ids.push_back(t.id);
         }
         r.seq = ++s->run_seq;
         for (size_t k = 0; k < cnt; ++k) pend[done + k]->run_seq = r.seq;
@@ -465,6 +489,8 @@ int run(smp_sampler_t* s, int blocking) {
         }
         HIPCHK(hipEventRecord(r.e_pass[NPASS], r.stream));
         HIPCHK(launch_finish(r.dev_desc, (int)cnt, blk, lines, r.stream));
+        HIPCHK(launch_gather_scalars(r.dev_desc, (int)cnt, r.dev_scal, r.stream));
+        HIPCHK(hipMemcpyAsync(r.host_scal, r.dev_scal, sizeof(Scalars) * cnt, hipMemcpyDeviceToHost, r.stream));
         HIPCHK(hipEventRecord(r.e_end, r.stream));
         r.busy = true;
         done += cnt;
@@ -504,8 +530,8 @@ int fetch_profile(smp_sampler_t* s, uint64_t trace_id, smp_profile_sizes_t* size
     HIPCHK(hipSetDevice(s->device));
     if (int rc = wait_trace(s, t)) return rc;
     uint8_t* base = s->ws + t.off;
-    Scalars sc;
-    HIPCHK(hipMemcpy(&sc, base + t.lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    Scalars sc = t.scal;
+    if (!t.have_scal) HIPCHK(hipMemcpy(&sc, base + t.lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
     int32_t status = SMP_OK;
     if (sc.err & 1u) status = SMP_EINVAL;
     else if (sc.err & 2u) status = SMP_EOVERFLOW;
@@ -547,8 +573,8 @@ int trace_device_results(smp_sampler_t* s, uint64_t trace_id, void** samples, vo
     if (samples) *samples = base + t.lay.samples;
     if (hist) *hist = base + t.lay.hist;
     if (n_samples) {
-        Scalars sc;
-        HIPCHK(hipMemcpy(&sc, base + t.lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
+        Scalars sc = t.scal;
+        if (!t.have_scal) HIPCHK(hipMemcpy(&sc, base + t.lay.scal, sizeof(sc), hipMemcpyDeviceToHost));
         *n_samples = sc.K;
     }
     return SMP_OK;

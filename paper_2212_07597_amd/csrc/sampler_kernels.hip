@@ -45,7 +45,9 @@ __device__ __forceinline__ int cache_to_hist(int c) {
         case C_CS: return H_CS;
         case C_CE: return H_CE;
         case C_PT: return H_PT;
-        default: return H_NT;
+        case C_NT: return H_NT;
+        case C_LM: return H_LEAK_M;
+        default: return H_LEAK_F;
     }
 }
 
@@ -1510,6 +1512,9 @@ __global__ void k_track_scan(const Desc* __restrict__ desc) {
     if (threadIdx.x == 0) *gp(&D.scal->H) = carry;
 }
 
+// Ordered tracked list, in two steps: k_track_emit writes the sample rank of
+// every tracked sample at its place in the list (stores only), then
+// k_track_fill completes each entry in parallel.
 __global__ void k_track_emit(const Desc* __restrict__ desc, int ntraces, uint64_t nblk_total) {
     const uint64_t b = blockIdx.x;
     if (b >= nblk_total) return;
@@ -1540,7 +1545,7 @@ __global__ void k_track_emit(const Desc* __restrict__ desc, int ntraces, uint64_
         __syncthreads();
     }
     uint64_t h = gp(D.blk)[lb] + part[threadIdx.x] - c;
-    const bool resolve_last = (D.options & 2u) != 0;
+    SMP_GLOBAL uint32_t* tq = (SMP_GLOBAL uint32_t*)D.tracked;
     for (int i = 0; i < PER; ++i) {
         uint64_t m = words[i];
         const uint64_t wi = w0 + threadIdx.x * PER + i;
@@ -1549,27 +1554,48 @@ __global__ void k_track_emit(const Desc* __restrict__ desc, int ntraces, uint64_
             m &= m - 1;
             const uint64_t r = wi * 64 + bit;
             if (r >= K || h >= H) break;  // only reachable after an internal fault
-            const Sample s = load_sample(D.samples + r);
-            const uint32_t freed =
-                s.event_idx < D.n ? (uint32_t)((gp(D.freed_bits)[s.event_idx >> 6] >> (s.event_idx & 63)) & 1) : 0u;
-            Tracked tr;
-            tr.event_idx = s.event_idx;
-            tr.line = s.line;
-            tr.ptr = gp(D.sample_ptr)[r];
-            tr.freed = freed;
-            SMP_GLOBAL uint32_t* tq = (SMP_GLOBAL uint32_t*)(D.tracked + h);
-            tq[0] = tr.event_idx;
-            tq[1] = tr.line;
-            tq[2] = tr.ptr;
-            tq[3] = tr.freed;
-            if (s.line < D.L) {
-                g_add((uint64_t*)&D.hist[(size_t)H_LEAK_M * D.L + s.line], 1ull);
-                if (freed && (h + 1 < H || resolve_last))
-                    g_add((uint64_t*)&D.hist[(size_t)H_LEAK_F * D.L + s.line], 1ull);
-            }
+            tq[4 * h] = (uint32_t)r;
             ++h;
         }
     }
+}
+
+// Entry h of the tracked list (rank r from k_track_emit): event, line and
+// ptr_id of the tracked sample, whether a free reclaimed it (section 3.4),
+// and the per-line (mallocs, frees) counts.  The last tracked object counts
+// as reclaimed only with RESOLVE_AT_END.
+__global__ __launch_bounds__(256) void k_track_fill(const Desc* __restrict__ desc, int ntraces, uint64_t nblk_total) {
+    __shared__ HistCache<TRACK_SLOTS> hc;
+    hist_init(hc);
+    __syncthreads();
+    const uint64_t b = blockIdx.x;
+    if (b < nblk_total) {
+        const uint32_t t = (uint32_t)find_trace_blk(desc, ntraces, b);
+        const Desc& D = desc[t];
+        const uint64_t lb = b - D.blk_begin;
+        const uint64_t H = *gp(&D.scal->H);
+        const uint64_t h0 = gp(D.blk)[lb];
+        const uint64_t h1 = lb + 1 < D.nblk ? gp(D.blk)[lb + 1] : H;
+        const uint64_t Kr = *gp(&D.scal->K);
+        const uint64_t K = Kr < D.n ? Kr : D.n;
+        const bool resolve_last = (D.options & 2u) != 0;
+        SMP_GLOBAL uint32_t* tq = (SMP_GLOBAL uint32_t*)D.tracked;
+        for (uint64_t h = h0 + threadIdx.x; h < h1 && h < H; h += blockDim.x) {
+            const uint64_t r = tq[4 * h];
+            if (r >= K) continue;  // only reachable after an internal fault
+            const Sample s = load_sample(D.samples + r);
+            const uint32_t freed =
+                s.event_idx < D.n ? (uint32_t)((gp(D.freed_bits)[s.event_idx >> 6] >> (s.event_idx & 63)) & 1) : 0u;
+            tq[4 * h] = s.event_idx;
+            tq[4 * h + 1] = s.line;
+            tq[4 * h + 2] = gp(D.sample_ptr)[r];
+            tq[4 * h + 3] = freed;
+            if (s.line < D.L)
+                hist_add(hc, D, t, s.line, C_LM, 1, C_LF, (freed && (h + 1 < H || resolve_last)) ? 1 : 0, -1, 0, -1, 0);
+        }
+    }
+    __syncthreads();
+    hist_flush(hc, desc);
 }
 
 // ------------------------------------------------ leak likelihood per line
@@ -1658,11 +1684,25 @@ hipError_t launch_pass(int pass, const Desc* desc, int ntraces, uint64_t nseg_to
     return hipGetLastError();
 }
 
+// Every trace's scalars into one array (copied to the host with one transfer).
+__global__ void k_gather_scalars(const Desc* __restrict__ desc, int ntraces, Scalars* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntraces * 8) return;
+    const int t = i >> 3, w = i & 7;  // 8 words per Scalars
+    gp((uint64_t*)(out + t))[w] = gp((const uint64_t*)desc[t].scal)[w];
+}
+
+hipError_t launch_gather_scalars(const Desc* desc, int ntraces, Scalars* out, hipStream_t s) {
+    k_gather_scalars<<<dim3((unsigned)((ntraces * 8 + 255) / 256)), dim3(256), 0, s>>>(desc, ntraces, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines, hipStream_t s) {
     if (nblk_total) {
         k_track_count<<<dim3((unsigned)nblk_total), dim3(256), 0, s>>>(desc, ntraces, nblk_total);
         k_track_scan<<<dim3((unsigned)ntraces), dim3(256), 0, s>>>(desc);
         k_track_emit<<<dim3((unsigned)nblk_total), dim3(256), 0, s>>>(desc, ntraces, nblk_total);
+        k_track_fill<<<dim3((unsigned)nblk_total), dim3(256), 0, s>>>(desc, ntraces, nblk_total);
     }
     if (total_lines) {
         const uint64_t blocks = (total_lines + 255) / 256;
