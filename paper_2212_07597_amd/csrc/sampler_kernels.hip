@@ -364,47 +364,6 @@ __device__ SegMap analyse_segment(const int64_t* F, int64_t T, int64_t sumF) {
     return m;
 }
 
-// Exit offset of segment j from entry offset x, following the records
-// (wave-uniform x; used for segments whose chains did not all coincide).
-__device__ int64_t simulate_exit(const Desc& D, int64_t j, int64_t x) {
-    const int l = lane_id();
-    const int nv = seg_events(D, j);
-    SegRecs rr;
-    fetch_segment(D, j * SEG, nv, rr);
-    int64_t cF = 0, lsp = 0;
-    ChainRun cr{x, 0, 0, -1, INT64_MIN, -1};
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const int k = w * 64 + l;
-        const Ev e = decode(rr.q0[w], rr.q1[w], rr.q2[w], k < nv, D.L);
-        const int64_t f = wave_incl_sum(e.dm) + cF;
-        cF = readlane64(f, 63);
-        chain_window<false>(f, 0, D.T, cr, lsp, w, -1);
-    }
-    return cr.ref - cF;
-}
-
-// Exit offset of segment j (map lo, hi, af, kf, kind) from entry offset x.
-__device__ __forceinline__ int64_t seg_exit(const Desc& D, int64_t j, int64_t x, int64_t lo, int64_t hi, int64_t af,
-                                            int64_t kf, int kind) {
-    if (x >= lo && x <= hi) return x - af;
-    if (kind != MAP_SIM) return kf;
-    return simulate_exit(D, j, x);
-}
-
-// Apply the maps of lanes [from, to) in order from the wave-uniform entry x;
-// lane i's exit goes to ex.  Returns the exit after lane to-1.
-__device__ int64_t resolve_lanes(const Desc& D, int64_t j0, int from, int to, int64_t x, int64_t lo, int64_t hi,
-                                 int64_t af, int64_t kf, int kind, int64_t& ex) {
-    const int l = lane_id();
-    for (int i = from; i < to; ++i) {
-        x = seg_exit(D, j0 + i, x, readlane64(lo, i), readlane64(hi, i), readlane64(af, i), readlane64(kf, i),
-                     readlane32(kind, i));
-        if (l == i) ex = x;
-    }
-    return x;
-}
-
 // ---------------------------------------------------------------- look-backs
 
 // Every wait on another tile's status polls with a budget and an exponential
@@ -800,81 +759,137 @@ __global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ de
 
 // ------------------------------------------------------------ resolve pass
 
+constexpr int RING = 6;  // SIM segments pre-scanned ahead of the walker
+
+// Relative footprint prefixes of segment j into F (one wave; lanes past the
+// segment end hold its last prefix).
+// Two halves of four windows each, to keep the register footprint small.
+__device__ __forceinline__ void prescan_segment(const Desc& D, int64_t j, int64_t* F) {
+    const int l = lane_id();
+    const int nv = seg_events(D, j);
+    gu8_t* base = (gu8_t*)(D.ev + (size_t)j * SEG * 24);
+    int64_t cF = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        uint64_t q0[NW / 2], q2[NW / 2];
+#pragma unroll
+        for (int w = 0; w < NW / 2; ++w) {
+            const int k = (h * NW / 2 + w) * 64 + l;
+            gu64_t* p = (gu64_t*)(base + (uint32_t)((k < nv ? k : nv - 1) * 24));
+            q0[w] = __builtin_nontemporal_load(p);
+            q2[w] = __builtin_nontemporal_load(p + 2);
+        }
+#pragma unroll
+        for (int w = 0; w < NW / 2; ++w) {
+            const int k = (h * NW / 2 + w) * 64 + l;
+            const uint32_t fl = (uint32_t)q2[w];
+            const int64_t dm = (k < nv && (fl & 6u) == 0) ? (int64_t)q0[w] : 0;
+            const int64_t f = wave_incl_sum(dm) + cF;
+            cF = readlane64(f, 63);
+            F[k] = f;
+        }
+    }
+}
+
+// Exit offset of a segment from entry offset x, following its prefixes F.
+__device__ __forceinline__ int64_t walk_prefixes(const int64_t* F, int64_t T, int64_t x) {
+    int64_t lsp = 0;
+    ChainRun cr{x, 0, 0, -1, INT64_MIN, -1};
+#pragma unroll
+    for (int w = 0; w < NW; ++w) chain_window<false>(F[w * 64 + lane_id()], 0, T, cr, lsp, w, -1);
+    return cr.ref - F[SEG - 1];
+}
+
+// Index of the r-th set bit (r < popcount(m)).
+__device__ __forceinline__ int nth_bit(uint64_t m, int r) {
+    for (; r > 0; --r) m &= m - 1;
+    return ctz64(m);
+}
+
+// Lanes [lo, hi) of wave w as a mask (tile-wide lane indices).
+__device__ __forceinline__ uint64_t range_mask(int w, int lo, int hi) {
+    const int a = lo - w * 64, b = hi - w * 64;
+    const uint64_t ma = a <= 0 ? ~0ull : (a >= 64 ? 0ull : (~0ull << a));
+    const uint64_t mb = b >= 64 ? ~0ull : (b <= 0 ? 0ull : ((1ull << b) - 1));
+    return ma & mb;
+}
+
 // One workgroup per tile of TILE segments (tiles taken in ticket order, so a
 // tile's predecessors are always running or done): exclusive prefix sums and
-// the chain's entry and exit offset of every segment.  Exits that do not
-// depend on the tile's entry (from the first segment with a total map on)
-// are published before the entry is awaited.
+// the chain's entry and exit offset of every segment.
+//
+// Exits of segments with a total map are known at once.  The other segments
+// are resolved in order by one wave (the walker), from the segment after the
+// tile's first total map to the tile end first (their exits do not depend on
+// the tile's entry, so the tile's exit is published before its entry is
+// awaited), then from the tile start.  A SIM segment whose entry lies
+// outside its no-sample interval is followed through its records; the other
+// waves scan those segments' footprint prefixes into an LDS ring ahead of
+// the walker, so each one costs the walker only a pass over LDS.
 __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc, int ntraces, uint64_t ntile_total,
                                                   unsigned long long* ctl) {
     __shared__ unsigned long long s_tk;
     __shared__ int64_t w_sum[3][TWAVES];
-    __shared__ int64_t w_exit[TWAVES];
-    __shared__ int w_ft[TWAVES];
     __shared__ int64_t s_pre[3];
-    __shared__ int64_t s_entry;
     __shared__ int64_t w_peak[TWAVES];
+    __shared__ int64_t m_lo[TILE], m_hi[TILE], m_af[TILE], m_kf[TILE], m_ex[TILE];
+    __shared__ uint64_t w_tot[TWAVES], w_sim[TWAVES];  // valid lanes with TOTAL / SIM maps
+    __shared__ int64_t ring[RING][SEG];
+    __shared__ int r_ready[RING];  // walk-order SIM index held by each slot
+    __shared__ int s_prod, s_cons, s_abort;
+    __shared__ int64_t s_entry;
     const int tid = threadIdx.x, wv = tid >> 6, l = lane_id();
-    if (tid == 0) s_tk = g_add_rtn((uint64_t*)&ctl[2], 1ull);
+    if (tid == 0) {
+        s_tk = g_add_rtn((uint64_t*)&ctl[2], 1ull);
+        s_prod = 0;
+        s_cons = 0;
+        s_abort = 0;
+    }
+    if (tid < RING) r_ready[tid] = -1;
     __syncthreads();
     const uint64_t tk = s_tk;
     if (tk >= ntile_total) return;
     const Desc& D = desc[find_trace_tile(desc, ntraces, tk)];
     const int64_t k = (int64_t)(tk - D.tile_begin);
     const int64_t ns = (int64_t)D.nseg;
-    const int64_t j0 = k * TILE + wv * 64;  // segment of lane 0
-    const int64_t j = j0 + l;
+    const int64_t j = k * TILE + tid;
     const bool valid = j < ns;
+    const int nval = (int)((ns - k * TILE) < TILE ? (ns - k * TILE) : TILE);  // valid lanes
     const StatusView ts{D.tstat, (int64_t)D.ntile};
     const SMP_GLOBAL int64_t* sp = gp(D.seg) + (valid ? j : 0);
-    int64_t af = 0, ap = 0, ac = 0, mxf = 0, mnf = 0, mxp = 0, mnp = 0, kf = 0;
-    int64_t lo = INT64_MIN, hi = INT64_MAX;  // past the trace end: the identity map
+    int64_t af = 0, ap = 0, ac = 0, kf = 0, lo = 0, hi = 0;
     int kind = MAP_CONST;
     if (valid) {
         af = sp[SP_AF * ns];
         ap = sp[SP_AP * ns];
         ac = sp[SP_AC * ns];
-        mxf = sp[SP_MXF * ns];
-        mnf = sp[SP_MNF * ns];
-        mxp = sp[SP_MXP * ns];
-        mnp = sp[SP_MNP * ns];
         lo = sp[SP_LO * ns];
         hi = sp[SP_HI * ns];
         kf = sp[SP_KF * ns];
         kind = (int)(sp[SP_FLG * ns] & 3);
     }
+    m_lo[tid] = lo;
+    m_hi[tid] = hi;
+    m_af[tid] = af;
+    m_kf[tid] = kf;
+    m_ex[tid] = kf;  // final for total maps; the walker overwrites the others
+    const uint64_t tot = ballot(valid && kind == MAP_TOTAL), sim = ballot(valid && kind == MAP_SIM);
     // sums inside the wave
     const int64_t iF = wave_incl_sum(af), iP = wave_incl_sum(ap), iC = wave_incl_sum(ac);
-    // exits that do not depend on the wave's entry: from the first total map on
-    const uint64_t tot = ballot(kind == MAP_TOTAL);
-    const int ft = tot ? ctz64(tot) : 64;
-    int64_t ex = kf;
-    if (ft < 63) {
-        uint64_t m = ~tot & (~0ull << (ft + 1));
-        int64_t x = 0;
-        int prev = -2;
-        while (m) {
-            const int i = ctz64(m);
-            m &= m - 1;
-            const int64_t xin = prev == i - 1 ? x : readlane64(kf, i - 1);
-            x = seg_exit(D, j0 + i, xin, readlane64(lo, i), readlane64(hi, i), readlane64(af, i), readlane64(kf, i),
-                         readlane32(kind, i));
-            if (l == i) ex = x;
-            prev = i;
-        }
-    }
     if (l == 63) {
         w_sum[0][wv] = iF;
         w_sum[1][wv] = iP;
         w_sum[2][wv] = iC;
     }
     if (l == 0) {
-        w_ft[wv] = ft;
-        w_exit[wv] = readlane64(ex, 63);
+        w_tot[wv] = tot;
+        w_sim[wv] = sim;
     }
     __syncthreads();
     int64_t oF = 0, oP = 0, oC = 0, tF = 0, tP = 0, tC = 0;
-    int lc = -1;
+    int ft = nval;  // first lane with a total map
+    for (int w = TWAVES - 1; w >= 0; --w)
+        if (w_tot[w]) ft = w * 64 + ctz64(w_tot[w]);
     for (int w = 0; w < TWAVES; ++w) {
         if (w == wv) {
             oF = tF;
@@ -884,61 +899,145 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
         tF += w_sum[0][w];
         tP += w_sum[1][w];
         tC += w_sum[2][w];
-        if (w_ft[w] < 64) lc = w;
+    }
+    // prefixes relative to the tile start (the tile's own prefix is added at the end)
+    const int64_t rF = oF + iF - af, rP = oP + iP - ap, rC = oC + iC - ac;
+    // SIM segments in walk order: (ft, nval) first, then [0, ft)
+    int nA = 0, nsim = 0;
+    for (int w = 0; w < TWAVES; ++w) {
+        nA += __popcll(w_sim[w] & range_mask(w, ft + 1, nval));
+        nsim += __popcll(w_sim[w]);
     }
     // publish the tile's sums (inclusive right away for the first tile)
     if (tid < 3) st_status(ts.at(W_AF + tid, k), pack(tid == 0 ? tF : (tid == 1 ? tP : tC), 1));
     if (k == 0 && tid < 3) st_status(ts.at(W_IF + tid, k), pack(tid == 0 ? tF : (tid == 1 ? tP : tC), 1));
-    // waves after the last one with a total map continue from its exit
-    if (lc >= 0) {
-        for (int w = lc + 1; w < TWAVES; ++w) {
-            if (wv == w) {
-                const int64_t xo = resolve_lanes(D, j0, 0, 64, w_exit[w - 1], lo, hi, af, kf, kind, ex);
-                if (l == 0) w_exit[w] = xo;
-            }
-            __syncthreads();
-        }
-        if (tid == 0) st_status(ts.at(W_XF, k), pack(w_exit[TWAVES - 1], 1));
-    }
-    // the tile's prefix sums and entry offset
+    const int64_t T = D.T;
+
     if (wv == 0) {
-        int64_t pF = 0, pP = 0, pC = 0, e = 0;
+        // ---- the walker ----
+        int q = 0;  // SIM segments passed, in walk order
         bool ok = true;
-        if (k > 0) {
-            ok = scan_sums(ts, k, pF, pP, pC, ctl);
-            if (l < 3) st_status(ts.at(W_IF + l, k), pack(l == 0 ? pF + tF : (l == 1 ? pP + tP : pC + tC), 1));
-            if (ok) ok = wait_word(ts.at(W_XF, k - 1), e, ctl);
+        auto step = [&](int i, int64_t x) -> int64_t {
+            const bool is_sim = (w_sim[i >> 6] >> (i & 63)) & 1;
+            int64_t r;
+            if (x >= m_lo[i] && x <= m_hi[i]) {
+                r = x - m_af[i];
+            } else if (!is_sim) {
+                r = m_kf[i];
+            } else {
+                r = 0;
+            }
+            if (is_sim) {
+                const int slot = q % RING;
+                Spin sp_;
+                while (__hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != q) {
+                    if (spin_abort(ctl, sp_)) {
+                        ok = false;
+                        break;
+                    }
+                }
+                if (ok && !(x >= m_lo[i] && x <= m_hi[i])) r = walk_prefixes(ring[slot], T, x);
+                ++q;
+                // every lane stores the same value (no lane-0-only region inside the loop)
+                __hip_atomic_store(&s_cons, q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            m_ex[i] = r;
+            return r;
+        };
+        // (ft, nval): entry-independent
+        if (ft < nval) {
+            int64_t x = m_kf[ft];
+            for (int w = ft >> 6; w < TWAVES && ok; ++w) {
+                uint64_t m = ~w_tot[w] & range_mask(w, ft + 1, nval);
+                while (m && ok) {
+                    const int i = w * 64 + ctz64(m);
+                    m &= m - 1;
+                    x = step(i, i > 0 && ((w_tot[(i - 1) >> 6] >> ((i - 1) & 63)) & 1) ? m_kf[i - 1] : x);
+                }
+            }
+            st_status(ts.at(W_XF, k), pack(m_ex[nval - 1], 1));
         }
+        // the tile's entry, then [0, ft)
+        int64_t e = 0;
+        if (k > 0 && ok) ok = wait_word(ts.at(W_XF, k - 1), e, ctl);
+        int64_t x = e;
+        for (int w = 0; w <= ((ft - 1) >> 6) && ft > 0 && ok; ++w) {
+            uint64_t m = ~w_tot[w] & range_mask(w, 0, ft);
+            while (m && ok) {
+                const int i = w * 64 + ctz64(m);
+                m &= m - 1;
+                const int64_t xin = i == 0 ? e : (((w_tot[(i - 1) >> 6] >> ((i - 1) & 63)) & 1) ? m_kf[i - 1] : x);
+                x = step(i, xin);
+            }
+        }
+        if (ft >= nval) st_status(ts.at(W_XF, k), pack(m_ex[nval - 1], 1));
         if (l == 0) {
-            s_pre[0] = pF;
-            s_pre[1] = pP;
-            s_pre[2] = pC;
             s_entry = e;
-            if (!ok) g_or32(&D.scal->err, 8u);
+            if (!ok) {
+                g_or32(&D.scal->err, 8u);
+                __hip_atomic_store(&s_abort, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    } else {
+        if (wv == 1) {
+            // ---- the tile's prefix sums ----
+            int64_t pF = 0, pP = 0, pC = 0;
+            bool ok = true;
+            if (k > 0) {
+                ok = scan_sums(ts, k, pF, pP, pC, ctl);
+                if (l < 3) st_status(ts.at(W_IF + l, k), pack(l == 0 ? pF + tF : (l == 1 ? pP + tP : pC + tC), 1));
+            }
+            if (l == 0) {
+                s_pre[0] = pF;
+                s_pre[1] = pP;
+                s_pre[2] = pC;
+                if (!ok) g_or32(&D.scal->err, 8u);
+            }
+        }
+        // ---- producers: pre-scan SIM segments in walk order ----
+        for (;;) {
+            // every lane takes part (lane 0 adds 1, the others 0): a lane-0-only
+            // region here lets the compiler split the wave across loop trips
+            const int pidx = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_fetch_add(&s_prod, l == 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            if (pidx >= nsim) break;
+            // its lane: the pidx-th SIM lane of (ft, nval), else of [0, ft)
+            int r = pidx < nA ? pidx : pidx - nA;
+            const int rlo = pidx < nA ? ft + 1 : 0, rhi = pidx < nA ? nval : ft;
+            int lane = -1;
+            for (int w = 0; w < TWAVES && lane < 0; ++w) {
+                const uint64_t m = w_sim[w] & range_mask(w, rlo, rhi);
+                const int c = __popcll(m);
+                if (r < c) lane = w * 64 + nth_bit(m, r);
+                else r -= c;
+            }
+            // wait until the walker has freed the slot
+            Spin sp_;
+            bool ok = true;
+            while (__hip_atomic_load(&s_cons, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= pidx - RING) {
+                if (__hip_atomic_load(&s_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ||
+                    spin_abort(ctl, sp_)) {
+                    ok = false;
+                    break;
+                }
+            }
+            if (!ok) break;
+            const int slot = pidx % RING;
+            if (lane >= 0) prescan_segment(D, k * TILE + lane, ring[slot]);
+            __hip_atomic_store(&r_ready[slot], pidx, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
     __syncthreads();
-    // segments before each wave's first total map, in order
-    const int last = lc >= 0 ? lc : TWAVES - 1;
-    for (int w = 0; w <= last; ++w) {
-        if (w > 0 && w_ft[w - 1] == 64) __syncthreads();  // its exit is computed in the previous step
-        if (wv == w) {
-            const int64_t xin = w == 0 ? s_entry : w_exit[w - 1];
-            const int to = w_ft[w];
-            const int64_t xo = resolve_lanes(D, j0, 0, to, xin, lo, hi, af, kf, kind, ex);
-            if (to == 64 && l == 0) w_exit[w] = xo;
-        }
-    }
-    __syncthreads();
-    if (lc < 0 && tid == 0) st_status(ts.at(W_XF, k), pack(w_exit[TWAVES - 1], 1));
-    const int64_t ein = wv == 0 ? s_entry : w_exit[wv - 1];
-    const int64_t ef = wave_shr1(ex, ein);
-    const int64_t F0 = s_pre[0] + oF + iF - af;
-    const int64_t P0 = s_pre[1] + oP + iP - ap;
-    const int64_t C0 = s_pre[2] + oC + iC - ac;
+    const int64_t ef = tid == 0 ? s_entry : m_ex[tid - 1];
+    const int64_t ex = m_ex[tid];
+    const int64_t F0 = s_pre[0] + rF;
+    const int64_t P0 = s_pre[1] + rP;
+    const int64_t C0 = s_pre[2] + rC;
     uint32_t err = 0;
     int64_t pk = 0;
     if (valid) {
+        const int64_t af = sp[SP_AF * ns], ac = sp[SP_AC * ns];
+        const int64_t mxf = sp[SP_MXF * ns], mnf = sp[SP_MNF * ns], mxp = sp[SP_MXP * ns], mnp = sp[SP_MNP * ns];
         SMP_GLOBAL int64_t* o = gp(D.seg) + j;
         o[SP_F0 * ns] = F0;
         o[SP_P0 * ns] = P0;
