@@ -759,7 +759,7 @@ __global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ de
 
 // ------------------------------------------------------------ resolve pass
 
-constexpr int RING = 6;  // SIM segments pre-scanned ahead of the walker
+constexpr int RING = 14;  // SIM segments pre-scanned ahead of the walker (one per producer wave)
 
 // Relative footprint prefixes of segment j into F (one wave; lanes past the
 // segment end hold its last prefix).
