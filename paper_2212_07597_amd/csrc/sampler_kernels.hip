@@ -138,17 +138,14 @@ struct Ev {
     int64_t dm;    // footprint delta
     int64_t dp;    // Python footprint delta
     int64_t dc;    // copy bytes
-    uint32_t ptr;
     bool bad;
     bool aux;      // well-formed copy or timer event
 };
 
-__device__ __forceinline__ Ev decode(uint64_t r0, uint64_t r1, uint64_t r2, bool valid, uint32_t L) {
+__device__ __forceinline__ Ev decode(uint64_t r0, uint32_t line, uint32_t fw, bool valid, uint32_t L) {
     Ev e;
     const int64_t delta = (int64_t)r0;
-    e.ptr = (uint32_t)r1;
-    const uint32_t line = (uint32_t)(r1 >> 32);
-    const uint32_t flags = (uint32_t)(r2 & 0xFF);
+    const uint32_t flags = fw & 0xFF;
     const uint32_t kind = (flags >> 1) & 3;
     const bool py = (flags & 1) == 0;
     const uint64_t shifted = (uint64_t)delta + (kind == 0 ? (uint64_t)(MAX_ABS_DELTA - 1) : 0ull);
@@ -185,30 +182,48 @@ struct SegScan {
     uint32_t err;
 };
 
-// A segment's records in registers: lane l holds records 64w + l.
+// A segment's records in registers: lane l holds records 64w + l.  Only the
+// words a pass uses are loaded (PTR: the pointer word, LINE: the line word;
+// the delta and the flags word always): a loaded word that is never read
+// lets the compiler reuse its register while the load is still in flight,
+// which makes it wait for every load of the segment before the first window.
 struct SegRecs {
-    uint64_t q0[NW], q1[NW], q2[NW];
+    uint64_t d[NW];      // delta
+    uint32_t ptr[NW];    // pointer tag
+    uint32_t line[NW];
+    uint32_t fw[NW];     // flags word (flags in the low byte)
 };
 
-// Issue the loads of one segment's first nv (>= 1) records; lanes past nv
-// re-read record nv-1 (a line already fetched).  All addresses are formed
-// before the first load so that the loads leave back to back.
+typedef const __attribute__((address_space(1))) uint32_t gu32_t;
+
+// Load the words of one record at p into slot w of r.
+template <bool PTR, bool LINE>
+__device__ __forceinline__ void load_record(gu8_t* p, int w, SegRecs& r) {
+    r.d[w] = *(gu64_t*)p;
+    if (PTR) r.ptr[w] = *(gu32_t*)(p + 8);
+    if (LINE) r.line[w] = *(gu32_t*)(p + 12);
+    r.fw[w] = *(gu32_t*)(p + 16);
+}
+
+// Address of lane l's record in window w of a segment at base with nv >= 1
+// records (lanes past nv re-read record nv-1, a line already fetched).
+__device__ __forceinline__ gu8_t* record_addr(gu8_t* base, int nv, int w) {
+    const int k = w * 64 + lane_id();
+    return base + (uint32_t)((k < nv ? k : nv - 1) * 24);
+}
+
+// Issue the loads of one segment's first nv (>= 1) records.  All addresses
+// are formed before the first load so that the loads leave back to back.
+// Plain loads: the nontemporal hint measured 5-7 % slower on this pattern.
+template <bool PTR, bool LINE>
 __device__ __forceinline__ void fetch_segment(const Desc& D, int64_t a, int nv, SegRecs& r) {
-    const int l = lane_id();
     gu8_t* base = (gu8_t*)(D.ev + (size_t)a * 24);  // wave-uniform
-    gu64_t* ptrs[NW];
+    gu8_t* ptrs[NW];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const int k = w * 64 + l;
-        ptrs[w] = (gu64_t*)(base + (uint32_t)((k < nv ? k : nv - 1) * 24));
-    }
+    for (int w = 0; w < NW; ++w) ptrs[w] = record_addr(base, nv, w);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        r.q0[w] = __builtin_nontemporal_load(ptrs[w]);
-        r.q1[w] = __builtin_nontemporal_load(ptrs[w] + 1);
-        r.q2[w] = __builtin_nontemporal_load(ptrs[w] + 2);
-    }
+    for (int w = 0; w < NW; ++w) load_record<PTR, LINE>(ptrs[w], w, r);
     __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -386,6 +401,21 @@ __device__ __forceinline__ bool spin_abort(unsigned long long* ctl, Spin& sp) {
         return true;
     }
     return false;
+}
+
+// A wait on a flag in LDS (set by another wave of the same workgroup) polls
+// with a short sleep and checks the abort word and the budget only every 64
+// polls: the exponential back-off above would add up to a microsecond to
+// every hand-off.
+struct LocalSpin {
+    Spin sp;
+    uint32_t n = 0;
+};
+
+__device__ __forceinline__ bool local_spin_abort(unsigned long long* ctl, LocalSpin& s) {
+    __builtin_amdgcn_s_sleep(1);
+    if ((++s.n & 63) != 0) return false;
+    return spin_abort(ctl, s.sp);
 }
 
 // Wait until a status word is published (wave-uniform address).
@@ -655,7 +685,7 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
     const int64_t a = j * SEG;
     const int nv = seg_events(D, j);
     SegRecs rr;
-    fetch_segment(D, a, nv, rr);
+    fetch_segment<false, true>(D, a, nv, rr);
     const int64_t T = D.T;
     const int64_t two_t = 2 * T - 1;
     int64_t cF = 0, cP = 0, accC = 0;
@@ -669,7 +699,7 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
     for (int w = 0; w < NW; ++w) {
         const int k = w * 64 + l;
         const bool valid = k < nv;
-        const Ev e = decode(rr.q0[w], rr.q1[w], rr.q2[w], valid, D.L);
+        const Ev e = decode(rr.d[w], rr.line[w], rr.fw[w], valid, D.L);
         if (ballot(e.bad)) err |= 1u;
         const uint64_t fm = ballot(e.dm >= two_t || e.dm <= -two_t);
         accC += e.dc;
@@ -771,18 +801,18 @@ __device__ __forceinline__ void prescan_segment(const Desc& D, int64_t j, int64_
     int64_t cF = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        uint64_t q0[NW / 2], q2[NW / 2];
+        uint64_t q0[NW / 2];
+        uint32_t q2[NW / 2];
 #pragma unroll
         for (int w = 0; w < NW / 2; ++w) {
-            const int k = (h * NW / 2 + w) * 64 + l;
-            gu64_t* p = (gu64_t*)(base + (uint32_t)((k < nv ? k : nv - 1) * 24));
-            q0[w] = __builtin_nontemporal_load(p);
-            q2[w] = __builtin_nontemporal_load(p + 2);
+            gu8_t* p = record_addr(base, nv, h * NW / 2 + w);
+            q0[w] = *(gu64_t*)p;
+            q2[w] = *(gu32_t*)(p + 16);
         }
 #pragma unroll
         for (int w = 0; w < NW / 2; ++w) {
             const int k = (h * NW / 2 + w) * 64 + l;
-            const uint32_t fl = (uint32_t)q2[w];
+            const uint32_t fl = q2[w];
             const int64_t dm = (k < nv && (fl & 6u) == 0) ? (int64_t)q0[w] : 0;
             const int64_t f = wave_incl_sum(dm) + cF;
             cF = readlane64(f, 63);
@@ -929,9 +959,9 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
             }
             if (is_sim) {
                 const int slot = q % RING;
-                Spin sp_;
+                LocalSpin sp_;
                 while (__hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != q) {
-                    if (spin_abort(ctl, sp_)) {
+                    if (local_spin_abort(ctl, sp_)) {
                         ok = false;
                         break;
                     }
@@ -1012,11 +1042,11 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                 else r -= c;
             }
             // wait until the walker has freed the slot
-            Spin sp_;
+            LocalSpin sp_;
             bool ok = true;
             while (__hip_atomic_load(&s_cons, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= pidx - RING) {
                 if (__hip_atomic_load(&s_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ||
-                    spin_abort(ctl, sp_)) {
+                    local_spin_abort(ctl, sp_)) {
                     ok = false;
                     break;
                 }
@@ -1115,7 +1145,7 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         const int fwin = fn >= 0 ? fn >> 6 : NW - 1;
         const int nlim = fn >= 0 ? fn + 1 : nv;
         SegRecs rr;
-        fetch_segment(D, a, nlim, rr);
+        fetch_segment<false, false>(D, a, nlim, rr);
         uint32_t err = 0;
         // the chain from the entry, window by window while scanning (prefixes in registers)
         ChainRun cr{eF, 0, 0, -1, INT64_MIN, -1};
@@ -1124,8 +1154,8 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         for (int w = 0; w < NW; ++w) {
             if (w > fwin) break;
             const int k = w * 64 + l;
-            const uint32_t fl = (uint32_t)rr.q2[w];
-            const int64_t dm = (k < nlim && (fl & 6u) == 0) ? (int64_t)rr.q0[w] : 0;
+            const uint32_t fl = rr.fw[w];
+            const int64_t dm = (k < nlim && (fl & 6u) == 0) ? (int64_t)rr.d[w] : 0;
             const int64_t dp = (fl & 1u) ? 0 : dm;
             const int64_t f = wave_incl_sum(dm) + cF;
             const int64_t p = wave_incl_sum(dp) + cP;
@@ -1363,6 +1393,10 @@ __global__ __launch_bounds__(TILE) void k_bscan(const Desc* __restrict__ desc, i
 // attribution, per-line counters, tracked samples and the frees that reclaim
 // them.
 constexpr int STAGE = 128;  // staged sample records per wave
+// The emit pass: four waves per workgroup around one line cache (30 KB of
+// LDS) and at most 96 VGPRs, so five waves share each SIMD.
+constexpr int EMIT_WAVES = 4;
+constexpr int EMIT_BLOCK = EMIT_WAVES * 64;
 
 // Write staged samples [0, cnt) (cnt <= 64) to ranks r0.. and add them to
 // their lines' counters, one sample per lane.
@@ -1381,29 +1415,69 @@ __device__ __forceinline__ void flush_stage(const Desc& D, uint32_t t, const Sam
     }
 }
 
-// Emit one segment g of trace t from its fetched records cur, after issuing
-// the fetch of the wave's next segment into nx (its trace index to tn).
-__device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, uint64_t g, int t,
-                                             HistCache<EMIT_SLOTS>& hc, Sample* stg) {
+// What the emit pass loads for a segment: its records, its plane values
+// (lanes 0-3: F0, P0, C0 (unused), entry offset; lanes 4-9: the scan state
+// before the segment) and its sample masks (lane w: window w).
+// The emit pass carries each window's records from one segment to the next
+// as one 16-byte vector (delta, pointer, line) and the flags word: the
+// registers a refill load writes are then the ones the next segment reads,
+// with no copy (a copy would wait for the load).  pv holds, on lanes 0-3,
+// F0, P0, C0 (unused) and the entry offset, on lanes 4-9 the scan state
+// before the segment, and on lanes 10-17 the sample masks of windows 0-7.
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4), aligned(8)));
+typedef const __attribute__((address_space(1))) v4u32 gv4u32_t;
+
+struct EmitIn {
+    v4u32 q[NW];
+    uint32_t fw[NW];
+    int64_t pv;
+};
+
+__device__ __forceinline__ void emit_load_record(gu8_t* p, int w, EmitIn& in) {
+    in.q[w] = *(gv4u32_t*)p;
+    in.fw[w] = *(gu32_t*)(p + 16);
+}
+
+// A segment of the emit pass: trace t, index j in the trace, nv records.
+struct EmitSeg {
+    int t;
+    int64_t j;
+    int nv;
+};
+
+__device__ __forceinline__ void emit_fetch_meta(const Desc& D, int64_t j, EmitIn& in) {
     const int l = lane_id();
+    const int pl = l < 4 ? SP_F0 + (l == 3 ? SP_EF - SP_F0 : l) : SP_XCNT + (l - 4);
+    gi64_t* src = l < 10 ? (gi64_t*)D.seg + (int64_t)pl * (int64_t)D.nseg + j
+                         : (gi64_t*)D.mask + j * NW + ((l - 10) & (NW - 1));
+    in.pv = *src;
+}
+
+// Emit segment s from in: its samples (staged in stg), the tracked and freed
+// bits of its growth samples and its lines' counters.  When hn, the wave's
+// next segment sn is loaded into in as this one is consumed: its planes at
+// the start, its records window by window as each window's registers free up
+// (so the next segment's loads are in flight while this one computes).
+__device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, const EmitSeg& s, HistCache<EMIT_SLOTS>& hc,
+                                             Sample* stg, EmitIn& in, bool hn, const EmitSeg& sn) {
+    const int l = lane_id();
+    const int t = s.t;
     const Desc& D = desc[t];
-    const int64_t j = (int64_t)(g - D.seg_begin);
-    const int64_t ns = (int64_t)D.nseg;
-    const int64_t a = j * SEG;
-    const int nv = seg_events(D, j);
-    const uint32_t L = D.L;
-    // lanes 0-3: F0, P0, C0 (unused), entry offset; lanes 4-9: state before the segment
-    const int pl_ = l < 4 ? SP_F0 + (l == 3 ? SP_EF - SP_F0 : l) : (l < 10 ? SP_XCNT + (l - 4) : SP_F0);
-    const int64_t pv = seg_val(D, pl_, j);
-    const uint64_t smask_v = ((gu64_t*)D.mask)[j * NW + (l & (NW - 1))];
-    SegRecs cur;
-    fetch_segment(D, a, nv, cur);
+    const int64_t a = s.j * SEG;
+    const int nv = s.nv;
+    const int64_t pv = in.pv;
+    const Desc& Dn = desc[sn.t];
+    gu8_t* nbase = (gu8_t*)(Dn.ev + (size_t)(sn.j * SEG) * 24);  // wave-uniform
     const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), eF = readlane64(pv, 3);
     int64_t base = readlane64(pv, 4);
     const int64_t hv = readlane64(pv, 5);
     const uint32_t hidx = (uint32_t)readlane64(pv, 6), hptr = (uint32_t)readlane64(pv, 7);
     const bool hh = (readlane64(pv, 8) & 1) != 0;
     const int64_t eP = readlane64(pv, 9);
+    uint64_t wm[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) wm[w] = readlaneu64((uint64_t)pv, 10 + w);
+    if (hn) emit_fetch_meta(Dn, sn.j, in);
     uint32_t err = 0;
     if (base < 0 || base > (int64_t)D.n) {  // only reachable after an internal fault
         err |= 8u;
@@ -1424,78 +1498,81 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, uint
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         const int k = w * 64 + l;
-        const uint32_t fl = (uint32_t)cur.q2[w];
-        const int64_t dm = (k < nv && (fl & 6u) == 0) ? (int64_t)cur.q0[w] : 0;
+        const uint32_t fl = in.fw[w];
+        const int64_t dm = (k < nv && (fl & 6u) == 0) ? (int64_t)(((uint64_t)in.q[w].y << 32) | in.q[w].x) : 0;
         const int64_t dp = (fl & 1u) ? 0 : dm;
         const int64_t f = wave_incl_sum(dm) + cF;
         const int64_t p = wave_incl_sum(dp) + cP;
         cF = readlane64(f, 63);
         cP = readlane64(p, 63);
         const uint64_t fm = ballot(dm < 0);
-        const uint64_t m = readlaneu64(smask_v, w);
-        if (m == 0 && (fm == 0 || !cur_has)) continue;
-        const uint64_t plw = cur.q1[w];
-        const uint32_t pt = (uint32_t)plw;
-        const uint64_t below = m & lanemask_lt();
-        uint64_t tmask = 0;
-        if (m) {
-            const int pl = below ? top64(below) : l;
-            int64_t fprev = shfl64(f, pl), pprev = shfl64(p, pl);
-            if (!below) {
-                fprev = refF;
-                pprev = refP;
-            }
-            const bool is_s = ((m >> l) & 1) && k < nv;
-            const int64_t dl = f - fprev;
-            const int64_t pyb = p - pprev;
-            const int64_t nat = dl - pyb;
-            const int64_t Fabs = F0 + f;
-            const int64_t rank = base + cnt + __popcll(below);
-            if (is_s) {
-                Sample smp;
-                smp.event_idx = (uint32_t)(a + k);
-                smp.line = (uint32_t)(plw >> 32);
-                smp.F = Fabs;
-                smp.py = pyb;
-                smp.nat = nat;
-                stg[staged + __popcll(below)] = smp;
-            }
-            uint64_t cand = ballot(is_s && dl > 0 && Fabs > hwm);
-            while (cand) {
-                const int c = ctz64(cand);
-                cand &= cand - 1;
-                const int64_t Fc = readlane64(Fabs, c);
-                if (Fc > hwm) {
-                    hwm = Fc;
-                    tmask |= 1ull << c;
+        const uint64_t m = wm[w];
+        if (m != 0 || (fm != 0 && cur_has)) {
+            const uint32_t pt = in.q[w].z, wline = in.q[w].w;
+            const uint64_t below = m & lanemask_lt();
+            uint64_t tmask = 0;
+            if (m) {
+                const int pl = below ? top64(below) : l;
+                int64_t fprev = shfl64(f, pl), pprev = shfl64(p, pl);
+                if (!below) {
+                    fprev = refF;
+                    pprev = refP;
                 }
+                const bool is_s = ((m >> l) & 1) && k < nv;
+                const int64_t dl = f - fprev;
+                const int64_t pyb = p - pprev;
+                const int64_t nat = dl - pyb;
+                const int64_t Fabs = F0 + f;
+                const int64_t rank = base + cnt + __popcll(below);
+                if (is_s) {
+                    Sample smp;
+                    smp.event_idx = (uint32_t)(a + k);
+                    smp.line = wline;
+                    smp.F = Fabs;
+                    smp.py = pyb;
+                    smp.nat = nat;
+                    stg[staged + __popcll(below)] = smp;
+                }
+                uint64_t cand = ballot(is_s && dl > 0 && Fabs > hwm);
+                while (cand) {
+                    const int c = ctz64(cand);
+                    cand &= cand - 1;
+                    const int64_t Fc = readlane64(Fabs, c);
+                    if (Fc > hwm) {
+                        hwm = Fc;
+                        tmask |= 1ull << c;
+                    }
+                }
+                if (((tmask >> l) & 1) && rank < (int64_t)D.n) {
+                    g_or(&D.tracked_bits[rank >> 6], 1ull << (rank & 63));
+                    gp(D.sample_ptr)[rank] = pt;
+                }
+                const int ls = top64(m);
+                refF = readlane64(f, ls);
+                refP = readlane64(p, ls);
             }
-            if (((tmask >> l) & 1) && rank < (int64_t)D.n) {
-                g_or(&D.tracked_bits[rank >> 6], 1ull << (rank & 63));
-                gp(D.sample_ptr)[rank] = pt;
+            if (fm && (cur_has || tmask)) {
+                const uint64_t tb = tmask & lanemask_lt();
+                const int al = tb ? top64(tb) : l;
+                const uint32_t spt = (uint32_t)shfl32((int)pt, al);
+                const uint32_t aptr = tb ? spt : cur_ptr;
+                const uint32_t aidx = tb ? (uint32_t)(a + w * 64 + al) : cur_idx;
+                const bool ahas = tb != 0 || cur_has;
+                if (((fm >> l) & 1) && ahas && pt == aptr && aidx < D.n)
+                    g_or(&D.freed_bits[aidx >> 6], 1ull << (aidx & 63));
             }
-            const int ls = top64(m);
-            refF = readlane64(f, ls);
-            refP = readlane64(p, ls);
+            if (tmask) {
+                const int tl = top64(tmask);
+                cur_ptr = (uint32_t)readlane32((int)pt, tl);
+                cur_idx = (uint32_t)(a + w * 64 + tl);
+                cur_has = true;
+            }
+            cnt += __popcll(m);
+            staged += __popcll(m);
         }
-        if (fm && (cur_has || tmask)) {
-            const uint64_t tb = tmask & lanemask_lt();
-            const int al = tb ? top64(tb) : l;
-            const uint32_t spt = (uint32_t)shfl32((int)pt, al);
-            const uint32_t aptr = tb ? spt : cur_ptr;
-            const uint32_t aidx = tb ? (uint32_t)(a + w * 64 + al) : cur_idx;
-            const bool ahas = tb != 0 || cur_has;
-            if (((fm >> l) & 1) && ahas && pt == aptr && aidx < D.n)
-                g_or(&D.freed_bits[aidx >> 6], 1ull << (aidx & 63));
-        }
-        if (tmask) {
-            const int tl = top64(tmask);
-            cur_ptr = (uint32_t)readlane32((int)pt, tl);
-            cur_idx = (uint32_t)(a + w * 64 + tl);
-            cur_has = true;
-        }
-        cnt += __popcll(m);
-        staged += __popcll(m);
+        // this window's registers take the next segment's window w (after
+        // their last use here, so no copies and no early wait)
+        if (hn) emit_load_record(record_addr(nbase, sn.nv, w), w, in);
         if (staged >= 64) {
             flush_stage(D, (uint32_t)t, stg, 64, stage_rank, hc);
             stage_rank += 64;
@@ -1509,17 +1586,42 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, uint
     if (err && l == 0) g_or32(&D.scal->err, err);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_emit(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
+__global__ __launch_bounds__(EMIT_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_emit(
+    const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
     __shared__ HistCache<EMIT_SLOTS> hc;
-    __shared__ Sample stage[WAVES][STAGE];
+    __shared__ Sample stage[EMIT_WAVES][STAGE];
     hist_init(hc);
     __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    // Segments are taken grid-stride (consecutive waves, consecutive segments).
-    int t = 0;
-    for (uint64_t g = (uint64_t)blockIdx.x * WAVES + wv; g < nseg_total; g += (uint64_t)gridDim.x * WAVES) {
-        t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, t, ntraces, g));
-        emit_segment(desc, g, t, hc, stage[wv]);
+    // Segments are taken grid-stride (consecutive waves, consecutive
+    // segments); each wave loads its next segment while it emits the current.
+    const uint64_t stride = (uint64_t)gridDim.x * EMIT_WAVES;
+    uint64_t g = (uint64_t)blockIdx.x * EMIT_WAVES + wv;
+    if (g < nseg_total) {
+        auto locate = [&](uint64_t x, int from) {
+            EmitSeg r;
+            r.t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, from, ntraces, x));
+            r.j = (int64_t)(x - desc[r.t].seg_begin);
+            r.nv = seg_events(desc[r.t], r.j);
+            return r;
+        };
+        EmitSeg s = locate(g, 0);
+        EmitIn in;
+        emit_fetch_meta(desc[s.t], s.j, in);
+        {
+            gu8_t* base = (gu8_t*)(desc[s.t].ev + (size_t)(s.j * SEG) * 24);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) emit_load_record(record_addr(base, s.nv, w), w, in);
+        }
+        for (;;) {
+            const uint64_t gn = g + stride;
+            const bool hn = gn < nseg_total;
+            const EmitSeg sn = hn ? locate(gn, s.t) : s;
+            emit_segment(desc, s, hc, stage[wv], in, hn, sn);
+            if (!hn) break;
+            g = gn;
+            s = sn;
+        }
     }
     __syncthreads();
     hist_flush(hc, desc);
@@ -1760,7 +1862,7 @@ static int occupancy_grid(const void* fn, int block) {
 }
 
 int chain_grid_limit() { return occupancy_grid((const void*)k_chain, BLOCK); }
-int emit_grid_limit() { return occupancy_grid((const void*)k_emit, BLOCK); }
+int emit_grid_limit() { return occupancy_grid((const void*)k_emit, EMIT_BLOCK); }
 
 hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, unsigned long long* ctl, hipStream_t s) {
     const uint64_t blocks = (total_bytes + (1ull << 16) - 1) >> 16;
@@ -1778,7 +1880,12 @@ hipError_t launch_pass(int pass, const Desc* desc, int ntraces, uint64_t nseg_to
         case 1: k_resolve<<<dim3((unsigned)ntile_total), dim3(TILE), 0, s>>>(desc, ntraces, ntile_total, ctl); break;
         case 2: k_chain<<<dim3(pgrid), dim3(BLOCK), 0, s>>>(desc, ntraces, nseg_total); break;
         case 3: k_bscan<<<dim3((unsigned)ntile_total), dim3(TILE), 0, s>>>(desc, ntraces, ntile_total, ctl); break;
-        default: k_emit<<<dim3(pgrid), dim3(BLOCK), 0, s>>>(desc, ntraces, nseg_total); break;
+        default: {
+            const uint64_t ewgs = (nseg_total + EMIT_WAVES - 1) / EMIT_WAVES;
+            const unsigned egrid = (unsigned)(ewgs < (uint64_t)grid_limit ? ewgs : (uint64_t)grid_limit);
+            k_emit<<<dim3(egrid), dim3(EMIT_BLOCK), 0, s>>>(desc, ntraces, nseg_total);
+            break;
+        }
     }
     return hipGetLastError();
 }
