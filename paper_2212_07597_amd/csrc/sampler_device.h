@@ -42,9 +42,11 @@ enum {
     // bit 2 = copy or timer events present), and the chain after the first forced sample, which is
     // the same for every entry: its node (-1 if none), samples after it, best growth sample after
     // it (value, node or -1), largest sampled footprint after it, last sample node after it (or -1)
-    // and the Python footprint there (relative values), and the forced window's sample mask after it
+    // and the Python footprint there (relative values), the forced window's sample mask after it,
+    // the entry offsets [PLO, PHI] that take no sample before it, and the footprint and Python
+    // footprint at it
     SP_AF = 0, SP_AP, SP_AC, SP_MXF, SP_MNF, SP_MXP, SP_MNP, SP_LO, SP_HI, SP_KF, SP_FLG,
-    SP_FN, SP_ACNT, SP_AGV, SP_AGN, SP_ASMX, SP_ALS, SP_ALP, SP_AMF,
+    SP_FN, SP_ACNT, SP_AGV, SP_AGN, SP_ASMX, SP_ALS, SP_ALP, SP_AMF, SP_PLO, SP_PHI, SP_FFN, SP_PFN,
     // resolve pass: exclusive prefixes, entry and exit offsets of the chain
     SP_F0, SP_P0, SP_C0, SP_EF, SP_XF,
     // chain pass: samples, best growth sample (value, event, ptr), Python footprint at the last sample, flags
@@ -229,6 +231,25 @@ __device__ __forceinline__ int64_t wave_incl_sum(int64_t x) {
 }
 __device__ __forceinline__ int64_t wave_incl_max(int64_t x) { return wave_scan<OpMax>(x); }
 __device__ __forceinline__ int64_t wave_incl_min(int64_t x) { return wave_scan<OpMin>(x); }
+
+// 32-bit max / min over the wave (DPP steps as in wave_scan, result broadcast).
+template <bool MAX>
+__device__ __forceinline__ int32_t wave_ext32(int32_t x) {
+    const int32_t id = MAX ? INT32_MIN : INT32_MAX;
+#define EXT32_STEP(CTRL, ROWS)                                                            \
+    {                                                                                     \
+        const int32_t y = __builtin_amdgcn_update_dpp(id, x, CTRL, ROWS, 0xf, false);     \
+        x = MAX ? (x > y ? x : y) : (x < y ? x : y);                                      \
+    }
+    EXT32_STEP(0x111, 0xf)
+    EXT32_STEP(0x112, 0xf)
+    EXT32_STEP(0x114, 0xf)
+    EXT32_STEP(0x118, 0xf)
+    EXT32_STEP(0x142, 0xa)
+    EXT32_STEP(0x143, 0xc)
+#undef EXT32_STEP
+    return __builtin_amdgcn_readlane(x, 63);
+}
 
 // value of the previous lane (lane 0 gets `old`)
 __device__ __forceinline__ int64_t wave_shr1(int64_t x, int64_t old) {

@@ -693,6 +693,7 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
     bool any_aux = false;
     uint32_t err = 0;
     int fnode = -1;
+    int64_t plo = -T + 1, phi = T - 1, ffn = 0, pfn = 0;
     ChainRun r{0, 0, 0, -1, INT64_MIN, -1};
     int64_t alp = 0;
 #pragma unroll
@@ -709,19 +710,40 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
         cF = readlane64(f, 63);
         cP = readlane64(p, 63);
         lF_[k] = f;
+        if (fnode < 0 && fm) {
+            // The first forced event: entries in [plo, phi] take no sample
+            // before it (the prefix's extremes: earlier windows, then the
+            // lanes before it in this one).
+            const int fl = ctz64(fm);
+            fnode = w * 64 + fl;
+            if (fnode > 0) {
+                int64_t pmx, pmn;
+                if (w == 0 && !ballot(l < fl && (f > INT32_MAX || f < INT32_MIN))) {
+                    // the usual case: a first-window prefix of 32-bit values
+                    pmx = wave_ext32<true>(l < fl ? (int32_t)f : INT32_MIN);
+                    pmn = wave_ext32<false>(l < fl ? (int32_t)f : INT32_MAX);
+                } else {
+                    pmx = wave_max(l < fl && f > mxF ? f : mxF);
+                    pmn = wave_min(l < fl && f < mnF ? f : mnF);
+                }
+                plo = pmx > 0 ? pmx - T + 1 : -T + 1;
+                phi = pmn < 0 ? pmn + T - 1 : T - 1;
+            }
+            ffn = readlane64(f, fl);
+            pfn = readlane64(p, fl);
+            r.ref = ffn;
+        }
         if (valid) {
             mxF = f > mxF ? f : mxF;
             mnF = f < mnF ? f : mnF;
             mxP = p > mxP ? p : mxP;
             mnP = p < mnP ? p : mnP;
         }
-        if (fnode >= 0) {
+        if (fnode >= w * 64) {
+            // the chain from the forced event (the same for every entry)
+            chain_window<true>(f, p, T, r, alp, w, fnode - w * 64);
+        } else if (fnode >= 0) {
             chain_window<true>(f, p, T, r, alp, w, -1);
-        } else if (fm) {
-            const int fl = ctz64(fm);
-            fnode = w * 64 + fl;
-            r.ref = readlane64(f, fl);
-            chain_window<true>(f, p, T, r, alp, w, fl);
         }
     }
     SegScan sc;
@@ -746,7 +768,7 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
     }
     const int64_t acnt = wave_sum(l < NW ? (int64_t)__popcll(r.mvec) : 0);
     const int64_t amf = fnode >= 0 ? (int64_t)readlaneu64(r.mvec, fnode >> 6) : 0;
-    if (l <= SP_AMF) {
+    if (l <= SP_PFN) {
         int64_t v;
         switch (l) {
             case SP_AF: v = sc.sumF; break;
@@ -767,7 +789,11 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
             case SP_ASMX: v = r.smax; break;
             case SP_ALS: v = r.lastS; break;
             case SP_ALP: v = r.lastS >= 0 ? alp : 0; break;
-            default: v = amf; break;
+            case SP_AMF: v = amf; break;
+            case SP_PLO: v = plo; break;
+            case SP_PHI: v = phi; break;
+            case SP_FFN: v = ffn; break;
+            default: v = pfn; break;
         }
         gp(D.seg)[(int64_t)l * (int64_t)D.nseg + j] = v;
     }
@@ -1105,10 +1131,11 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
     int cur_t = 0;
     int64_t peakS = 0;
     bool have_t = false;
-    // lanes 0-4: prefixes, entry and exit from the resolve pass; lanes 5-13:
-    // flags and the chain after the first forced sample from the summary
-    // pass.  Each wave reads them one segment ahead.
-    const int pl_ = l < 5 ? SP_F0 + l : (l == 5 ? SP_FLG : (l < 14 ? SP_FN + (l - 6) : SP_F0));
+    // lanes 0-4: prefixes, entry and exit from the resolve pass; lanes 5-17:
+    // flags, the chain after the first forced sample and the entries that
+    // take no sample before it, from the summary pass.  Each wave reads them
+    // one segment ahead.
+    const int pl_ = l < 5 ? SP_F0 + l : (l == 5 ? SP_FLG : (l < 18 ? SP_FN + (l - 6) : SP_F0));
     const uint64_t stride = (uint64_t)gridDim.x * WAVES;
     uint64_t g = (uint64_t)blockIdx.x * WAVES + wv;
     int64_t pv_next = 0;
@@ -1144,24 +1171,40 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         // so only the events up to it are read again.
         const int fwin = fn >= 0 ? fn >> 6 : NW - 1;
         const int nlim = fn >= 0 ? fn + 1 : nv;
-        SegRecs rr;
-        fetch_segment<false, false>(D, a, nlim, rr);
         uint32_t err = 0;
-        // the chain from the entry, window by window while scanning (prefixes in registers)
         ChainRun cr{eF, 0, 0, -1, INT64_MIN, -1};
         int64_t lsp = 0, cF = 0, cP = 0;
+        const int64_t plo = readlane64(pv, 14), phi = readlane64(pv, 15);
+        if (fn >= 0 && eF >= plo && eF <= phi) {
+            // No sample before the forced event: the prefix's chain is that
+            // event's sample alone, known from the summary pass.
+            const int64_t ffn = readlane64(pv, 16);
+            if (ffn > eF) {
+                cr.gbest = ffn;
+                cr.gnode = fn;
+            }
+            cr.smax = ffn;
+            cr.lastS = fn;
+            cr.ref = ffn;
+            if (l == fwin) cr.mvec = 1ull << (fn & 63);
+            lsp = readlane64(pv, 17);
+        } else {
+            // the chain from the entry, window by window while scanning (prefixes in registers)
+            SegRecs rr;
+            fetch_segment<false, false>(D, a, nlim, rr);
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            if (w > fwin) break;
-            const int k = w * 64 + l;
-            const uint32_t fl = rr.fw[w];
-            const int64_t dm = (k < nlim && (fl & 6u) == 0) ? (int64_t)rr.d[w] : 0;
-            const int64_t dp = (fl & 1u) ? 0 : dm;
-            const int64_t f = wave_incl_sum(dm) + cF;
-            const int64_t p = wave_incl_sum(dp) + cP;
-            cF = readlane64(f, 63);
-            cP = readlane64(p, 63);
-            chain_window<true>(f, p, T, cr, lsp, w, -1);
+            for (int w = 0; w < NW; ++w) {
+                if (w > fwin) break;
+                const int k = w * 64 + l;
+                const uint32_t fl = rr.fw[w];
+                const int64_t dm = (k < nlim && (fl & 6u) == 0) ? (int64_t)rr.d[w] : 0;
+                const int64_t dp = (fl & 1u) ? 0 : dm;
+                const int64_t f = wave_incl_sum(dm) + cF;
+                const int64_t p = wave_incl_sum(dp) + cP;
+                cF = readlane64(f, 63);
+                cP = readlane64(p, 63);
+                chain_window<true>(f, p, T, cr, lsp, w, -1);
+            }
         }
 
         // Copy volume (section 3.5: one Tc sample per multiple of Tc crossed by
