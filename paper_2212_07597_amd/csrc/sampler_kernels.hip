@@ -847,13 +847,24 @@ __device__ __forceinline__ void prescan_segment(const Desc& D, int64_t j, int64_
     }
 }
 
-// Exit offset of a segment from entry offset x, following its prefixes F.
+// Exit offset of a segment from entry offset x, following its prefixes F
+// window by window (read four windows at a time, so that the LDS reads
+// overlap).  A round-based search over all windows at once measured slower:
+// walked segments often hold many samples.
 __device__ __forceinline__ int64_t walk_prefixes(const int64_t* F, int64_t T, int64_t x) {
+    const int l = lane_id();
+    const int64_t fend = F[SEG - 1];
     int64_t lsp = 0;
     ChainRun cr{x, 0, 0, -1, INT64_MIN, -1};
 #pragma unroll
-    for (int w = 0; w < NW; ++w) chain_window<false>(F[w * 64 + lane_id()], 0, T, cr, lsp, w, -1);
-    return cr.ref - F[SEG - 1];
+    for (int h = 0; h < NW; h += 4) {
+        int64_t f[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) f[w] = F[(h + w) * 64 + l];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) chain_window<false>(f[w], 0, T, cr, lsp, h + w, -1);
+    }
+    return cr.ref - fend;
 }
 
 // Index of the r-th set bit (r < popcount(m)).
@@ -878,10 +889,12 @@ __device__ __forceinline__ uint64_t range_mask(int w, int lo, int hi) {
 // are resolved in order by one wave (the walker), from the segment after the
 // tile's first total map to the tile end first (their exits do not depend on
 // the tile's entry, so the tile's exit is published before its entry is
-// awaited), then from the tile start.  A SIM segment whose entry lies
-// outside its no-sample interval is followed through its records; the other
-// waves scan those segments' footprint prefixes into an LDS ring ahead of
-// the walker, so each one costs the walker only a pass over LDS.
+// awaited), then from the tile start; the walker takes 64 segments per step
+// and stops only at segments whose entry lies outside their no-sample
+// interval.  A SIM segment where it stops is followed through its records;
+// the other waves scan the SIM segments' footprint prefixes into an LDS ring
+// ahead of the walker (skipping those it has already passed), so each one
+// costs the walker only a pass over LDS.
 __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc, int ntraces, uint64_t ntile_total,
                                                   unsigned long long* ctl) {
     __shared__ unsigned long long s_tk;
@@ -973,60 +986,78 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
         // ---- the walker ----
         int q = 0;  // SIM segments passed, in walk order
         bool ok = true;
-        auto step = [&](int i, int64_t x) -> int64_t {
-            const bool is_sim = (w_sim[i >> 6] >> (i & 63)) & 1;
-            int64_t r;
-            if (x >= m_lo[i] && x <= m_hi[i]) {
-                r = x - m_af[i];
-            } else if (!is_sim) {
-                r = m_kf[i];
-            } else {
-                r = 0;
-            }
-            if (is_sim) {
-                const int slot = q % RING;
-                LocalSpin sp_;
-                while (__hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != q) {
-                    if (local_spin_abort(ctl, sp_)) {
-                        ok = false;
-                        break;
+        // Follow the chain through segments [b, e) of the tile from entry
+        // offset x and return the exit.  64 segments at a time, one per lane,
+        // with S the group's exclusive sums of af.  A segment with a total
+        // map always exits at kf; after the last such segment j before lane
+        // i the entry of i is kf_j - (S_i - S_j - af_j), and before any, from
+        // a position i0 with entry x, it is x - (S_i - S_i0) -- as long as no
+        // other segment in between changes the chain.  So one ballot finds
+        // the next segment whose entry lies outside its no-sample interval
+        // [lo, hi], and only that one needs work (its constant exit, or a
+        // walk through its pre-scanned prefixes).  Modular arithmetic: exact
+        // wherever the entry is in (-T, T), as it is up to that segment.
+        auto walk = [&](int b, int e, int64_t x) -> int64_t {
+            for (int g0 = b & ~63; g0 < e && ok; g0 += 64) {
+                const int i = g0 + l;
+                const int64_t lo = m_lo[i], hi = m_hi[i], af = m_af[i], kf = m_kf[i];
+                const uint64_t sim = w_sim[g0 >> 6], tot = w_tot[g0 >> 6];
+                const bool is_tot = (tot >> l) & 1;
+                const int64_t S = (int64_t)((uint64_t)wave_incl_sum(af) - (uint64_t)af);
+                // the last total-map lane before this one, and the entry it gives
+                const uint64_t tb = tot & lanemask_lt();
+                const int jl = tb ? top64(tb) : -1;
+                const int64_t rj = (int64_t)((uint64_t)kf + (uint64_t)S + (uint64_t)af);  // kf_j + S_(j+1) on lane j
+                const int64_t xt = (int64_t)((uint64_t)shfl64(rj, jl < 0 ? l : jl) - (uint64_t)S);
+                const int ge = e - g0 < 64 ? e - g0 : 64;
+                int i0 = b > g0 ? b - g0 : 0;
+                while (i0 < ge) {
+                    const int64_t xi = jl >= i0 ? xt : (int64_t)((uint64_t)x - ((uint64_t)S - (uint64_t)readlane64(S, i0)));
+                    const uint64_t fire = ballot(l >= i0 && l < ge && !is_tot && !(xi >= lo && xi <= hi));
+                    const int stop = fire ? ctz64(fire) : ge;
+                    const int64_t xo = is_tot ? kf : (int64_t)((uint64_t)xi - (uint64_t)af);
+                    if (l >= i0 && l < stop && !is_tot) m_ex[i] = xo;
+                    q += __popcll(sim & range_mask(0, i0, stop));
+                    // release the slots passed over before any wait below (a
+                    // producer may be waiting for them); every lane stores the
+                    // same value (no lane-0-only region inside the loop)
+                    __hip_atomic_store(&s_cons, q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (stop > i0) x = readlane64(xo, stop - 1);
+                    if (stop < ge) {
+                        const int64_t xs = readlane64(xi, stop);
+                        int64_t r = readlane64(kf, stop);
+                        if ((sim >> stop) & 1) {
+                            const int slot = q % RING;
+                            LocalSpin sp_;
+                            while (__hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != q) {
+                                if (local_spin_abort(ctl, sp_)) {
+                                    ok = false;
+                                    break;
+                                }
+                            }
+                            r = ok ? walk_prefixes(ring[slot], T, xs) : 0;
+                            ++q;
+                            __hip_atomic_store(&s_cons, q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                        if (l == stop) m_ex[i] = r;
+                        x = r;
                     }
+                    i0 = stop + 1;
+                    if (!ok) break;
                 }
-                if (ok && !(x >= m_lo[i] && x <= m_hi[i])) r = walk_prefixes(ring[slot], T, x);
-                ++q;
-                // every lane stores the same value (no lane-0-only region inside the loop)
-                __hip_atomic_store(&s_cons, q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            m_ex[i] = r;
-            return r;
+            return x;
         };
         // (ft, nval): entry-independent
         if (ft < nval) {
-            int64_t x = m_kf[ft];
-            for (int w = ft >> 6; w < TWAVES && ok; ++w) {
-                uint64_t m = ~w_tot[w] & range_mask(w, ft + 1, nval);
-                while (m && ok) {
-                    const int i = w * 64 + ctz64(m);
-                    m &= m - 1;
-                    x = step(i, i > 0 && ((w_tot[(i - 1) >> 6] >> ((i - 1) & 63)) & 1) ? m_kf[i - 1] : x);
-                }
-            }
-            st_status(ts.at(W_XF, k), pack(m_ex[nval - 1], 1));
+            const int64_t xa = walk(ft + 1, nval, m_kf[ft]);
+            st_status(ts.at(W_XF, k), pack(xa, 1));
         }
         // the tile's entry, then [0, ft)
         int64_t e = 0;
         if (k > 0 && ok) ok = wait_word(ts.at(W_XF, k - 1), e, ctl);
-        int64_t x = e;
-        for (int w = 0; w <= ((ft - 1) >> 6) && ft > 0 && ok; ++w) {
-            uint64_t m = ~w_tot[w] & range_mask(w, 0, ft);
-            while (m && ok) {
-                const int i = w * 64 + ctz64(m);
-                m &= m - 1;
-                const int64_t xin = i == 0 ? e : (((w_tot[(i - 1) >> 6] >> ((i - 1) & 63)) & 1) ? m_kf[i - 1] : x);
-                x = step(i, xin);
-            }
-        }
-        if (ft >= nval) st_status(ts.at(W_XF, k), pack(m_ex[nval - 1], 1));
+        const int64_t xb = ok ? walk(0, ft, e) : 0;
+        if (ft >= nval) st_status(ts.at(W_XF, k), pack(xb, 1));
         if (l == 0) {
             s_entry = e;
             if (!ok) {
@@ -1067,10 +1098,15 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                 if (r < c) lane = w * 64 + nth_bit(m, r);
                 else r -= c;
             }
-            // wait until the walker has freed the slot
+            // Wait until the slot is free: the walker has passed its previous
+            // occupant (it may pass one without reading it) and that
+            // occupant's producer has finished writing.
+            const int slot = pidx % RING;
             LocalSpin sp_;
             bool ok = true;
-            while (__hip_atomic_load(&s_cons, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= pidx - RING) {
+            while (__hip_atomic_load(&s_cons, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= pidx - RING ||
+                   (pidx >= RING &&
+                    __hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != pidx - RING)) {
                 if (__hip_atomic_load(&s_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ||
                     local_spin_abort(ctl, sp_)) {
                     ok = false;
@@ -1078,8 +1114,9 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                 }
             }
             if (!ok) break;
-            const int slot = pidx % RING;
-            if (lane >= 0) prescan_segment(D, k * TILE + lane, ring[slot]);
+            // a segment the walker has already passed is not scanned
+            if (lane >= 0 && __hip_atomic_load(&s_cons, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= pidx)
+                prescan_segment(D, k * TILE + lane, ring[slot]);
             __hip_atomic_store(&r_ready[slot], pidx, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
