@@ -215,13 +215,24 @@ SMP_API int trace_device_results(smp_sampler_t *s, uint64_t trace_id, void **sam
 
 /* Timing of the last run() (milliseconds, HIP events on the launch's
  * stream): the five sampling passes together (summarize, resolve, chain,
- * scan, emit), and the whole launch sequence including clearing, the
- * tracked-list compaction and the leak rationals. */
+ * scan, emit; -1 unless the events before the first and after the last pass
+ * are recorded, see sampler_set_pass_events), and the whole launch sequence
+ * including clearing, the tracked-list compaction and the leak rationals
+ * (-1 unless the start event is recorded). */
 SMP_API int sampler_last_timing(smp_sampler_t *s, float *main_kernel_ms, float *total_ms);
+
+/* Which timing events later runs record: bit p (0-4) = the event before
+ * sampling pass p, bit 5 = the event after the last pass, bit 6 = the
+ * launch's start event (total_ms of sampler_last_timing).  Default 0x7F
+ * (all).  Each event between two kernels idles the GPU for a few
+ * microseconds, so a timed loop may keep only the two around the pass it
+ * measures (0x30: the emit pass).  Returns SMP_EINVAL for bits above 6. */
+SMP_API int sampler_set_pass_events(smp_sampler_t *s, uint32_t mask);
 
 /* Per-pass timing of the last run(): pass_ms[0..4] = summarize, resolve,
  * chain, scan, emit (milliseconds, HIP events around each kernel on the
- * launch's stream).  pass_ms must hold 5 floats. */
+ * launch's stream; -1 for a pass whose two events were not recorded).
+ * pass_ms must hold 5 floats. */
 SMP_API int sampler_last_pass_timing(smp_sampler_t *s, float *pass_ms);
 
 /* Diagnostics: the 32 control words of the last launch (word 1: abort flag,

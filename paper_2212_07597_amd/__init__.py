@@ -29,7 +29,7 @@ SAMPLE_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("F", "<i8"), ("
 TRACKED_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("ptr", "<u4"), ("freed", "<u4")])
 
 EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", "fetch_profile",
-            "trace_device_results", "sampler_last_timing", "sampler_last_pass_timing", "sampler_last_counters",
+            "trace_device_results", "sampler_last_timing", "sampler_set_pass_events", "sampler_last_pass_timing", "sampler_last_counters",
             "sampler_fixed_bytes", "sampler_destroy", "error_string")
 
 PASS_NAMES = ("summarize", "resolve", "chain", "scan", "emit")
@@ -108,6 +108,8 @@ def lib():
         L.sampler_last_timing.restype = i32
         L.sampler_last_pass_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
         L.sampler_last_pass_timing.restype = i32
+        L.sampler_set_pass_events.argtypes = [vp, ctypes.c_uint32]
+        L.sampler_set_pass_events.restype = i32
         L.sampler_last_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
         L.sampler_last_counters.restype = i32
         L.sampler_fixed_bytes.argtypes = []
@@ -257,8 +259,15 @@ class Sampler:
         _check("sampler_last_timing", lib().sampler_last_timing(self.h, ctypes.byref(a), ctypes.byref(b)))
         return float(a.value), float(b.value)
 
+    def set_pass_events(self, mask):
+        """Which timing events later runs record (bit p: before sampling pass
+        p, bit 5: after the last pass, bit 6: the launch's start); default
+        0x7F."""
+        _check("sampler_set_pass_events", lib().sampler_set_pass_events(self.h, mask))
+
     def last_pass_timing(self):
-        """Milliseconds of each sampling pass of the last run, by PASS_NAMES."""
+        """Milliseconds of each sampling pass of the last run, by PASS_NAMES
+        (-1 for a pass whose events were not recorded)."""
         buf = (ctypes.c_float * len(PASS_NAMES))()
         _check("sampler_last_pass_timing", lib().sampler_last_pass_timing(self.h, buf))
         return dict(zip(PASS_NAMES, (float(x) for x in buf)))

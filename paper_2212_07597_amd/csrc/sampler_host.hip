@@ -151,9 +151,16 @@ struct TraceRec {
     Scalars scal{};
 };
 
+// Timing events: bit p (0-4) the event before pass p, bit 5 the event after
+// the last pass, bit 6 the launch's start event.
+constexpr uint32_t PASS_EVENTS_ALL = 0x7F;
+constexpr int START_EVENT_BIT = NPASS + 1;
+
 struct RunSlot {
     Desc* host_desc = nullptr;   // pinned staging
     Desc* dev_desc = nullptr;
+    Desc* last_desc = nullptr;   // what dev_desc holds (host copy), to skip an unchanged upload
+    size_t last_cnt = 0;
     Scalars* dev_scal = nullptr;   // every trace's scalars, gathered after the launch
     Scalars* host_scal = nullptr;  // pinned copy of dev_scal
     std::vector<uint64_t> ids;     // the launch's traces, in descriptor order
@@ -162,6 +169,7 @@ struct RunSlot {
     hipEvent_t e_ready = nullptr;  // recorded on the caller's stream at run()
     hipEvent_t e_start = nullptr, e_end = nullptr;
     hipEvent_t e_pass[NPASS + 1] = {};  // around each pass of the sampling kernels
+    uint32_t ev_mask = 0;               // which e_pass events this launch recorded
     bool busy = false;
     uint64_t seq = 0;
 };
@@ -185,6 +193,7 @@ struct smp_sampler {
     bool failed = false;
     float last_main_ms = 0, last_total_ms = 0;
     float last_pass_ms[NPASS] = {};
+    uint32_t pass_events = PASS_EVENTS_ALL;  // timing events to record (all by default)
     uint64_t last_seq = 0;
 };
 
@@ -242,10 +251,15 @@ int fail(smp_sampler* s) {
 int retire_slot(smp_sampler* s, RunSlot& r) {
     if (!r.busy) return SMP_OK;
     HIPCHK(hipEventSynchronize(r.e_end));
-    float a = 0, b = 0, p[NPASS] = {};
-    HIPCHK(hipEventElapsedTime(&a, r.e_pass[0], r.e_pass[NPASS]));
-    HIPCHK(hipEventElapsedTime(&b, r.e_start, r.e_end));
-    for (int i = 0; i < NPASS; ++i) HIPCHK(hipEventElapsedTime(&p[i], r.e_pass[i], r.e_pass[i + 1]));
+    // intervals whose two events were not recorded read -1
+    float a = -1, b = -1, p[NPASS];
+    const uint32_t m = r.ev_mask;
+    if ((m & 1u) && ((m >> NPASS) & 1u)) HIPCHK(hipEventElapsedTime(&a, r.e_pass[0], r.e_pass[NPASS]));
+    if ((m >> START_EVENT_BIT) & 1u) HIPCHK(hipEventElapsedTime(&b, r.e_start, r.e_end));
+    for (int i = 0; i < NPASS; ++i) {
+        p[i] = -1;
+        if (((m >> i) & 1u) && ((m >> (i + 1)) & 1u)) HIPCHK(hipEventElapsedTime(&p[i], r.e_pass[i], r.e_pass[i + 1]));
+    }
     if (r.seq >= s->last_seq) {
         s->last_seq = r.seq;
         s->last_main_ms = a;
@@ -320,7 +334,8 @@ int sampler_create(int device, void* hip_stream, uint64_t mem_budget, void* work
             hipHostMalloc((void**)&r.host_scal, sizeof(Scalars) * MAX_TRACES_PER_RUN, hipHostMallocDefault) != hipSuccess ||
             hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&r.e_ready, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreate(&r.e_start) != hipSuccess || hipEventCreate(&r.e_end) != hipSuccess) {
+            hipEventCreate(&r.e_start) != hipSuccess || hipEventCreate(&r.e_end) != hipSuccess ||
+            !(r.last_desc = new (std::nothrow) Desc[MAX_TRACES_PER_RUN])) {
             sampler_destroy(s);
             return SMP_EDEVICE;
         }
@@ -349,6 +364,8 @@ void sampler_destroy(smp_sampler_t* s) {
     }
     for (auto& r : s->slots) {
         if (r.host_desc) (void)hipHostFree(r.host_desc);
+        delete[] r.last_desc;
+        r.last_desc = nullptr;
         if (r.host_scal) (void)hipHostFree(r.host_scal);
         if (r.stream) (void)hipStreamDestroy(r.stream);
         if (r.e_ready) (void)hipEventDestroy(r.e_ready);
@@ -479,15 +496,23 @@ int run(smp_sampler_t* s, int blocking) {
         // everything the caller queued on its stream (event copies) comes first
         HIPCHK(hipEventRecord(r.e_ready, s->stream));
         HIPCHK(hipStreamWaitEvent(r.stream, r.e_ready, 0));
-        HIPCHK(hipMemcpyAsync(r.dev_desc, r.host_desc, sizeof(Desc) * cnt, hipMemcpyHostToDevice, r.stream));
-        HIPCHK(hipEventRecord(r.e_start, r.stream));
+        // the slot's previous launch has retired, and kernels never write the
+        // descriptors: an unchanged table need not be uploaded again
+        if (r.last_cnt != cnt || memcmp(r.last_desc, r.host_desc, sizeof(Desc) * cnt) != 0) {
+            HIPCHK(hipMemcpyAsync(r.dev_desc, r.host_desc, sizeof(Desc) * cnt, hipMemcpyHostToDevice, r.stream));
+            memcpy(r.last_desc, r.host_desc, sizeof(Desc) * cnt);
+            r.last_cnt = cnt;
+        }
+        // an event between two kernels costs a few microseconds of idle GPU
+        r.ev_mask = s->pass_events;
+        if ((r.ev_mask >> START_EVENT_BIT) & 1u) HIPCHK(hipEventRecord(r.e_start, r.stream));
         HIPCHK(launch_clear(r.dev_desc, (int)cnt, zero, r.dev_ticket, r.stream));
         for (int p = 0; p < NPASS; ++p) {
-            HIPCHK(hipEventRecord(r.e_pass[p], r.stream));
+            if ((r.ev_mask >> p) & 1u) HIPCHK(hipEventRecord(r.e_pass[p], r.stream));
             const int lim = p == 2 ? s->grid_chain : s->grid_emit;
             HIPCHK(launch_pass(p, r.dev_desc, (int)cnt, seg, tile, r.dev_ticket, lim, r.stream));
         }
-        HIPCHK(hipEventRecord(r.e_pass[NPASS], r.stream));
+        if ((r.ev_mask >> NPASS) & 1u) HIPCHK(hipEventRecord(r.e_pass[NPASS], r.stream));
         HIPCHK(launch_finish(r.dev_desc, (int)cnt, blk, lines, r.stream));
         HIPCHK(launch_gather_scalars(r.dev_desc, (int)cnt, r.dev_scal, r.stream));
         HIPCHK(hipMemcpyAsync(r.host_scal, r.dev_scal, sizeof(Scalars) * cnt, hipMemcpyDeviceToHost, r.stream));
@@ -599,6 +624,12 @@ int sampler_last_timing(smp_sampler_t* s, float* main_kernel_ms, float* total_ms
         if (int rc = retire_slot(s, r)) return rc;
     if (main_kernel_ms) *main_kernel_ms = s->last_main_ms;
     if (total_ms) *total_ms = s->last_total_ms;
+    return SMP_OK;
+}
+
+int sampler_set_pass_events(smp_sampler_t* s, uint32_t mask) {
+    if (!s || (mask & ~PASS_EVENTS_ALL) != 0) return SMP_EINVAL;
+    s->pass_events = mask;
     return SMP_OK;
 }
 

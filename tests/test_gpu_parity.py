@@ -263,6 +263,34 @@ def test_errors(sampler):
         assert oracle.run(ev, **kw)["status"] == g["status"], label
 
 
+def test_pass_event_mask(sampler):
+    say("pass event mask")
+    ev, kw = tg.config1(seed=11, n=50_000)
+    p = smp.make_params(kw["threshold"], kw["num_lines"])
+    o = oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"])
+    try:
+        sampler.set_pass_events(0x30)  # only the two events around the emit pass
+        tid = sampler.submit_trace(ev, p)
+        sampler.run(blocking=True)
+        t = sampler.last_pass_timing()
+        assert t["emit"] > 0, t
+        assert all(t[k] == -1 for k in smp.PASS_NAMES if k != "emit"), t
+        assert sampler.last_timing() == (-1, -1)
+        g = sampler.fetch_profile(tid)
+        compare(g, o, "mask 0x30")
+        sampler.set_pass_events(0x7F)
+        tid = sampler.submit_trace(ev, p)
+        sampler.run(blocking=True)
+        t = sampler.last_pass_timing()
+        assert all(t[k] > 0 for k in smp.PASS_NAMES), t
+        assert all(x > 0 for x in sampler.last_timing())
+        compare(sampler.fetch_profile(tid), o, "mask 0x3F")
+        with pytest.raises(smp.SamplerError):
+            sampler.set_pass_events(0x80)
+    finally:
+        sampler.set_pass_events(0x7F)
+
+
 def test_budget_admission(sampler):
     say("admission by budget")
     import torch
