@@ -1673,11 +1673,27 @@ __global__ __launch_bounds__(EMIT_BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
     hist_init(hc);
     __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    // Segments are taken grid-stride (consecutive waves, consecutive
-    // segments); each wave loads its next segment while it emits the current.
-    const uint64_t stride = (uint64_t)gridDim.x * EMIT_WAVES;
-    uint64_t g = (uint64_t)blockIdx.x * EMIT_WAVES + wv;
-    if (g < nseg_total) {
+    // A batch of several traces: each workgroup takes one contiguous run of
+    // segments (its waves interleaved in it), so that it sees the lines of
+    // one or two traces and its line cache holds their hot lines; spread over
+    // the grid, it would fill the cache with the first keys seen and send
+    // nearly every later update to global atomics.  A single trace: segments
+    // grid-stride (consecutive waves, consecutive segments), which streams
+    // HBM faster than one run per workgroup.  Each wave loads its next
+    // segment while it emits the current.
+    uint64_t g, g_end, stride;
+    if (ntraces > 1) {
+        const uint64_t per = (nseg_total + (uint64_t)gridDim.x * EMIT_WAVES - 1) / ((uint64_t)gridDim.x * EMIT_WAVES);
+        const uint64_t e0 = ((uint64_t)blockIdx.x + 1) * per * EMIT_WAVES;
+        g = (uint64_t)blockIdx.x * per * EMIT_WAVES + wv;
+        g_end = e0 < nseg_total ? e0 : nseg_total;
+        stride = EMIT_WAVES;
+    } else {
+        g = (uint64_t)blockIdx.x * EMIT_WAVES + wv;
+        g_end = nseg_total;
+        stride = (uint64_t)gridDim.x * EMIT_WAVES;
+    }
+    if (g < g_end) {
         auto locate = [&](uint64_t x, int from) {
             EmitSeg r;
             r.t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, from, ntraces, x));
@@ -1695,7 +1711,7 @@ __global__ __launch_bounds__(EMIT_BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
         }
         for (;;) {
             const uint64_t gn = g + stride;
-            const bool hn = gn < nseg_total;
+            const bool hn = gn < g_end;
             const EmitSeg sn = hn ? locate(gn, s.t) : s;
             emit_segment(desc, s, hc, stage[wv], in, hn, sn);
             if (!hn) break;
