@@ -236,7 +236,9 @@ SMP_API int sampler_set_pass_events(smp_sampler_t *s, uint32_t mask);
 SMP_API int sampler_last_pass_timing(smp_sampler_t *s, float *pass_ms);
 
 /* Diagnostics: the 32 control words of the last launch (word 1: abort flag,
- * words 2 and 3: tiles taken by the resolve and scan passes). */
+ * words 2 and 3: tiles taken by the resolve and scan passes, word 4:
+ * segments the chain pass followed through their records; the resolve pass
+ * finishes the others). */
 SMP_API int sampler_last_counters(smp_sampler_t *s, uint64_t *out32);
 
 /* Bytes of the workspace the sampler keeps for itself (descriptor tables,

@@ -50,11 +50,13 @@ enum {
     // resolve pass: exclusive prefixes, entry and exit offsets of the chain
     SP_F0, SP_P0, SP_C0, SP_EF, SP_XF,
     // chain pass: samples, best growth sample (value, event, ptr), Python footprint at the last sample, flags
+    // (BFL_CHAIN until the chain pass has run: the resolve pass writes these planes itself where it can)
     SP_BCNT, SP_BGV, SP_BGI, SP_BGP, SP_LSV, SP_BFL,
     // scan pass: state before the segment (rank base, high-water mark record, flags, last-sample Python footprint)
     SP_XCNT, SP_XHV, SP_XHI, SP_XHP, SP_XFL, SP_XLS,
     NSPLANE
 };
+constexpr int64_t BFL_CHAIN = 8;
 
 // Look-back status words of one tile (each: 2-bit state | 62-bit payload,
 // written once per run; stored plane by plane like the segment values).

@@ -900,7 +900,8 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     __shared__ unsigned long long s_tk;
     __shared__ int64_t w_sum[3][TWAVES];
     __shared__ int64_t s_pre[3];
-    __shared__ int64_t w_peak[TWAVES];
+    __shared__ int64_t w_peak[TWAVES], w_peakS[TWAVES];
+    __shared__ int w_left[TWAVES];
     __shared__ int64_t m_lo[TILE], m_hi[TILE], m_af[TILE], m_kf[TILE], m_ex[TILE];
     __shared__ uint64_t w_tot[TWAVES], w_sim[TWAVES];  // valid lanes with TOTAL / SIM maps
     __shared__ int64_t ring[RING][SEG];
@@ -1127,7 +1128,8 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     const int64_t P0 = s_pre[1] + rP;
     const int64_t C0 = s_pre[2] + rC;
     uint32_t err = 0;
-    int64_t pk = 0;
+    int64_t pk = 0, pks = 0;
+    bool left = false;  // left to the chain pass
     if (valid) {
         const int64_t af = sp[SP_AF * ns], ac = sp[SP_AC * ns];
         const int64_t mxf = sp[SP_MXF * ns], mnf = sp[SP_MNF * ns], mxp = sp[SP_MXP * ns], mnp = sp[SP_MNP * ns];
@@ -1142,15 +1144,66 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
             err = 2u;
         pk = F0 + mxf;
         if (j == ns - 1) *gp(&D.scal->final_F) = F0 + af;
+        // The chain pass's results, here, for a segment whose entry takes no
+        // sample before its first forced event and that holds no copy or
+        // timer events: the prefix's only sample is that event's, and from
+        // it on the chain is the summary pass's.  Every other segment is left
+        // to the chain pass.
+        const int fn = (int)sp[SP_FN * ns];
+        if (fn >= 0 && (sp[SP_FLG * ns] & 4) == 0 && ef >= sp[SP_PLO * ns] && ef <= sp[SP_PHI * ns]) {
+            const int64_t ffn = sp[SP_FFN * ns];
+            int64_t gbest = 0, smax = ffn, lsrel;
+            int gnode = -1;
+            if (ffn > ef) {
+                gbest = ffn;
+                gnode = fn;
+            }
+            const int64_t agv = sp[SP_AGV * ns], asmx = sp[SP_ASMX * ns];
+            const int agn = (int)sp[SP_AGN * ns], als = (int)sp[SP_ALS * ns];
+            if (agn >= 0 && (gnode < 0 || agv > gbest)) {
+                gbest = agv;
+                gnode = agn;
+            }
+            if (asmx > smax) smax = asmx;
+            lsrel = als >= 0 ? sp[SP_ALP * ns] : sp[SP_PFN * ns];
+            pks = F0 + smax;
+            const int64_t a = j * SEG;
+            const bool hg = gnode >= 0 && gnode < seg_events(D, j);
+            o[SP_BCNT * ns] = 1 + sp[SP_ACNT * ns];
+            o[SP_BGV * ns] = hg ? F0 + gbest : 0;
+            o[SP_BGI * ns] = hg ? a + gnode : 0;
+            o[SP_BGP * ns] = hg ? (int64_t)(uint32_t)record(D, a + gnode)[1] : 0;
+            o[SP_LSV * ns] = P0 + lsrel;
+            o[SP_BFL * ns] = (hg ? 1 : 0) | 2;
+            // windows before the forced one hold no sample (as the summary
+            // pass wrote); the forced window gains the forced sample
+            gp(D.mask)[j * NW + (fn >> 6)] = (1ull << (fn & 63)) | (uint64_t)sp[SP_AMF * ns];
+        } else {
+            o[SP_BFL * ns] = BFL_CHAIN;
+            left = true;
+        }
     }
     if (ballot(err != 0) && l == 0) g_or32(&D.scal->err, 2u);
+    const int nleft = __popcll(ballot(left));
     pk = wave_max(pk);
-    if (l == 0) w_peak[wv] = pk;
+    pks = wave_max(pks);
+    if (l == 0) {
+        w_peak[wv] = pk;
+        w_peakS[wv] = pks;
+        w_left[wv] = nleft;
+    }
     __syncthreads();
     if (tid == 0) {
-        int64_t p = 0;
-        for (int w = 0; w < TWAVES; ++w) p = w_peak[w] > p ? w_peak[w] : p;
+        int64_t p = 0, q = 0;
+        uint64_t c = 0;
+        for (int w = 0; w < TWAVES; ++w) {
+            p = w_peak[w] > p ? w_peak[w] : p;
+            q = w_peakS[w] > q ? w_peakS[w] : q;
+            c += (uint64_t)w_left[w];
+        }
         if (p > 0) g_max(&D.scal->peak_F, (int64_t)p);
+        if (q > 0) g_max(&D.scal->peak_S, (int64_t)q);
+        if (c) g_add((uint64_t*)&ctl[4], c);
     }
 }
 
@@ -1173,14 +1226,39 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
     // take no sample before it, from the summary pass.  Each wave reads them
     // one segment ahead.
     const int pl_ = l < 5 ? SP_F0 + l : (l == 5 ? SP_FLG : (l < 18 ? SP_FN + (l - 6) : SP_F0));
+    // Only the segments the resolve pass left to this pass, grid-stride:
+    // each wave reads the flags of its next 64 segments in one load (lane i:
+    // the i-th) and visits the marked ones.
     const uint64_t stride = (uint64_t)gridDim.x * WAVES;
-    uint64_t g = (uint64_t)blockIdx.x * WAVES + wv;
+    uint64_t gb = (uint64_t)blockIdx.x * WAVES + wv, cur_gb = 0;
+    uint64_t pend = 0;  // marked segments among the last 64 read, not yet taken
+    int hint = 0;       // a trace at or before the wave's next segment
+    auto next_marked = [&]() -> uint64_t {
+        while (!pend) {
+            if (gb >= nseg_total) return nseg_total;
+            hint = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, hint, ntraces, gb));
+            const uint64_t x = gb + (uint64_t)l * stride;
+            bool mk = false;
+            if (x < nseg_total) {
+                const Desc& Dx = desc[find_trace_seg(desc, hint, ntraces, x)];
+                mk = seg_val(Dx, SP_BFL, (int64_t)(x - Dx.seg_begin)) == BFL_CHAIN;
+            }
+            pend = ballot(mk);
+            cur_gb = gb;
+            gb += 64 * stride;
+        }
+        const int i = ctz64(pend);
+        pend &= pend - 1;
+        return cur_gb + (uint64_t)i * stride;
+    };
+    uint64_t g = next_marked();
     int64_t pv_next = 0;
     if (g < nseg_total) {
         const Desc& D0 = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g))];
         pv_next = seg_val(D0, pl_, (int64_t)(g - D0.seg_begin));
     }
-    for (; g < nseg_total; g += stride) {
+    for (uint64_t gn; g < nseg_total; g = gn) {
+        gn = next_marked();
         const int t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, cur_t, ntraces, g));
         if (t != cur_t && have_t && l == 0 && peakS > 0)
             g_max(&desc[cur_t].scal->peak_S, (int64_t)peakS);
@@ -1196,9 +1274,9 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         const int64_t pv = pv_next;
         {
             // past the last segment, this one's again (no branch)
-            const uint64_t gn = g + stride < nseg_total ? g + stride : g;
-            const Desc& Dn = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, t, ntraces, gn))];
-            pv_next = seg_val(Dn, pl_, (int64_t)(gn - Dn.seg_begin));
+            const uint64_t gq = gn < nseg_total ? gn : g;
+            const Desc& Dn = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, t, ntraces, gq))];
+            pv_next = seg_val(Dn, pl_, (int64_t)(gq - Dn.seg_begin));
         }
         const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), C0 = readlane64(pv, 2);
         const int64_t eF = readlane64(pv, 3), xF = readlane64(pv, 4);
