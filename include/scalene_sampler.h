@@ -237,8 +237,9 @@ SMP_API int sampler_last_pass_timing(smp_sampler_t *s, float *pass_ms);
 
 /* Diagnostics: the 32 control words of the last launch (word 1: abort flag,
  * words 2 and 3: tiles taken by the resolve and scan passes, word 4:
- * segments the chain pass followed through their records; the resolve pass
- * finishes the others). */
+ * segments the chain pass followed through their records (the resolve pass
+ * finishes the others), word 5: tracked-bitmap blocks taken by the ranking
+ * of the tracked list). */
 SMP_API int sampler_last_counters(smp_sampler_t *s, uint64_t *out32);
 
 /* Bytes of the workspace the sampler keeps for itself (descriptor tables,

@@ -18,7 +18,8 @@ int emit_grid_limit();
 hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, unsigned long long* ctl, hipStream_t s);
 hipError_t launch_pass(int pass, const Desc* desc, int ntraces, uint64_t nseg_total, uint64_t ntile_total,
                        unsigned long long* ctl, int grid_limit, hipStream_t s);
-hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines, hipStream_t s);
+hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines,
+                         unsigned long long* ctl, hipStream_t s);
 hipError_t launch_gather_scalars(const Desc* desc, int ntraces, Scalars* out, hipStream_t s);
 }  // namespace smp
 
@@ -513,7 +514,7 @@ int run(smp_sampler_t* s, int blocking) {
             HIPCHK(launch_pass(p, r.dev_desc, (int)cnt, seg, tile, r.dev_ticket, lim, r.stream));
         }
         if ((r.ev_mask >> NPASS) & 1u) HIPCHK(hipEventRecord(r.e_pass[NPASS], r.stream));
-        HIPCHK(launch_finish(r.dev_desc, (int)cnt, blk, lines, r.stream));
+        HIPCHK(launch_finish(r.dev_desc, (int)cnt, blk, lines, r.dev_ticket, r.stream));
         HIPCHK(launch_gather_scalars(r.dev_desc, (int)cnt, r.dev_scal, r.stream));
         HIPCHK(hipMemcpyAsync(r.host_scal, r.dev_scal, sizeof(Scalars) * cnt, hipMemcpyDeviceToHost, r.stream));
         HIPCHK(hipEventRecord(r.e_end, r.stream));

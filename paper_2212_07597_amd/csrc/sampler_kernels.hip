@@ -1840,58 +1840,51 @@ __device__ __forceinline__ int find_trace_blk(const Desc* desc, int ntraces, uin
     return lo;
 }
 
-__global__ void k_track_count(const Desc* __restrict__ desc, int ntraces, uint64_t nblk_total) {
-    const uint64_t b = blockIdx.x;
-    if (b >= nblk_total) return;
-    const Desc& D = desc[find_trace_blk(desc, ntraces, b)];
-    const uint64_t lb = b - D.blk_begin;
-    const uint64_t Kr = *gp(&D.scal->K);
-    const uint64_t K = Kr < D.n ? Kr : D.n;
-    const uint64_t nwords = (K + 63) >> 6;
-    const uint64_t w0 = lb * CBLK_WORDS;
-    uint64_t c = 0;
-    for (uint64_t i = threadIdx.x; i < CBLK_WORDS; i += blockDim.x)
-        if (w0 + i < nwords) c += __popcll(gp(D.tracked_bits)[w0 + i]);
-    __shared__ uint64_t red[256];
-    red[threadIdx.x] = c;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) gp(D.blk)[lb] = red[0];
-}
-
-__global__ void k_track_scan(const Desc* __restrict__ desc) {
-    const Desc& D = desc[blockIdx.x];
-    __shared__ uint64_t part[256];
-    __shared__ uint64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (uint64_t b0 = 0; b0 < D.nblk; b0 += blockDim.x) {
-        const uint64_t i = b0 + threadIdx.x;
-        const uint64_t v = i < D.nblk ? gp(D.blk)[i] : 0;
-        part[threadIdx.x] = v;
-        __syncthreads();
-        for (int s = 1; s < (int)blockDim.x; s <<= 1) {
-            uint64_t x = (int)threadIdx.x >= s ? part[threadIdx.x - s] : 0;
-            __syncthreads();
-            part[threadIdx.x] += x;
-            __syncthreads();
+// Count before compaction block b of a trace's tracked bitmap, by a
+// decoupled look-back over its earlier blocks (one wave; status words st:
+// state 1 = a block's own count, 2 = the count through it).
+__device__ bool count_lookback(const uint64_t* st, int64_t b, uint64_t& excl, unsigned long long* ctl) {
+    const int l = lane_id();
+    uint64_t acc = 0;
+    int64_t base = b - 1;
+    Spin sp;
+    while (base >= 0) {
+        const int64_t jj = base - l;
+        const bool in = jj >= 0;
+        const uint64_t w = in ? ld_status(st + (in ? jj : 0)) : 0;
+        const uint32_t stt = wstate(w);
+        const uint64_t incl = ballot(in && stt == 2);
+        // lanes before the nearest inclusive word need their blocks' own counts
+        const int lim = incl ? ctz64(incl) : 64;
+        const uint64_t need = ballot(in && l < lim);
+        if ((ballot(in && stt != 0) & need) != need) {
+            if (spin_abort(ctl, sp)) return false;
+            continue;
         }
-        if (i < D.nblk) gp(D.blk)[i] = carry + part[threadIdx.x] - v;  // exclusive
-        __syncthreads();
-        if (threadIdx.x == blockDim.x - 1) carry += part[threadIdx.x];
-        __syncthreads();
+        acc += (uint64_t)wave_sum(in && l <= lim && (l < lim || incl) ? unpack(w) : 0);
+        if (incl) break;
+        base -= 64;
     }
-    if (threadIdx.x == 0) *gp(&D.scal->H) = carry;
+    excl = acc;
+    return true;
 }
 
-// Ordered tracked list, in two steps: k_track_emit writes the sample rank of
-// every tracked sample at its place in the list (stores only), then
-// k_track_fill completes each entry in parallel.
-__global__ void k_track_emit(const Desc* __restrict__ desc, int ntraces, uint64_t nblk_total) {
-    const uint64_t b = blockIdx.x;
+// Ordered tracked list (the samples that set a new high-water mark, section
+// 3.4), in two steps.  k_track_rank: each compaction block of a trace's
+// tracked bitmap counts its set bits, takes the count before it from a
+// look-back over the trace's earlier blocks (status words in D.blk, cleared
+// per launch; blocks are taken by ticket, so every block waited on is
+// running or done) and writes the sample rank of each of its tracked samples
+// at its place in the list (stores only); the block holding the bitmap's
+// last word writes H.  k_track_fill then completes each entry in parallel.
+__global__ __launch_bounds__(256) void k_track_rank(const Desc* __restrict__ desc, int ntraces, uint64_t nblk_total,
+                                                    unsigned long long* ctl) {
+    __shared__ uint64_t s_tk, s_excl;
+    __shared__ uint64_t w_cnt[4];
+    const int tid = threadIdx.x, l = lane_id(), wv = tid >> 6;
+    if (tid == 0) s_tk = g_add_rtn((uint64_t*)&ctl[5], 1ull);
+    __syncthreads();
+    const uint64_t b = s_tk;
     if (b >= nblk_total) return;
     const Desc& D = desc[find_trace_blk(desc, ntraces, b)];
     const uint64_t lb = b - D.blk_begin;
@@ -1899,43 +1892,60 @@ __global__ void k_track_emit(const Desc* __restrict__ desc, int ntraces, uint64_
     const uint64_t K = Kr < D.n ? Kr : D.n;
     const uint64_t nwords = (K + 63) >> 6;
     const uint64_t w0 = lb * CBLK_WORDS;
-    if (w0 >= nwords) return;
-    const uint64_t H = *gp(&D.scal->H);
+    if (w0 >= nwords) return;  // the whole block: no tracked sample here (H stays 0 if none at all)
     // each thread owns 4 consecutive words
     constexpr int PER = CBLK_WORDS / 256;
     uint64_t words[PER];
     uint64_t c = 0;
+#pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const uint64_t wi = w0 + threadIdx.x * PER + i;
+        const uint64_t wi = w0 + (uint64_t)tid * PER + i;
         words[i] = wi < nwords ? gp(D.tracked_bits)[wi] : 0;
         c += __popcll(words[i]);
     }
-    __shared__ uint64_t part[256];
-    part[threadIdx.x] = c;
+    const uint64_t ci = (uint64_t)wave_incl_sum((int64_t)c);
+    if (l == 63) w_cnt[wv] = ci;
     __syncthreads();
-    for (int s = 1; s < 256; s <<= 1) {
-        uint64_t x = (int)threadIdx.x >= s ? part[threadIdx.x - s] : 0;
-        __syncthreads();
-        part[threadIdx.x] += x;
-        __syncthreads();
+    uint64_t woff = 0, total = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wv) woff += w_cnt[w];
+        total += w_cnt[w];
     }
-    uint64_t h = gp(D.blk)[lb] + part[threadIdx.x] - c;
+    uint64_t* st = D.blk;
+    if (wv == 0) {
+        uint64_t excl = 0;
+        bool ok = true;
+        if (lb == 0) {
+            if (l == 0) st_status(st, pack((int64_t)total, 2));
+        } else {
+            if (l == 0) st_status(st + lb, pack((int64_t)total, 1));
+            ok = count_lookback(st, (int64_t)lb, excl, ctl);
+            if (l == 0) st_status(st + lb, pack((int64_t)(excl + total), 2));
+        }
+        if (l == 0) {
+            s_excl = excl;
+            if (!ok) g_or32(&D.scal->err, 8u);
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && w0 + CBLK_WORDS >= nwords) *gp(&D.scal->H) = s_excl + total;
+    uint64_t h = s_excl + woff + ci - c;
     SMP_GLOBAL uint32_t* tq = (SMP_GLOBAL uint32_t*)D.tracked;
     for (int i = 0; i < PER; ++i) {
         uint64_t m = words[i];
-        const uint64_t wi = w0 + threadIdx.x * PER + i;
+        const uint64_t wi = w0 + (uint64_t)tid * PER + i;
         while (m) {
             const int bit = __builtin_ctzll(m);
             m &= m - 1;
             const uint64_t r = wi * 64 + bit;
-            if (r >= K || h >= H) break;  // only reachable after an internal fault
+            if (r >= K) break;  // only reachable after an internal fault
             tq[4 * h] = (uint32_t)r;
             ++h;
         }
     }
 }
 
-// Entry h of the tracked list (rank r from k_track_emit): event, line and
+// Entry h of the tracked list (rank r from k_track_rank): event, line and
 // ptr_id of the tracked sample, whether a free reclaimed it (section 3.4),
 // and the per-line (mallocs, frees) counts.  The last tracked object counts
 // as reclaimed only with RESOLVE_AT_END.
@@ -1949,10 +1959,13 @@ __global__ __launch_bounds__(256) void k_track_fill(const Desc* __restrict__ des
         const Desc& D = desc[t];
         const uint64_t lb = b - D.blk_begin;
         const uint64_t H = *gp(&D.scal->H);
-        const uint64_t h0 = gp(D.blk)[lb];
-        const uint64_t h1 = lb + 1 < D.nblk ? gp(D.blk)[lb + 1] : H;
         const uint64_t Kr = *gp(&D.scal->K);
         const uint64_t K = Kr < D.n ? Kr : D.n;
+        // the counts through this block and through the one before it (only
+        // blocks that hold bitmap words published one)
+        const bool active = lb * CBLK_WORDS < ((K + 63) >> 6);
+        const uint64_t h1 = active ? (uint64_t)unpack(ld_status(D.blk + lb)) : 0;
+        const uint64_t h0 = active && lb > 0 ? (uint64_t)unpack(ld_status(D.blk + lb - 1)) : 0;
         const bool resolve_last = (D.options & 2u) != 0;
         SMP_GLOBAL uint32_t* tq = (SMP_GLOBAL uint32_t*)D.tracked;
         for (uint64_t h = h0 + threadIdx.x; h < h1 && h < H; h += blockDim.x) {
@@ -2077,11 +2090,10 @@ hipError_t launch_gather_scalars(const Desc* desc, int ntraces, Scalars* out, hi
     return hipGetLastError();
 }
 
-hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines, hipStream_t s) {
+hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines,
+                         unsigned long long* ctl, hipStream_t s) {
     if (nblk_total) {
-        k_track_count<<<dim3((unsigned)nblk_total), dim3(256), 0, s>>>(desc, ntraces, nblk_total);
-        k_track_scan<<<dim3((unsigned)ntraces), dim3(256), 0, s>>>(desc);
-        k_track_emit<<<dim3((unsigned)nblk_total), dim3(256), 0, s>>>(desc, ntraces, nblk_total);
+        k_track_rank<<<dim3((unsigned)nblk_total), dim3(256), 0, s>>>(desc, ntraces, nblk_total, ctl);
         k_track_fill<<<dim3((unsigned)nblk_total), dim3(256), 0, s>>>(desc, ntraces, nblk_total);
     }
     if (total_lines) {
