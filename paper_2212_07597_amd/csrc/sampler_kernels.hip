@@ -1144,13 +1144,26 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
             err = 2u;
         pk = F0 + mxf;
         if (j == ns - 1) *gp(&D.scal->final_F) = F0 + af;
-        // The chain pass's results, here, for a segment whose entry takes no
-        // sample before its first forced event and that holds no copy or
-        // timer events: the prefix's only sample is that event's, and from
-        // it on the chain is the summary pass's.  Every other segment is left
-        // to the chain pass.
+        // The chain pass's results, here, for a segment that holds no copy
+        // or timer events and whose entry takes no sample before its first
+        // forced event (the prefix's only sample is that event's, and from it
+        // on the chain is the summary pass's) or, without a forced event, no
+        // sample at all.  Every other segment is left to the chain pass.
         const int fn = (int)sp[SP_FN * ns];
-        if (fn >= 0 && (sp[SP_FLG * ns] & 4) == 0 && ef >= sp[SP_PLO * ns] && ef <= sp[SP_PHI * ns]) {
+        const bool aux = (sp[SP_FLG * ns] & 4) != 0;
+        if (!aux && fn < 0 && ef >= lo && ef <= hi) {
+            // no forced event and an entry inside the no-sample interval:
+            // the segment takes no sample
+            o[SP_BCNT * ns] = 0;
+            o[SP_BGV * ns] = 0;
+            o[SP_BGI * ns] = 0;
+            o[SP_BGP * ns] = 0;
+            o[SP_LSV * ns] = 0;
+            o[SP_BFL * ns] = 0;
+            SMP_GLOBAL uint64_t* mk = gp(D.mask) + j * NW;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) mk[w] = 0;
+        } else if (!aux && fn >= 0 && ef >= sp[SP_PLO * ns] && ef <= sp[SP_PHI * ns]) {
             const int64_t ffn = sp[SP_FFN * ns];
             int64_t gbest = 0, smax = ffn, lsrel;
             int gnode = -1;
