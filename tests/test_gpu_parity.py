@@ -379,3 +379,24 @@ def test_config5_mix_1e8(sampler):
     o = oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"], copy_threshold=kw["copy_threshold"],
                    quantum_us=kw["quantum_us"])
     compare(g, o, "config5 1e8")
+
+
+def test_config5_full(sampler):
+    """The full config-5 trace (5e8 events, copy and timer events, 1e6
+    lines), compared field by field with the oracle."""
+    say("config 5: 5e8 events, generating")
+    import torch
+    ev, kw = tg.config5()
+    dev = torch.from_numpy(ev.view(np.uint8)).to("cuda")
+    p = smp.make_params(kw["threshold"], kw["num_lines"], kw["copy_threshold"], kw["quantum_us"])
+    say("  gpu")
+    tid = sampler.submit_trace(dev, p)
+    sampler.run(blocking=True)
+    g = sampler.fetch_profile(tid)
+    del dev
+    torch.cuda.empty_cache()
+    say("  oracle")
+    o = oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"], copy_threshold=kw["copy_threshold"],
+                   quantum_us=kw["quantum_us"])
+    compare(g, o, "config5")
+    assert g["K"] > 10_000
