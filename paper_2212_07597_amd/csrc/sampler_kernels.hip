@@ -679,6 +679,17 @@ __device__ bool scan_last_sample(const StatusView& sv, int64_t g, int64_t& oP, u
 // here, window by window while scanning, with its samples recorded for the
 // chain and emit passes.  Segments without one get the all-entry analysis
 // over the prefixes kept in LDS.
+// The footprint prefixes of SIM segments, kept for the resolve pass in the
+// sample area (written only later, by the emit pass): segment j at
+// samples + 4 KB * j.  A trace of fewer than 127 events has too small an
+// area; the resolve pass then scans such segments from their records.
+__device__ __forceinline__ bool prefixes_kept(const Desc& D) {
+    return (D.n + 1) * sizeof(Sample) >= (uint64_t)D.nseg * SEG * sizeof(int64_t);
+}
+__device__ __forceinline__ SMP_GLOBAL int64_t* kept_prefixes(const Desc& D, int64_t j) {
+    return gp((int64_t*)D.samples) + j * SEG;
+}
+
 __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int64_t* lF_) {
     const int l = lane_id();
     const int64_t j = (int64_t)(g - D.seg_begin);
@@ -765,6 +776,11 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
         m.fnode = fnode;
     } else {
         m = analyse_segment(lF_, T, cF);
+        if (m.kind == MAP_SIM && prefixes_kept(D)) {
+            SMP_GLOBAL int64_t* o = kept_prefixes(D, j);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) o[w * 64 + l] = lF_[w * 64 + l];
+        }
     }
     const int64_t acnt = wave_sum(l < NW ? (int64_t)__popcll(r.mvec) : 0);
     const int64_t amf = fnode >= 0 ? (int64_t)readlaneu64(r.mvec, fnode >> 6) : 0;
@@ -847,6 +863,17 @@ __device__ __forceinline__ void prescan_segment(const Desc& D, int64_t j, int64_
     }
 }
 
+// The kept prefixes of segment j into F (one wave, one round trip).
+__device__ __forceinline__ void copy_prefixes(const Desc& D, int64_t j, int64_t* F) {
+    const int l = lane_id();
+    const SMP_GLOBAL int64_t* src = kept_prefixes(D, j);
+    int64_t v[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v[w] = src[w * 64 + l];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) F[w * 64 + l] = v[w];
+}
+
 // Exit offset of a segment from entry offset x, following its prefixes F
 // window by window (read four windows at a time, so that the LDS reads
 // overlap).  A round-based search over all windows at once measured slower:
@@ -865,6 +892,20 @@ __device__ __forceinline__ int64_t walk_prefixes(const int64_t* F, int64_t T, in
         for (int w = 0; w < 4; ++w) chain_window<false>(f[w], 0, T, cr, lsp, h + w, -1);
     }
     return cr.ref - fend;
+}
+
+// The same from the kept prefixes in HBM (all windows loaded at once).
+__device__ __forceinline__ int64_t walk_kept(const Desc& D, int64_t j, int64_t T, int64_t x) {
+    const int l = lane_id();
+    const SMP_GLOBAL int64_t* F = kept_prefixes(D, j);
+    int64_t f[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) f[w] = F[w * 64 + l];
+    int64_t lsp = 0;
+    ChainRun cr{x, 0, 0, -1, INT64_MIN, -1};
+#pragma unroll
+    for (int w = 0; w < NW; ++w) chain_window<false>(f[w], 0, T, cr, lsp, w, -1);
+    return cr.ref - readlane64(f[NW - 1], 63);
 }
 
 // Index of the r-th set bit (r < popcount(m)).
@@ -983,6 +1024,7 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     if (k == 0 && tid < 3) st_status(ts.at(W_IF + tid, k), pack(tid == 0 ? tF : (tid == 1 ? tP : tC), 1));
     const int64_t T = D.T;
 
+    const bool kept = prefixes_kept(D);
     if (wv == 0) {
         // ---- the walker ----
         int q = 0;  // SIM segments passed, in walk order
@@ -1029,14 +1071,21 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                         int64_t r = readlane64(kf, stop);
                         if ((sim >> stop) & 1) {
                             const int slot = q % RING;
-                            LocalSpin sp_;
-                            while (__hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != q) {
-                                if (local_spin_abort(ctl, sp_)) {
-                                    ok = false;
-                                    break;
+                            if (kept && __hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE,
+                                                          __HIP_MEMORY_SCOPE_WORKGROUP) != q) {
+                                // its producer is behind: read the kept prefixes instead of waiting
+                                r = walk_kept(D, k * TILE + g0 + stop, T, xs);
+                            } else {
+                                LocalSpin sp_;
+                                while (__hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP) != q) {
+                                    if (local_spin_abort(ctl, sp_)) {
+                                        ok = false;
+                                        break;
+                                    }
                                 }
+                                r = ok ? walk_prefixes(ring[slot], T, xs) : 0;
                             }
-                            r = ok ? walk_prefixes(ring[slot], T, xs) : 0;
                             ++q;
                             __hip_atomic_store(&s_cons, q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                         }
@@ -1116,8 +1165,10 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
             }
             if (!ok) break;
             // a segment the walker has already passed is not scanned
-            if (lane >= 0 && __hip_atomic_load(&s_cons, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= pidx)
-                prescan_segment(D, k * TILE + lane, ring[slot]);
+            if (lane >= 0 && __hip_atomic_load(&s_cons, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= pidx) {
+                if (kept) copy_prefixes(D, k * TILE + lane, ring[slot]);
+                else prescan_segment(D, k * TILE + lane, ring[slot]);
+            }
             __hip_atomic_store(&r_ready[slot], pidx, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
