@@ -262,12 +262,11 @@ def bench_batched(smp, tg, torch, np, steps=3):
     pass_runs = []
 
     def batched():
-        ids = [s.submit_trace(d, p) for d, p in zip(devs, params)]
+        ids = s.submit_traces(devs, params)
         s.run(blocking=True)
         km, _ = s.last_timing()
         pass_runs.append(s.last_pass_timing())
-        for i in ids:
-            s.release(i)
+        s.release_traces(ids)
         return km
 
     def plain():

@@ -188,8 +188,16 @@ SMP_API int sampler_create(int device, void *hip_stream, uint64_t mem_budget, vo
 SMP_API int submit_trace(smp_sampler_t *s, const smp_event_t *ev, uint64_t n, const smp_params_t *params,
                          int ev_on_device, uint64_t *trace_id);
 
-/* Launch every submitted, not yet launched trace as one batch (one
- * persistent kernel over all their segments).  The launch runs on one of the
+/* Admit count traces with one call (a batch of many small traces): as
+ * submit_trace(s, ev[i], n[i], &params[i], ev_on_device, &trace_ids[i]) for
+ * i in order, stopping at the first one refused.  *submitted receives how
+ * many were admitted (their ids are trace_ids[0 .. *submitted-1]); the
+ * return value is SMP_OK when all were, else the refused trace's code. */
+SMP_API int submit_traces(smp_sampler_t *s, uint32_t count, const smp_event_t *const *ev, const uint64_t *n,
+                          const smp_params_t *params, int ev_on_device, uint64_t *trace_ids, uint32_t *submitted);
+
+/* Launch every submitted, not yet launched trace as one batch (each pass of
+ * the launch sequence covers the segments of all of them).  The launch runs on one of the
  * sampler's internal streams, ordered after all work queued so far on the
  * caller's stream, so consecutive batches may overlap on the device.
  * blocking = 1 waits for completion. */
@@ -206,6 +214,15 @@ SMP_API int poll(smp_sampler_t *s, uint64_t trace_id);
  * status (SMP_OK / SMP_EINVAL / SMP_EOVERFLOW) is in sizes->status and
  * out->status. */
 SMP_API int fetch_profile(smp_sampler_t *s, uint64_t trace_id, smp_profile_sizes_t *sizes, smp_profile_t *out);
+
+/* Release count launched traces without copying their profiles out, with
+ * one call: as fetch_profile with no output buffers for each, in order.
+ * n_samples[i] and status[i] (either may be NULL) receive each trace's
+ * sample count and own status.  Stops at the first call that fails (an id
+ * that is not a launched trace: SMP_ESTATE; a device error: SMP_EDEVICE) and
+ * returns its code; *released receives how many were released. */
+SMP_API int release_traces(smp_sampler_t *s, uint32_t count, const uint64_t *trace_ids, uint64_t *n_samples,
+                           int32_t *status, uint32_t *released);
 
 /* Device pointers of a finished trace's results, for callers that keep them
  * on the GPU (valid until fetch_profile releases the trace).  Any out pointer

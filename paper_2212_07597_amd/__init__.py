@@ -29,8 +29,9 @@ SAMPLE_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("F", "<i8"), ("
 TRACKED_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("ptr", "<u4"), ("freed", "<u4")])
 
 EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", "fetch_profile",
-            "trace_device_results", "sampler_last_timing", "sampler_set_pass_events", "sampler_last_pass_timing", "sampler_last_counters",
-            "sampler_fixed_bytes", "sampler_destroy", "error_string")
+            "trace_device_results", "submit_traces", "release_traces", "sampler_last_timing",
+            "sampler_set_pass_events", "sampler_last_pass_timing", "sampler_last_counters", "sampler_fixed_bytes",
+            "sampler_destroy", "error_string")
 
 PASS_NAMES = ("summarize", "resolve", "chain", "scan", "emit")
 
@@ -96,6 +97,12 @@ def lib():
         L.sampler_create.restype = i32
         L.submit_trace.argtypes = [vp, vp, u64, ctypes.POINTER(Params), i32, ctypes.POINTER(u64)]
         L.submit_trace.restype = i32
+        L.submit_traces.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(vp), ctypes.POINTER(u64), ctypes.POINTER(Params),
+                                    i32, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_uint32)]
+        L.submit_traces.restype = i32
+        L.release_traces.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint32)]
+        L.release_traces.restype = i32
         L.run.argtypes = [vp, i32]
         L.run.restype = i32
         L.poll.argtypes = [vp, u64]
@@ -244,6 +251,56 @@ class Sampler:
         for k, name in enumerate(GATE_NAMES):
             res[name] = gates[k]
         return res
+
+    def submit_traces(self, events_list, params_list):
+        """Admit several traces with one call (all CUDA tensors, borrowed until
+        fetch, or all numpy arrays, copied).  Returns their ids.  If one is
+        refused, raises SamplerError whose .ids holds the admitted ones."""
+        k = len(events_list)
+        if len(params_list) != k:
+            raise ValueError("one Params per trace")
+        if k == 0:
+            return []
+        on_dev = all(hasattr(e, "data_ptr") and e.is_cuda for e in events_list)
+        if not on_dev and any(hasattr(e, "data_ptr") for e in events_list):
+            raise ValueError("pass all CUDA tensors or all numpy arrays")
+        arrs = events_list if on_dev else [np.ascontiguousarray(e) for e in events_list]
+        if on_dev:
+            ptrs = [e.data_ptr() for e in arrs]
+            ns = [e.numel() * e.element_size() // 24 for e in arrs]
+        else:
+            ptrs = [a.ctypes.data if a.nbytes else 0 for a in arrs]
+            ns = [a.nbytes // 24 for a in arrs]
+        ev_a = (ctypes.c_void_p * k)(*ptrs)
+        n_a = (ctypes.c_uint64 * k)(*ns)
+        p_a = (Params * k)(*params_list)
+        ids = (ctypes.c_uint64 * k)()
+        done = ctypes.c_uint32()
+        rc = lib().submit_traces(self.h, k, ev_a, n_a, p_a, 1 if on_dev else 0, ids, ctypes.byref(done))
+        out = [int(ids[i]) for i in range(done.value)]
+        if on_dev:
+            for i, tid in enumerate(out):
+                self._keep[tid] = arrs[i]
+        if rc != SMP_OK:
+            err = SamplerError("submit_traces", rc)
+            err.ids = out
+            raise err
+        return out
+
+    def release_traces(self, trace_ids):
+        """release() for several traces with one call; returns [(n_samples, status)]."""
+        k = len(trace_ids)
+        if k == 0:
+            return []
+        ids = (ctypes.c_uint64 * k)(*[int(t) for t in trace_ids])
+        ns = (ctypes.c_uint64 * k)()
+        st = (ctypes.c_int32 * k)()
+        done = ctypes.c_uint32()
+        rc = lib().release_traces(self.h, k, ids, ns, st, ctypes.byref(done))
+        for i in range(done.value):
+            self._keep.pop(int(trace_ids[i]), None)
+        _check("release_traces", rc)
+        return [(int(ns[i]), int(st[i])) for i in range(k)]
 
     def release(self, trace_id):
         """Wait for a trace and free its workspace without copying results out.

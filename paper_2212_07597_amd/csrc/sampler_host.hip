@@ -588,6 +588,32 @@ int fetch_profile(smp_sampler_t* s, uint64_t trace_id, smp_profile_sizes_t* size
     return SMP_OK;
 }
 
+int submit_traces(smp_sampler_t* s, uint32_t count, const smp_event_t* const* ev, const uint64_t* n,
+                  const smp_params_t* params, int ev_on_device, uint64_t* trace_ids, uint32_t* submitted) {
+    if (submitted) *submitted = 0;
+    if (!s || (count && (!ev || !n || !params || !trace_ids))) return SMP_EINVAL;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (int rc = submit_trace(s, ev[i], n[i], &params[i], ev_on_device, &trace_ids[i])) return rc;
+        if (submitted) *submitted = i + 1;
+    }
+    return SMP_OK;
+}
+
+int release_traces(smp_sampler_t* s, uint32_t count, const uint64_t* trace_ids, uint64_t* n_samples, int32_t* status,
+                   uint32_t* released) {
+    if (released) *released = 0;
+    if (!s || (count && !trace_ids)) return SMP_EINVAL;
+    for (uint32_t i = 0; i < count; ++i) {
+        smp_profile_sizes_t sz{};
+        smp_profile_t none{};
+        if (int rc = fetch_profile(s, trace_ids[i], &sz, &none)) return rc;
+        if (n_samples) n_samples[i] = sz.n_samples;
+        if (status) status[i] = sz.status;
+        if (released) *released = i + 1;
+    }
+    return SMP_OK;
+}
+
 int trace_device_results(smp_sampler_t* s, uint64_t trace_id, void** samples, void** hist, uint64_t* n_samples) {
     if (!s) return SMP_EINVAL;
     auto it = s->traces.find(trace_id);

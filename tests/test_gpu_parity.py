@@ -291,6 +291,29 @@ def test_pass_event_mask(sampler):
         sampler.set_pass_events(0x7F)
 
 
+def test_batch_submit_and_release(sampler):
+    say("submit_traces / release_traces")
+    import torch
+    cases = [tg.config1(seed=31 + i, n=n) for i, n in enumerate((1, 700, 50_000, 200_000))]
+    params = [smp.make_params(kw["threshold"], kw["num_lines"]) for _, kw in cases]
+    # device tensors: results equal the oracle's
+    devs = [torch.from_numpy(ev.view(np.uint8)).to("cuda") for ev, _ in cases]
+    ids = sampler.submit_traces(devs, params)
+    assert len(ids) == len(cases)
+    sampler.run(blocking=True)
+    for (ev, kw), tid in zip(cases, ids):
+        compare(sampler.fetch_profile(tid), oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"]),
+                "submit_traces")
+    # host arrays, released without copying out: sample counts and statuses
+    ids = sampler.submit_traces([ev for ev, _ in cases], params)
+    sampler.run(blocking=True)
+    got = sampler.release_traces(ids)
+    want = [oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"]) for ev, kw in cases]
+    assert got == [(o["K"], smp.SMP_OK) for o in want]
+    with pytest.raises(smp.SamplerError):
+        sampler.release_traces(ids)  # already released
+
+
 def test_budget_admission(sampler):
     say("admission by budget")
     import torch
