@@ -136,7 +136,7 @@ struct Desc {
 // ---- wave64 helpers -------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
     int l = lane_id();
@@ -258,10 +258,52 @@ __device__ __forceinline__ int64_t wave_shr1(int64_t x, int64_t old) {
     return (int64_t)dpp64<0x138>((uint64_t)x, (uint64_t)old);
 }
 
-// reductions: the inclusive scan's last lane, broadcast
+// unsigned 32-bit max / min over the wave (as wave_ext32)
+template <bool MAX>
+__device__ __forceinline__ uint32_t wave_extu32(uint32_t x) {
+    const uint32_t id = MAX ? 0u : 0xFFFFFFFFu;
+#define EXTU32_STEP(CTRL, ROWS)                                                                       \
+    {                                                                                                 \
+        const uint32_t y = (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, CTRL, ROWS, 0xf, false); \
+        x = MAX ? (x > y ? x : y) : (x < y ? x : y);                                                  \
+    }
+    EXTU32_STEP(0x111, 0xf)
+    EXTU32_STEP(0x112, 0xf)
+    EXTU32_STEP(0x114, 0xf)
+    EXTU32_STEP(0x118, 0xf)
+    EXTU32_STEP(0x142, 0xa)
+    EXTU32_STEP(0x143, 0xc)
+#undef EXTU32_STEP
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Signed 64-bit max / min over the wave, exact: the extreme high word (signed),
+// then the extreme low word (unsigned) among the lanes that hold it.  Two
+// 32-bit reductions cost far fewer instructions than one 64-bit one.
+template <bool MAX>
+__device__ __forceinline__ int64_t wave_ext64(int64_t x) {
+    const int32_t hi = (int32_t)((uint64_t)x >> 32);
+    const int32_t mh = wave_ext32<MAX>(hi);
+    const uint32_t lo = (uint32_t)(uint64_t)x;
+    const uint32_t ml = wave_extu32<MAX>(hi == mh ? lo : (MAX ? 0u : 0xFFFFFFFFu));
+    return (int64_t)(((uint64_t)(uint32_t)mh << 32) | ml);
+}
+
+// reductions, broadcast
 __device__ __forceinline__ int64_t wave_sum(int64_t x) { return readlane64(wave_incl_sum(x), 63); }
-__device__ __forceinline__ int64_t wave_max(int64_t x) { return readlane64(wave_scan<OpMax>(x), 63); }
-__device__ __forceinline__ int64_t wave_min(int64_t x) { return readlane64(wave_scan<OpMin>(x), 63); }
+__device__ __forceinline__ int64_t wave_max(int64_t x) { return wave_ext64<true>(x); }
+__device__ __forceinline__ int64_t wave_min(int64_t x) { return wave_ext64<false>(x); }
+
+// x with lane L's value replaced by the wave-uniform v (v_writelane; this
+// compiler exposes no builtin for it).  The lane index is an immediate.
+template <int L>
+__device__ __forceinline__ int64_t writelane64(int64_t x, int64_t v) {
+    uint32_t lo = (uint32_t)(uint64_t)x, hi = (uint32_t)((uint64_t)x >> 32);
+    const uint32_t vlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uint64_t)v);
+    const uint32_t vhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    asm("v_writelane_b32 %0, %2, %4\n\tv_writelane_b32 %1, %3, %4" : "+v"(lo), "+v"(hi) : "s"(vlo), "s"(vhi), "n"(L));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 __device__ __forceinline__ int ctz64(uint64_t m) { return __builtin_ctzll(m); }
 __device__ __forceinline__ int top64(uint64_t m) { return 63 - __builtin_clzll(m); }

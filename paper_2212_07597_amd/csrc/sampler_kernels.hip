@@ -135,28 +135,31 @@ __device__ __forceinline__ int find_trace_tile(const Desc* desc, int ntraces, ui
 // timer delays 0 <= delta < 2^32, and line < L; anything else is malformed
 // and contributes nothing.
 struct Ev {
+    int64_t delta;
     int64_t dm;    // footprint delta
     int64_t dp;    // Python footprint delta
-    int64_t dc;    // copy bytes
+    bool cp;       // well-formed copy event (its bytes: delta)
     bool bad;
     bool aux;      // well-formed copy or timer event
 };
 
+// Each kind's range test is made for every lane and the results combined as
+// lane masks: cheaper than choosing per-lane bounds by kind.
 __device__ __forceinline__ Ev decode(uint64_t r0, uint32_t line, uint32_t fw, bool valid, uint32_t L) {
     Ev e;
-    const int64_t delta = (int64_t)r0;
-    const uint32_t flags = fw & 0xFF;
-    const uint32_t kind = (flags >> 1) & 3;
-    const bool py = (flags & 1) == 0;
-    const uint64_t shifted = (uint64_t)delta + (kind == 0 ? (uint64_t)(MAX_ABS_DELTA - 1) : 0ull);
-    const uint64_t span =
-        kind == 0 ? (uint64_t)(2 * MAX_ABS_DELTA - 1) : (kind == 1 ? (uint64_t)MAX_ABS_DELTA : (1ull << 32));
-    e.bad = valid && (kind == 3 || line >= L || shifted >= span);
-    const bool ok = valid && !e.bad;
-    e.dm = (ok && kind == 0) ? delta : 0;
-    e.dp = py ? e.dm : 0;
-    e.dc = (ok && kind == 1) ? delta : 0;
-    e.aux = ok && kind != 0;
+    e.delta = (int64_t)r0;
+    const uint32_t kind = (fw >> 1) & 3;
+    const bool okm = r0 + (uint64_t)(MAX_ABS_DELTA - 1) < (uint64_t)(2 * MAX_ABS_DELTA - 1);
+    const bool okc = r0 < (uint64_t)MAX_ABS_DELTA;
+    const bool okt = (r0 >> 32) == 0;
+    const bool mem = kind == 0, cpy = kind == 1;
+    // bitwise, not short-circuit: no branches
+    const bool good = valid & (line < L) & ((mem & okm) | (cpy & okc) | ((kind == 2) & okt));
+    e.bad = valid & !good;
+    e.dm = (good & mem) ? e.delta : 0;
+    e.dp = (fw & 1u) ? 0 : e.dm;
+    e.cp = good & cpy;
+    e.aux = good & !mem;
     return e;
 }
 
@@ -244,6 +247,7 @@ struct ChainRun {
     int gnode;
     int64_t smax;
     int lastS;
+    int cnt;  // samples recorded
 };
 
 // Advance cr through one window whose footprint prefixes f (and Python
@@ -277,6 +281,7 @@ __device__ __forceinline__ void chain_window(int64_t f, int64_t p, int64_t T, Ch
     if (FULL && m) {
         lsp = readlane64(p, top64(m));
         if (l == w) cr.mvec |= m;
+        cr.cnt += __popcll(m);
     }
 }
 
@@ -701,21 +706,22 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
     const int64_t two_t = 2 * T - 1;
     int64_t cF = 0, cP = 0, accC = 0;
     int64_t mxF = INT64_MIN, mnF = INT64_MAX, mxP = INT64_MIN, mnP = INT64_MAX;
-    bool any_aux = false;
-    uint32_t err = 0;
+    uint64_t bad_m = 0, aux_m = 0, cp_m = 0;  // lanes that saw such a record
     int fnode = -1;
     int64_t plo = -T + 1, phi = T - 1, ffn = 0, pfn = 0;
-    ChainRun r{0, 0, 0, -1, INT64_MIN, -1};
+    ChainRun r{0, 0, 0, -1, INT64_MIN, -1, 0};
     int64_t alp = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         const int k = w * 64 + l;
         const bool valid = k < nv;
         const Ev e = decode(rr.d[w], rr.line[w], rr.fw[w], valid, D.L);
-        if (ballot(e.bad)) err |= 1u;
+        bad_m |= ballot(e.bad);
+        aux_m |= ballot(e.aux);
         const uint64_t fm = ballot(e.dm >= two_t || e.dm <= -two_t);
-        accC += e.dc;
-        if (ballot(e.aux)) any_aux = true;
+        const uint64_t cpw = ballot(e.cp);
+        cp_m |= cpw;
+        if (cpw) accC += e.cp ? e.delta : 0;
         const int64_t f = wave_incl_sum(e.dm) + cF;
         const int64_t p = wave_incl_sum(e.dp) + cP;
         cF = readlane64(f, 63);
@@ -744,12 +750,12 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
             pfn = readlane64(p, fl);
             r.ref = ffn;
         }
-        if (valid) {
-            mxF = f > mxF ? f : mxF;
-            mnF = f < mnF ? f : mnF;
-            mxP = p > mxP ? p : mxP;
-            mnP = p < mnP ? p : mnP;
-        }
+        // lanes past the segment end hold its last prefixes, which are
+        // prefixes too: no lane mask needed
+        mxF = f > mxF ? f : mxF;
+        mnF = f < mnF ? f : mnF;
+        mxP = p > mxP ? p : mxP;
+        mnP = p < mnP ? p : mnP;
         if (fnode >= w * 64) {
             // the chain from the forced event (the same for every entry)
             chain_window<true>(f, p, T, r, alp, w, fnode - w * 64);
@@ -760,13 +766,13 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
     SegScan sc;
     sc.sumF = cF;
     sc.sumP = cP;
-    sc.sumC = wave_sum(accC);
+    sc.sumC = cp_m ? wave_sum(accC) : 0;
     sc.mxF = wave_max(mxF);
     sc.mnF = wave_min(mnF);
     sc.mxP = wave_max(mxP);
     sc.mnP = wave_min(mnP);
-    sc.any_aux = any_aux;
-    sc.err = err;
+    sc.any_aux = aux_m != 0;
+    sc.err = bad_m ? 1u : 0u;
     SegMap m;
     if (fnode >= 0) {
         m.lo = 1;
@@ -782,37 +788,34 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
             for (int w = 0; w < NW; ++w) o[w * 64 + l] = lF_[w * 64 + l];
         }
     }
-    const int64_t acnt = wave_sum(l < NW ? (int64_t)__popcll(r.mvec) : 0);
+    const int64_t acnt = r.cnt;
     const int64_t amf = fnode >= 0 ? (int64_t)readlaneu64(r.mvec, fnode >> 6) : 0;
-    if (l <= SP_PFN) {
-        int64_t v;
-        switch (l) {
-            case SP_AF: v = sc.sumF; break;
-            case SP_AP: v = sc.sumP; break;
-            case SP_AC: v = sc.sumC; break;
-            case SP_MXF: v = sc.mxF; break;
-            case SP_MNF: v = sc.mnF; break;
-            case SP_MXP: v = sc.mxP; break;
-            case SP_MNP: v = sc.mnP; break;
-            case SP_LO: v = m.lo; break;
-            case SP_HI: v = m.hi; break;
-            case SP_KF: v = m.kf; break;
-            case SP_FLG: v = m.kind | (sc.any_aux ? 4 : 0); break;
-            case SP_FN: v = m.fnode; break;
-            case SP_ACNT: v = acnt; break;
-            case SP_AGV: v = r.gbest; break;
-            case SP_AGN: v = r.gnode; break;
-            case SP_ASMX: v = r.smax; break;
-            case SP_ALS: v = r.lastS; break;
-            case SP_ALP: v = r.lastS >= 0 ? alp : 0; break;
-            case SP_AMF: v = amf; break;
-            case SP_PLO: v = plo; break;
-            case SP_PHI: v = phi; break;
-            case SP_FFN: v = ffn; break;
-            default: v = pfn; break;
-        }
-        gp(D.seg)[(int64_t)l * (int64_t)D.nseg + j] = v;
-    }
+    // the plane values (all wave-uniform) into lanes 0..SP_PFN, one store
+    int64_t v = 0;
+    v = writelane64<SP_AF>(v, sc.sumF);
+    v = writelane64<SP_AP>(v, sc.sumP);
+    v = writelane64<SP_AC>(v, sc.sumC);
+    v = writelane64<SP_MXF>(v, sc.mxF);
+    v = writelane64<SP_MNF>(v, sc.mnF);
+    v = writelane64<SP_MXP>(v, sc.mxP);
+    v = writelane64<SP_MNP>(v, sc.mnP);
+    v = writelane64<SP_LO>(v, m.lo);
+    v = writelane64<SP_HI>(v, m.hi);
+    v = writelane64<SP_KF>(v, m.kf);
+    v = writelane64<SP_FLG>(v, m.kind | (sc.any_aux ? 4 : 0));
+    v = writelane64<SP_FN>(v, m.fnode);
+    v = writelane64<SP_ACNT>(v, acnt);
+    v = writelane64<SP_AGV>(v, r.gbest);
+    v = writelane64<SP_AGN>(v, r.gnode);
+    v = writelane64<SP_ASMX>(v, r.smax);
+    v = writelane64<SP_ALS>(v, r.lastS);
+    v = writelane64<SP_ALP>(v, r.lastS >= 0 ? alp : 0);
+    v = writelane64<SP_AMF>(v, amf);
+    v = writelane64<SP_PLO>(v, plo);
+    v = writelane64<SP_PHI>(v, phi);
+    v = writelane64<SP_FFN>(v, ffn);
+    v = writelane64<SP_PFN>(v, pfn);
+    if (l <= SP_PFN) gp(D.seg)[(int64_t)l * (int64_t)D.nseg + j] = v;
     if (fnode >= 0 && l < NW) gp(D.mask)[j * NW + l] = r.mvec;
     if (sc.err && l == 0) g_or32(&D.scal->err, sc.err);
 }
@@ -882,7 +885,7 @@ __device__ __forceinline__ int64_t walk_prefixes(const int64_t* F, int64_t T, in
     const int l = lane_id();
     const int64_t fend = F[SEG - 1];
     int64_t lsp = 0;
-    ChainRun cr{x, 0, 0, -1, INT64_MIN, -1};
+    ChainRun cr{x, 0, 0, -1, INT64_MIN, -1, 0};
 #pragma unroll
     for (int h = 0; h < NW; h += 4) {
         int64_t f[4];
@@ -902,7 +905,7 @@ __device__ __forceinline__ int64_t walk_kept(const Desc& D, int64_t j, int64_t T
 #pragma unroll
     for (int w = 0; w < NW; ++w) f[w] = F[w * 64 + l];
     int64_t lsp = 0;
-    ChainRun cr{x, 0, 0, -1, INT64_MIN, -1};
+    ChainRun cr{x, 0, 0, -1, INT64_MIN, -1, 0};
 #pragma unroll
     for (int w = 0; w < NW; ++w) chain_window<false>(f[w], 0, T, cr, lsp, w, -1);
     return cr.ref - readlane64(f[NW - 1], 63);
@@ -1273,6 +1276,28 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
 
 // -------------------------------------------------------------- chain pass
 
+// The first two windows of a segment's records (delta, pointer, flags), which
+// the chain pass loads one marked segment ahead: in most segments the first
+// forced event lies in them, so the walk needs no other record.
+constexpr int HEAD_W = 2;  // (the pointer lookup below assumes two)
+struct ChainHead {
+    uint64_t d[HEAD_W];
+    uint32_t ptr[HEAD_W];
+    uint32_t fw[HEAD_W];
+};
+
+__device__ __forceinline__ void load_head(const Desc& D, int64_t j, ChainHead& h) {
+    gu8_t* base = (gu8_t*)(D.ev + (size_t)(j * SEG) * 24);  // wave-uniform
+    const int nv = seg_events(D, j);
+#pragma unroll
+    for (int w = 0; w < HEAD_W; ++w) {
+        gu8_t* p = record_addr(base, nv, w);
+        h.d[w] = *(gu64_t*)p;
+        h.ptr[w] = *(gu32_t*)(p + 8);
+        h.fw[w] = *(gu32_t*)(p + 16);
+    }
+}
+
 // One wave per segment (grid-stride): follow the chain from the segment's
 // entry offset; record its samples, count, best growth sample and the Python
 // footprint at its last sample.  Copy and timer events are counted here.
@@ -1317,9 +1342,11 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
     };
     uint64_t g = next_marked();
     int64_t pv_next = 0;
+    ChainHead hd;  // the head of the wave's next segment
     if (g < nseg_total) {
         const Desc& D0 = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g))];
         pv_next = seg_val(D0, pl_, (int64_t)(g - D0.seg_begin));
+        load_head(D0, (int64_t)(g - D0.seg_begin), hd);
     }
     for (uint64_t gn; g < nseg_total; g = gn) {
         gn = next_marked();
@@ -1336,22 +1363,30 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         const int nv = seg_events(D, j);
         const int64_t T = D.T;
         const int64_t pv = pv_next;
+        const ChainHead cur = hd;
         {
             // past the last segment, this one's again (no branch)
             const uint64_t gq = gn < nseg_total ? gn : g;
             const Desc& Dn = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, t, ntraces, gq))];
             pv_next = seg_val(Dn, pl_, (int64_t)(gq - Dn.seg_begin));
+            load_head(Dn, (int64_t)(gq - Dn.seg_begin), hd);
         }
         const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), C0 = readlane64(pv, 2);
         const int64_t eF = readlane64(pv, 3), xF = readlane64(pv, 4);
         const int64_t flg = readlane64(pv, 5);
         const int fn = (int)readlane64(pv, 6);
+        // The pointer of the summary pass's best growth sample after the forced
+        // event, loaded now (it is the segment's best unless the walk below
+        // finds a larger one before the forced event).
+        const int agn0 = (int)readlane64(pv, 9);
+        uint32_t aptr = 0;
+        if (fn >= 0 && agn0 >= 0 && agn0 < nv) aptr = (uint32_t)record(D, a + agn0)[1];
         // From a forced sample on the chain is the one the summary pass followed,
         // so only the events up to it are read again.
         const int fwin = fn >= 0 ? fn >> 6 : NW - 1;
         const int nlim = fn >= 0 ? fn + 1 : nv;
         uint32_t err = 0;
-        ChainRun cr{eF, 0, 0, -1, INT64_MIN, -1};
+        ChainRun cr{eF, 0, 0, -1, INT64_MIN, -1, 0};
         int64_t lsp = 0, cF = 0, cP = 0;
         const int64_t plo = readlane64(pv, 14), phi = readlane64(pv, 15);
         if (fn >= 0 && eF >= plo && eF <= phi) {
@@ -1366,17 +1401,30 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
             cr.lastS = fn;
             cr.ref = ffn;
             if (l == fwin) cr.mvec = 1ull << (fn & 63);
+            cr.cnt = 1;
             lsp = readlane64(pv, 17);
         } else {
-            // the chain from the entry, window by window while scanning (prefixes in registers)
-            SegRecs rr;
-            fetch_segment<false, false>(D, a, nlim, rr);
+            // the chain from the entry, window by window while scanning
+            // (prefixes in registers): the head from the prefetch, later
+            // windows loaded here
+            uint64_t rd[NW - HEAD_W];
+            uint32_t rfw[NW - HEAD_W];
+            if (fwin >= HEAD_W) {
+                gu8_t* base = (gu8_t*)(D.ev + (size_t)a * 24);  // wave-uniform
+#pragma unroll
+                for (int w = HEAD_W; w < NW; ++w) {
+                    gu8_t* p = record_addr(base, nlim, w);
+                    rd[w - HEAD_W] = *(gu64_t*)p;
+                    rfw[w - HEAD_W] = *(gu32_t*)(p + 16);
+                }
+            }
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 if (w > fwin) break;
                 const int k = w * 64 + l;
-                const uint32_t fl = rr.fw[w];
-                const int64_t dm = (k < nlim && (fl & 6u) == 0) ? (int64_t)rr.d[w] : 0;
+                const uint32_t fl = w < HEAD_W ? cur.fw[w] : rfw[w - HEAD_W];
+                const uint64_t rdw = w < HEAD_W ? cur.d[w] : rd[w - HEAD_W];
+                const int64_t dm = (k < nlim && (fl & 6u) == 0) ? (int64_t)rdw : 0;
                 const int64_t dp = (fl & 1u) ? 0 : dm;
                 const int64_t f = wave_incl_sum(dm) + cF;
                 const int64_t p = wave_incl_sum(dp) + cP;
@@ -1430,7 +1478,7 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
             }
         }
 
-        int64_t count = wave_sum(l < NW ? (int64_t)__popcll(cr.mvec) : 0);
+        int64_t count = cr.cnt;
         int64_t gbest = cr.gbest, smax = cr.smax, lsrel = 0;
         int gnode = cr.gnode, lastS = cr.lastS;
         if (fn >= 0) {
@@ -1456,7 +1504,14 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         if (smax != INT64_MIN && F0 + smax > peakS) peakS = F0 + smax;
         const bool hg = gnode >= 0 && gnode < nv;  // nodes past the trace end never sample
         uint32_t gptr = 0;
-        if (hg) gptr = (uint32_t)record(D, a + gnode)[1];
+        if (hg) {
+            if (fn >= 0 && gnode > fn)
+                gptr = aptr;  // the summary pass's sample (gnode == agn0)
+            else if (gnode < HEAD_W * 64)
+                gptr = (uint32_t)readlane32((int)((gnode >> 6) == 0 ? cur.ptr[0] : cur.ptr[1]), gnode & 63);
+            else
+                gptr = (uint32_t)record(D, a + gnode)[1];
+        }
         const int64_t lsv = lastS >= 0 ? P0 + lsrel : 0;
         if (l < 6) {
             int64_t v;
