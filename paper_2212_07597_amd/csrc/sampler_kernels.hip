@@ -138,6 +138,7 @@ struct Ev {
     int64_t delta;
     int64_t dm;    // footprint delta
     int64_t dp;    // Python footprint delta
+    bool mem_ok;   // well-formed memory event
     bool cp;       // well-formed copy event (its bytes: delta)
     bool bad;
     bool aux;      // well-formed copy or timer event
@@ -156,7 +157,8 @@ __device__ __forceinline__ Ev decode(uint64_t r0, uint32_t line, uint32_t fw, bo
     // bitwise, not short-circuit: no branches
     const bool good = valid & (line < L) & ((mem & okm) | (cpy & okc) | ((kind == 2) & okt));
     e.bad = valid & !good;
-    e.dm = (good & mem) ? e.delta : 0;
+    e.mem_ok = good & mem;
+    e.dm = e.mem_ok ? e.delta : 0;
     e.dp = (fw & 1u) ? 0 : e.dm;
     e.cp = good & cpy;
     e.aux = good & !mem;
@@ -237,6 +239,24 @@ __device__ __forceinline__ int seg_events(const Desc& D, int64_t j) {
 
 // ------------------------------------------------------------------- chains
 
+// a > b for wave-uniform values below 2^62 in magnitude, as the sign of
+// b - a in scalar arithmetic (the scalar unit has no 64-bit ordered compare,
+// so a plain comparison would run on the vector unit).
+__device__ __forceinline__ bool sgt64(int64_t a, int64_t b) {
+    // the high word's sign (readfirstlane, free on a scalar value, keeps the
+    // compiler from turning this back into a 64-bit compare)
+    return __builtin_amdgcn_readfirstlane((int)(uint32_t)(((uint64_t)b - (uint64_t)a) >> 32)) < 0;
+}
+
+// Lanes whose prefix f is at least T away from ref, from fT = f + (T - 1)
+// (formed once per window): |f - ref| >= T as one unsigned compare,
+// fT - ref >= 2T - 1 modulo 2^64.  Exact here: prefixes and references stay
+// below 2^61 in magnitude and T below 2^61, so the true value of fT - ref lies
+// in (-2^63, 2^63) and a negative one wraps above 2^63.
+__device__ __forceinline__ uint64_t crossing(int64_t fT, int64_t ref, uint64_t span) {
+    return ballot((uint64_t)fT - (uint64_t)ref >= span);
+}
+
 // One chain followed through a segment: its reference, sample masks (lane w
 // holds window w's mask), the largest growth-sample footprint (earliest on
 // ties), the largest sampled footprint and the last sample's index.
@@ -260,18 +280,21 @@ __device__ __forceinline__ void chain_window(int64_t f, int64_t p, int64_t T, Ch
                                              int st) {
     const int l = lane_id();
     uint64_t m = 0;
-    for (;;) {
-        const int64_t d = f - cr.ref;
-        const uint64_t ex = ballot(l > st && (d >= T || d <= -T));
+    const int64_t fT = (int64_t)((uint64_t)f + (uint64_t)(T - 1));
+    const uint64_t span = (uint64_t)(2 * T - 1);
+    while (st < 63) {  // (lanes above st: ~0 << (st + 1))
+        const uint64_t ex = crossing(fT, cr.ref, span) & (~0ull << (st + 1));
         if (!ex) break;
         const int jj = ctz64(ex);
         const int64_t fj = readlane64(f, jj);
         if (FULL) {
-            if (fj > cr.ref && (cr.gnode < 0 || fj > cr.gbest)) {
+            // (prefixes and references stay below 2^61 in magnitude; smax
+            // starts at INT64_MIN)
+            if (sgt64(fj, cr.ref) && (cr.gnode < 0 || sgt64(fj, cr.gbest))) {
                 cr.gbest = fj;
                 cr.gnode = w * 64 + jj;
             }
-            if (fj > cr.smax) cr.smax = fj;
+            if (cr.smax == INT64_MIN || sgt64(fj, cr.smax)) cr.smax = fj;
             m |= 1ull << jj;
             cr.lastS = w * 64 + jj;
         }
@@ -289,10 +312,11 @@ __device__ __forceinline__ void chain_window(int64_t f, int64_t p, int64_t T, Ch
 // after lane st.  U holds the lanes where an earlier chain of this window
 // sampled; reaching one of them means the chains coincide (returns false).
 __device__ __forceinline__ bool follow(int64_t f, int64_t T, int64_t& ref, int st, uint64_t& U) {
-    const int l = lane_id();
+    const int64_t fT = (int64_t)((uint64_t)f + (uint64_t)(T - 1));
+    const uint64_t span = (uint64_t)(2 * T - 1);
     for (;;) {
-        const int64_t d = f - ref;
-        const uint64_t m = ballot(l > st && (d >= T || d <= -T));
+        if (st >= 63) return true;
+        const uint64_t m = crossing(fT, ref, span) & (~0ull << (st + 1));
         if (!m) return true;
         const int j = ctz64(m);
         if ((U >> j) & 1) return false;
@@ -716,12 +740,16 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
         const int k = w * 64 + l;
         const bool valid = k < nv;
         const Ev e = decode(rr.d[w], rr.line[w], rr.fw[w], valid, D.L);
-        bad_m |= ballot(e.bad);
-        aux_m |= ballot(e.aux);
-        const uint64_t fm = ballot(e.dm >= two_t || e.dm <= -two_t);
-        const uint64_t cpw = ballot(e.cp);
-        cp_m |= cpw;
-        if (cpw) accC += e.cp ? e.delta : 0;
+        // malformed, copy and timer records are rare: one test per window
+        if (ballot(valid & !e.mem_ok)) {
+            bad_m |= ballot(e.bad);
+            aux_m |= ballot(e.aux);
+            const uint64_t cpw = ballot(e.cp);
+            cp_m |= cpw;
+            if (cpw) accC += e.cp ? e.delta : 0;
+        }
+        // forced: |dm| >= 2T - 1, as one unsigned compare (as in crossing)
+        const uint64_t fm = ballot((uint64_t)e.dm + (uint64_t)(two_t - 1) >= (uint64_t)(2 * two_t - 1));
         const int64_t f = wave_incl_sum(e.dm) + cF;
         const int64_t p = wave_incl_sum(e.dp) + cP;
         cF = readlane64(f, 63);
