@@ -78,6 +78,9 @@ def lib():
         p64 = ctypes.POINTER(ctypes.c_int64)
         p8 = ctypes.POINTER(ctypes.c_uint8)
         L.oracle_leak_scores.argtypes = [p64, p64, ctypes.c_uint32, p64, p64, p64, p64, p8, p8]
+        L.oracle_rate.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32,
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]
+        L.oracle_rate.restype = ctypes.c_int
         L.oracle_leak_scores.restype = None
         _lib = L
     return _lib
@@ -144,3 +147,15 @@ def run(events, threshold, num_lines, copy_threshold=None, quantum_us=10_000, op
         return out
     finally:
         lib().oracle_free(rp)
+
+
+def rate(events, threshold, num_lines, options=0):
+    """Deterministic rate-based sampling (section 3.2): one sample per T bytes
+    allocated or freed.  Returns (status, K, samples per line)."""
+    ev = np.ascontiguousarray(events)
+    T = prime_at_least(threshold) if options & OPT_PRIME_T else threshold
+    counts = np.zeros(num_lines, np.int64)
+    K = ctypes.c_uint64(0)
+    st = lib().oracle_rate(ev.ctypes.data if ev.size else None, ev.shape[0], T, num_lines,
+                           counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(K))
+    return int(st), int(K.value), counts

@@ -30,6 +30,9 @@
  *    sample of Tc bytes per multiple of Tc crossed by the cumulative count.
  *  - Python/native time (section 2.1): each timer sample adds the quantum q
  *    to the line's Python time and the signal delay to its native time.
+ *  - Rate-based sampling (section 3.2, the scheme threshold sampling is
+ *    compared with; oracle_rate below): one sample per T bytes allocated or
+ *    freed, counted over the cumulative volume of memory events.
  *
  * Readings where the paper is silent (all stated in the design notes):
  *  start state 0 before event 0; ">=" triggers; reset discards overshoot; the
@@ -315,4 +318,42 @@ OR_EXPORT void oracle_leak_scores(const int64_t *mallocs, const int64_t *frees, 
         lap_gate[i] = (uint8_t)(20 * (m - f + 1) > 19 * (m + 2));
         lit_gate[i] = (uint8_t)(20 * (m - 2 * f + 1) > 19 * (m - f + 2));
     }
+}
+
+/*
+ * Rate-based sampling (section 3.2): every byte allocated or freed counts
+ * towards the next sample, one sample per T bytes, whatever it does to the
+ * footprint.  Deterministic reading: the countdown starts at T instead of a
+ * random draw, so the event that brings V, the cumulative bytes allocated
+ * plus bytes freed (memory events only), to or past a multiple of T takes one
+ * sample per multiple reached: n_i = floor(V_i / T) - floor(V_{i-1} / T),
+ * attributed to the event's line.  line_counts (num_lines entries) receives
+ * the samples per line and *K their total.  Input contract as for oracle_run
+ * (OR_EINVAL wins); V must stay below 2^62 (else OR_EOVERFLOW).
+ */
+OR_EXPORT int oracle_rate(const void *events, uint64_t n, int64_t T, uint32_t L, int64_t *line_counts, uint64_t *K) {
+    *K = 0;
+    if (T < 1 || T >= OR_MAX_T || L == 0 || n >= 0xFFFFFFFFull || (n && !events) || !line_counts) return OR_EINVAL;
+    memset(line_counts, 0, sizeof(int64_t) * L);
+    const or_event *ev = (const or_event *)events;
+    __int128 V = 0;
+    int overflow = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        const or_event e = ev[i];
+        const int kind = (e.flags >> 1) & 3;
+        const int64_t d = e.delta;
+        if (kind == 3 || e.line_id >= L) return OR_EINVAL;
+        if (kind == 1 && (d < 0 || d >= OR_MAX_ABS_DELTA)) return OR_EINVAL;
+        if (kind == 2 && (d < 0 || d > 0xFFFFFFFFll)) return OR_EINVAL;
+        if (kind != 0) continue;
+        if (d >= OR_MAX_ABS_DELTA || d <= -OR_MAX_ABS_DELTA) return OR_EINVAL;
+        if (overflow) continue;
+        const __int128 Vn = V + (d < 0 ? -(__int128)d : (__int128)d);
+        if (Vn >= ((__int128)1 << 62)) { overflow = 1; continue; }
+        const int64_t ni = (int64_t)(Vn / T - V / T);
+        line_counts[e.line_id] += ni;
+        *K += (uint64_t)ni;
+        V = Vn;
+    }
+    return overflow ? OR_EOVERFLOW : OR_OK;
 }

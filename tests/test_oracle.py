@@ -405,3 +405,78 @@ def test_resolve_at_end_option():
 def test_empty_trace():
     r = oracle.run(np.zeros(0, tg.EVENT_DTYPE), threshold=10, num_lines=3)
     assert r["status"] == oracle.OK and r["K"] == 0 and r["final_F"] == 0
+
+
+# ------------------------------------------- rate-based sampling (3.2) --
+
+def _rate(rows, params):
+    return oracle.rate(events_from_rows(rows), params["threshold"], params["num_lines"], params.get("options", 0))
+
+
+def test_rate_golden():
+    """Hand-worked rate-based counts for the golden fixtures' events."""
+    spec = json.load(open(os.path.join(GOLDEN, "rate.json")))
+    for case in spec["cases"]:
+        w = json.load(open(os.path.join(GOLDEN, case["fixture"] + ".json")))
+        st, K, counts = _rate(w["events"], w["params"])
+        assert st == oracle.OK
+        assert K == case["K"] == sum(case["per_event"]), case["fixture"]
+        want = np.zeros(w["params"]["num_lines"], np.int64)
+        for line, v in case["lines"].items():
+            want[int(line)] = v
+        np.testing.assert_array_equal(counts, want, err_msg=case["fixture"])
+        # per event: the same trace cut after each event
+        for i in range(len(w["events"])):
+            _, Ki, _ = _rate(w["events"][: i + 1], w["params"])
+            assert Ki == sum(case["per_event"][: i + 1]), (case["fixture"], i)
+
+
+@pytest.mark.parametrize("d,T,n", [(6, 10, 7), (7, 3, 1000), (1, 1, 513), (4096, 1 << 20, 5000), (10, 10, 64)])
+def test_rate_closed_form(d, T, n):
+    """Events of equal size d (alternating allocations and frees, lines in
+    turn): K = floor(n d / T); the lines share it, and with T dividing d every
+    event takes exactly d / T samples."""
+    rows = [(d if i % 2 == 0 else -d, i, i % 3, 0, 0) for i in range(n)]
+    st, K, counts = _rate(rows, {"threshold": T, "num_lines": 3})
+    assert st == oracle.OK
+    assert K == (n * d) // T
+    assert int(counts.sum()) == K
+    if d % T == 0:
+        want = [(d // T) * len(range(l, n, 3)) for l in range(3)]
+        assert counts.tolist() == want
+
+
+def test_rate_volume_at_t_one():
+    """With T = 1 every byte is a sample: K = sum of |delta| over memory events."""
+    ev, _ = tg.config1(seed=3, n=5_000)
+    mem = ((ev["flags"] >> 1) & 3) == 0
+    st, K, counts = oracle.rate(ev, 1, 64)
+    assert st == oracle.OK
+    assert K == int(np.abs(ev["delta"][mem].astype(object)).sum())
+    assert int(counts.sum()) == K
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_rate_bounds_threshold_count(seed):
+    """A threshold sample needs T bytes of net change since the last one, so
+    at least T bytes of volume: K_threshold <= K_rate on any trace (the
+    paper's comparison of the two samplers, made exact)."""
+    ev, kw = tg.config1(seed=seed, n=30_000)
+    for T in (1 << 12, 1 << 16, 1 << 20, 10_000_019):
+        r = oracle.run(ev, threshold=T, num_lines=kw["num_lines"])
+        st, K, _ = oracle.rate(ev, T, kw["num_lines"])
+        assert st == oracle.OK and r["status"] == oracle.OK
+        assert len(r["samples"]) <= K
+
+
+def test_rate_errors():
+    st, K, _ = _rate([(5, 1, 0, 0, 0), (5, 1, 0, 0, 3)], {"threshold": 10, "num_lines": 1})
+    assert st == oracle.EINVAL
+    st, _, _ = _rate([(5, 1, 2, 0, 0)], {"threshold": 10, "num_lines": 2})
+    assert st == oracle.EINVAL
+    big = (1 << 52) - 1
+    rows = [(big if i % 2 == 0 else -big, 1, 0, 0, 0) for i in range(1025)]
+    st, _, _ = _rate(rows, {"threshold": 1 << 40, "num_lines": 1})
+    assert st == oracle.EOVERFLOW
+    st, K, _ = _rate(rows[:1000], {"threshold": 1 << 40, "num_lines": 1})
+    assert st == oracle.OK and K == (1000 * big) >> 40
