@@ -167,10 +167,12 @@ def main():
         cpu = {"value": round(n * reps / dt, 1), "unit": "events/s", "cores": 1, "kind": "oracle",
                "sample": f"the full config-2 trace ({n} events), {reps} sequential pass(es), one host thread"}
 
+    extras = {}
+    if not args.no_extras:
+        extras["rate"] = bench_rate(smp, tg, torch, np, s, dev, n, kw, K)
     s.close()
     del dev
     torch.cuda.empty_cache()
-    extras = {}
     if not args.no_extras:
         extras["config5"] = bench_config5(smp, tg, torch, np)
         extras["batched"] = bench_batched(smp, tg, torch, np)
@@ -203,6 +205,59 @@ def main():
     }
     out.update(extras)
     print(json.dumps(out), flush=True)
+
+
+def bench_rate(smp, tg, torch, np, s, dev, n, kw, K_thr, steps=10):
+    """Rate-based sampling (section 3.2, one sample per T bytes allocated or
+    freed) on the headline trace, timed with HIP events around `steps`
+    calls; and the sample counts of the two samplers side by side (the
+    paper's comparison) on config 1 and on 32 config-3 traces."""
+    T, L = kw["threshold"], kw["num_lines"]
+    log("rate-based sampler")
+    ws = torch.empty(smp.rate_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    lc = torch.empty(L, dtype=torch.int64, device="cuda")
+    res = torch.empty(2, dtype=torch.int64, device="cuda")
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        smp.rate_run(dev, T, L, workspace=ws, line_counts=lc, result=res, stream=st, sync=False)
+    st.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        smp.rate_run(dev, T, L, workspace=ws, line_counts=lc, result=res, stream=st, sync=False)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    r = res.cpu().numpy()
+    if int(r[1]) != smp.SMP_OK:
+        raise RuntimeError(f"rate status {int(r[1])}")
+    K_rate = int(r[0])
+
+    def counts(ev, kw_):
+        d = torch.from_numpy(ev.view(np.uint8)).to("cuda")
+        tid = s.submit_trace(d, smp.make_params(kw_["threshold"], kw_["num_lines"]))
+        s.run(blocking=True)
+        k_thr, status = s.release(tid)
+        stt, k_rate, _ = smp.rate_run(d, kw_["threshold"], kw_["num_lines"])
+        if status != smp.SMP_OK or stt != smp.SMP_OK:
+            raise RuntimeError("status")
+        return k_thr, k_rate
+
+    ev1, kw1 = tg.config1(seed=1)
+    k1t, k1r = counts(ev1, kw1)
+    ratios = []
+    for (n3, T3, seed3) in tg.config3_plan()[::32]:
+        ev3, kw3 = tg.config3_trace(n3, T3, seed3)
+        kt, kr = counts(ev3, kw3)
+        ratios.append(kr / max(kt, 1))
+    ratios.sort()
+    return {"workload": "config2 (the headline trace), T = 10 MiB; the rate path reads the records twice",
+            "ms": round(ms, 4), "events_per_s": round(n / (ms * 1e-3), 1),
+            "hbm_gbs_algorithmic": round(2 * BYTES_PER_EVENT * n / (ms * 1e-3) / 1e9, 1),
+            "K_rate": K_rate, "K_threshold": K_thr, "rate_over_threshold": round(K_rate / max(K_thr, 1), 2),
+            "config1": {"K_threshold": k1t, "K_rate": k1r, "rate_over_threshold": round(k1r / max(k1t, 1), 2)},
+            "config3_32_traces": {"median_rate_over_threshold": round(ratios[len(ratios) // 2], 2),
+                                  "max_rate_over_threshold": round(ratios[-1], 2)}}
 
 
 def bench_config5(smp, tg, torch, np, steps=3):

@@ -268,6 +268,39 @@ SMP_API void sampler_destroy(smp_sampler_t *s);
 /* Static string for a status code. */
 SMP_API const char *error_string(int status);
 
+/* ---- rate-based sampling (section 3.2) --------------------------------
+ * The scheme threshold sampling is compared with: every byte allocated or
+ * freed counts towards the next sample, one sample per T bytes, whatever the
+ * bytes do to the footprint.  Read deterministically (the countdown starts at
+ * T, not at a random draw): memory event i takes
+ * floor(V_i / T) - floor(V_(i-1) / T) samples, V the cumulative bytes
+ * allocated plus bytes freed by memory events, attributed to the event's
+ * line.  Copy and timer events add nothing.  Independent of a sampler
+ * object: the caller owns every buffer and the stream. */
+
+/* Device workspace bytes rate_run needs for a trace of n_events events
+ * (256 bytes plus 8 per 512 events). */
+SMP_API uint64_t rate_workspace_bytes(uint64_t n_events);
+
+/* Rate-based sampling of one trace, asynchronous on hip_stream (a
+ * hipStream_t; NULL = the null stream).
+ *   ev          : device pointer to n records (layout smp_event_t), read only
+ *   n           : < 2^32 events (0 allowed)
+ *   threshold   : T, 1 <= T < 2^60, used as given
+ *   num_lines   : L >= 1; every record's line must be < L
+ *   workspace   : device scratch of at least rate_workspace_bytes(n) bytes,
+ *                 owned by the caller, contents not preserved
+ *   line_counts : device array of L int64, written: samples per line
+ *   result      : device array of 2 uint64, written: [0] = K, the total
+ *                 number of samples; [1] = SMP_OK, SMP_EINVAL (a malformed
+ *                 record, as fetch_profile reports it) or SMP_EOVERFLOW (V
+ *                 reaches 2^62); counts are meaningful only with SMP_OK
+ * Returns SMP_EINVAL for invalid arguments (nothing launched), SMP_EDEVICE
+ * if a launch failed, else SMP_OK; the results are complete when the stream
+ * reaches them.  Concurrent calls must use separate workspaces. */
+SMP_API int rate_run(const smp_event_t *ev, uint64_t n, int64_t threshold, uint32_t num_lines, void *workspace,
+                     uint64_t workspace_bytes, int64_t *line_counts, uint64_t *result, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,7 +31,7 @@ TRACKED_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("ptr", "<u4"),
 EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", "fetch_profile",
             "trace_device_results", "submit_traces", "release_traces", "sampler_last_timing",
             "sampler_set_pass_events", "sampler_last_pass_timing", "sampler_last_counters", "sampler_fixed_bytes",
-            "sampler_destroy", "error_string")
+            "sampler_destroy", "error_string", "rate_workspace_bytes", "rate_run")
 
 PASS_NAMES = ("summarize", "resolve", "chain", "scan", "emit")
 
@@ -125,6 +125,10 @@ def lib():
         L.sampler_destroy.restype = None
         L.error_string.argtypes = [i32]
         L.error_string.restype = ctypes.c_char_p
+        L.rate_workspace_bytes.argtypes = [u64]
+        L.rate_workspace_bytes.restype = u64
+        L.rate_run.argtypes = [vp, u64, ctypes.c_int64, ctypes.c_uint32, vp, u64, vp, vp, vp]
+        L.rate_run.restype = i32
         _lib = L
     return _lib
 
@@ -144,6 +148,46 @@ def workspace_bytes(n_events, params: Params, ev_on_device=True) -> int:
 
 def sampler_fixed_bytes() -> int:
     return int(lib().sampler_fixed_bytes())
+
+
+def rate_workspace_bytes(n_events) -> int:
+    return int(lib().rate_workspace_bytes(int(n_events)))
+
+
+def rate_run(events, threshold, num_lines, *, workspace=None, line_counts=None, result=None, stream=None,
+             sync=True):
+    """Rate-based sampling (section 3.2) of one trace on the GPU.
+
+    ``events``: a CUDA uint8 tensor holding the 24-byte records.  Buffers
+    not given are allocated with torch on the events' device; ``stream``
+    defaults to torch's current stream.  With ``sync`` the call waits and
+    returns (status, K, samples per line as numpy); otherwise it returns the
+    device tensors (line_counts, result) and the results are ready when the
+    stream reaches them."""
+    import torch
+
+    if not (isinstance(events, torch.Tensor) and events.is_cuda and events.dtype == torch.uint8):
+        raise TypeError("events must be a CUDA uint8 tensor of 24-byte records")
+    if events.numel() % 24:
+        raise ValueError("events must hold whole 24-byte records")
+    n = events.numel() // 24
+    dev = events.device
+    if workspace is None:
+        workspace = torch.empty(rate_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    if line_counts is None:
+        line_counts = torch.empty(int(num_lines), dtype=torch.int64, device=dev)
+    if result is None:
+        result = torch.empty(2, dtype=torch.int64, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    code = lib().rate_run(events.data_ptr() if n else None, n, int(threshold), int(num_lines), workspace.data_ptr(),
+                          workspace.numel(), line_counts.data_ptr(), result.data_ptr(), stream.cuda_stream)
+    _check("rate_run", code)
+    if not sync:
+        return line_counts, result
+    stream.synchronize()
+    r = result.cpu().numpy()
+    return int(r[1]), int(r[0]), line_counts.cpu().numpy()
 
 
 def _check(fn, code):

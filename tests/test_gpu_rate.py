@@ -1,0 +1,136 @@
+"""GPU parity of the rate-based sampler (section 3.2) with the CPU oracle.
+
+Every case runs the HIP path through the C ABI (``rate_run``) and compares
+the status, the total count K and the samples per line with
+``oracle.rate`` exactly (integer work: bit-exact)."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2212_07597_amd as smp
+import tracegen as tg
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(ev):
+    import torch
+
+    if len(ev) == 0:
+        return torch.empty(0, dtype=torch.uint8, device="cuda")
+    return torch.from_numpy(np.ascontiguousarray(ev).view(np.uint8)).to("cuda")
+
+
+def check(ev, T, L, label):
+    st, K, counts = smp.rate_run(to_dev(ev), T, L)
+    ost, oK, ocounts = oracle.rate(ev, T, L)
+    assert st == ost, (label, st, ost)
+    if ost == oracle.OK:
+        assert K == oK, (label, K, oK)
+        np.testing.assert_array_equal(counts, ocounts, err_msg=label)
+    return K
+
+
+def test_rate_golden_fixtures():
+    spec = json.load(open(os.path.join(GOLDEN, "rate.json")))
+    for case in spec["cases"]:
+        w = json.load(open(os.path.join(GOLDEN, case["fixture"] + ".json")))
+        ev = tg.make_events([tuple(r) for r in w["events"]])
+        say(f"rate golden {case['fixture']}")
+        K = check(ev, w["params"]["threshold"], w["params"]["num_lines"], case["fixture"])
+        assert K == case["K"]
+
+
+def test_rate_empty():
+    st, K, counts = smp.rate_run(to_dev(tg.make_events([])), 10, 3)
+    assert (st, K) == (smp.SMP_OK, 0) and not counts.any()
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 511, 512, 513, 1500, 8 * 512 + 7, 100_000])
+def test_rate_config1_sizes(n):
+    """Sizes around a window, a segment, several segments and a ragged tail;
+    T from every byte a sample to rare samples."""
+    ev, kw = tg.config1(seed=n % 7 + 1, n=n)
+    for T in (1, 4096, 1 << 20, 10_000_019):
+        say(f"rate config1 n={n} T={T}")
+        check(ev, T, kw["num_lines"], f"n={n} T={T}")
+
+
+def test_rate_config3_traces():
+    plan = tg.config3_plan()
+    for (n, T, seed) in plan[:: 97]:
+        ev, kw = tg.config3_trace(n, T, seed)
+        say(f"rate config3 n={n} T={T}")
+        check(ev, kw["threshold"], kw["num_lines"], f"config3 n={n}")
+
+
+def test_rate_errors():
+    ev = tg.make_events([(5, 1, 0, 0, 0), (5, 1, 0, 0, 3)])
+    check(ev, 10, 1, "kind 3")
+    st, _, _ = smp.rate_run(to_dev(ev), 10, 1)
+    assert st == smp.SMP_EINVAL
+    ev = tg.make_events([(5, 1, 2, 0, 0)])
+    st, _, _ = smp.rate_run(to_dev(ev), 10, 2)
+    assert st == smp.SMP_EINVAL
+    big = (1 << 52) - 1
+    rows = [(big if i % 2 == 0 else -big, 1, 0, 0, 0) for i in range(1025)]
+    st, _, _ = smp.rate_run(to_dev(tg.make_events(rows)), 1 << 40, 1)
+    assert st == smp.SMP_EOVERFLOW
+    check(tg.make_events(rows[:1000]), 1 << 40, 1, "just below 2^62")
+    # a malformed record wins over an overflow
+    st, _, _ = smp.rate_run(to_dev(tg.make_events(rows + [(1, 1, 5, 0, 0)])), 1 << 40, 1)
+    assert st == smp.SMP_EINVAL
+
+
+def test_rate_bad_arguments():
+    import torch
+
+    dev = to_dev(tg.config1(seed=1, n=1000)[0])
+    for T, L in ((0, 4), (1 << 60, 4), (10, 0)):
+        with pytest.raises(smp.SamplerError):
+            smp.rate_run(dev, T, L)
+    with pytest.raises(smp.SamplerError):
+        smp.rate_run(dev, 10, 64, workspace=torch.empty(8, dtype=torch.uint8, device="cuda"))
+
+
+def test_rate_two_calls_share_nothing():
+    """Two traces in a row through caller-owned buffers: each result is its
+    own (the workspace is cleared by the call)."""
+    import torch
+
+    a, kw = tg.config1(seed=5, n=20_000)
+    b, _ = tg.config1(seed=6, n=3_000)
+    ws = torch.empty(smp.rate_workspace_bytes(len(a)), dtype=torch.uint8, device="cuda")
+    for ev in (a, b):
+        st, K, counts = smp.rate_run(to_dev(ev), 4096, kw["num_lines"], workspace=ws)
+        ost, oK, oc = oracle.rate(ev, 4096, kw["num_lines"])
+        assert (st, K) == (ost, oK)
+        np.testing.assert_array_equal(counts, oc)
+
+
+def test_rate_config2_full():
+    """The full config-2 trace (1e8 events, 10,000 lines, T = 10 MiB): counts
+    per line equal to the oracle's, and at least the threshold sampler's
+    sample count (a threshold sample needs T bytes of volume)."""
+    say("rate config 2: generating")
+    ev, kw = tg.config2()
+    say("  gpu")
+    st, K, counts = smp.rate_run(to_dev(ev), kw["threshold"], kw["num_lines"])
+    say("  oracle")
+    ost, oK, oc = oracle.rate(ev, kw["threshold"], kw["num_lines"])
+    assert (st, K) == (ost, oK)
+    np.testing.assert_array_equal(counts, oc)
+    say("  oracle, threshold sampler")
+    r = oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"])
+    assert len(r["samples"]) <= K
