@@ -69,7 +69,9 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and served measurements")
+    ap.add_argument("--no-extras", action="store_true", help="skip every extra measurement (same as --extras '')")
+    ap.add_argument("--extras", default="rate,config5,batched,served",
+                    help="comma-separated extra measurements: rate, config5, batched, served")
     ap.add_argument("--served-requests", type=int, default=1000)
     args = ap.parse_args()
 
@@ -168,14 +170,17 @@ def main():
                "sample": f"the full config-2 trace ({n} events), {reps} sequential pass(es), one host thread"}
 
     extras = {}
-    if not args.no_extras:
+    want = set() if args.no_extras else {x for x in args.extras.split(",") if x}
+    if "rate" in want:
         extras["rate"] = bench_rate(smp, tg, torch, np, s, dev, n, kw, K)
     s.close()
     del dev
     torch.cuda.empty_cache()
-    if not args.no_extras:
+    if "config5" in want:
         extras["config5"] = bench_config5(smp, tg, torch, np)
+    if "batched" in want:
         extras["batched"] = bench_batched(smp, tg, torch, np)
+    if "served" in want:
         extras["served"] = bench_served(smp, tg, torch, np, args.served_requests)
 
     out = {
