@@ -81,6 +81,9 @@ def lib():
         L.oracle_rate.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32,
                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]
         L.oracle_rate.restype = ctypes.c_int
+        p64c = ctypes.POINTER(ctypes.c_int64)
+        L.oracle_report_lines.argtypes = [p64c, p64c, p64c, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+        L.oracle_report_lines.restype = ctypes.c_uint32
         L.oracle_leak_scores.restype = None
         _lib = L
     return _lib
@@ -159,3 +162,15 @@ def rate(events, threshold, num_lines, options=0):
     st = lib().oracle_rate(ev.ctypes.data if ev.size else None, ev.shape[0], T, num_lines,
                            counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(K))
     return int(st), int(K.value), counts
+
+
+def report_lines(py_time, nat_time, growth_bytes):
+    """Report line filter (section 5): the ids of the lines with at least 1 %
+    of the time or of the growth bytes, and their neighbours, ascending."""
+    a = [np.ascontiguousarray(x, dtype=np.int64) for x in (py_time, nat_time, growth_bytes)]
+    L = a[0].shape[0]
+    out = np.zeros(max(L, 1), np.uint32)
+    p = ctypes.POINTER(ctypes.c_int64)
+    k = lib().oracle_report_lines(a[0].ctypes.data_as(p), a[1].ctypes.data_as(p), a[2].ctypes.data_as(p), L,
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    return out[:k].copy()

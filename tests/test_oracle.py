@@ -480,3 +480,56 @@ def test_rate_errors():
     assert st == oracle.EOVERFLOW
     st, K, _ = _rate(rows[:1000], {"threshold": 1 << 40, "num_lines": 1})
     assert st == oracle.OK and K == (1000 * big) >> 40
+
+
+# ------------------------------------------- report line filter (5) --
+
+def _rl(time=None, mem=None, L=None):
+    L = L or len(time if time is not None else mem)
+    z = np.zeros(L, np.int64)
+    t = np.asarray(time, np.int64) if time is not None else z
+    m = np.asarray(mem, np.int64) if mem is not None else z
+    return oracle.report_lines(t, z, m).tolist()
+
+
+def test_report_lines_hand_cases():
+    """Section 5: lines with at least 1 % of the time or of the memory, with
+    the line before and after each."""
+    assert _rl(mem=[0, 0, 10, 0, 0]) == [1, 2, 3]
+    assert _rl(mem=[10, 0, 0, 0, 0]) == [0, 1]          # no line before line 0
+    assert _rl(mem=[0, 0, 0, 0, 10]) == [3, 4]          # none after the last
+    assert _rl(time=[1] * 100) == list(range(100))      # exactly 1 % each: "at least"
+    assert _rl(time=[1] * 101) == []                    # just under 1 % each
+    assert _rl(time=[0] * 7) == []                      # no time at all
+    # the two criteria: line 2 by time, line 8 by memory
+    t = [0] * 12
+    t[2] = 5
+    m = [0] * 12
+    m[8] = 7
+    assert _rl(time=t, mem=m) == [1, 2, 3, 7, 8, 9]
+    # Python and native time add up: 0.6 % + 0.6 % of the time
+    py = np.zeros(200, np.int64)
+    nat = np.zeros(200, np.int64)
+    py[:] = 1
+    py[50], nat[50] = 3, 3     # line 50: 6 of 205
+    z = np.zeros(200, np.int64)
+    assert oracle.report_lines(py, nat, z).tolist() == [49, 50, 51]
+    # non-positive values never qualify and do not count in the total
+    assert _rl(mem=[-100, 1, 0]) == [0, 1, 2]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_report_lines_bounds(seed):
+    """At most 100 lines can hold 1 % of a total each, so one criterion
+    selects at most 300 lines with neighbours (the paper's bound); the two
+    criteria together at most 600."""
+    rng = np.random.default_rng(seed)
+    L = int(rng.integers(1, 5000))
+    t = (rng.pareto(1.0 + seed / 3, L) * 100).astype(np.int64)
+    m = (rng.pareto(0.8 + seed / 4, L) * 1000).astype(np.int64)
+    z = np.zeros(L, np.int64)
+    sel_t = oracle.report_lines(t, z, z)
+    sel_m = oracle.report_lines(z, z, m)
+    both = oracle.report_lines(t, z, m)
+    assert len(sel_t) <= 300 and len(sel_m) <= 300 and len(both) <= 600
+    assert sorted(set(sel_t) | set(sel_m)) == both.tolist()
