@@ -301,6 +301,23 @@ SMP_API uint64_t rate_workspace_bytes(uint64_t n_events);
 SMP_API int rate_run(const smp_event_t *ev, uint64_t n, int64_t threshold, uint32_t num_lines, void *workspace,
                      uint64_t workspace_bytes, int64_t *line_counts, uint64_t *result, void *hip_stream);
 
+/* ---- report line filter (section 5) -----------------------------------
+ * The lines a profile shows: those with at least 1 % of the execution time
+ * or at least 1 % of the memory, each with the line before and the line
+ * after it.  Readings: a line's time is py_time_us + nat_time_us (timer
+ * samples), its memory growth_bytes (bytes of its growth samples), both as
+ * fetch_profile returns them; "at least 1 %" is 100 x >= the total of the
+ * lines' positive values (a line with x <= 0 never qualifies; a zero total
+ * selects nothing); neighbours are the ids one below and one above, inside
+ * [0, num_lines).  At most 100 lines can hold 1 % each, so one criterion
+ * selects at most 300 lines and the two together at most 600.
+ *   py_time_us, nat_time_us, growth_bytes : host arrays of num_lines values
+ *   out_lines : host array with room for num_lines ids, written in
+ *               increasing order; *n_out receives their number
+ * Host-only; returns SMP_EINVAL for missing pointers, else SMP_OK. */
+SMP_API int report_lines(const int64_t *py_time_us, const int64_t *nat_time_us, const int64_t *growth_bytes,
+                         uint32_t num_lines, uint32_t *out_lines, uint32_t *n_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,7 +31,7 @@ TRACKED_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("ptr", "<u4"),
 EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", "fetch_profile",
             "trace_device_results", "submit_traces", "release_traces", "sampler_last_timing",
             "sampler_set_pass_events", "sampler_last_pass_timing", "sampler_last_counters", "sampler_fixed_bytes",
-            "sampler_destroy", "error_string", "rate_workspace_bytes", "rate_run")
+            "sampler_destroy", "error_string", "rate_workspace_bytes", "rate_run", "report_lines")
 
 PASS_NAMES = ("summarize", "resolve", "chain", "scan", "emit")
 
@@ -129,6 +129,10 @@ def lib():
         L.rate_workspace_bytes.restype = u64
         L.rate_run.argtypes = [vp, u64, ctypes.c_int64, ctypes.c_uint32, vp, u64, vp, vp, vp]
         L.rate_run.restype = i32
+        p64 = ctypes.POINTER(ctypes.c_int64)
+        L.report_lines.argtypes = [p64, p64, p64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                   ctypes.POINTER(ctypes.c_uint32)]
+        L.report_lines.restype = i32
         _lib = L
     return _lib
 
@@ -188,6 +192,22 @@ def rate_run(events, threshold, num_lines, *, workspace=None, line_counts=None, 
     stream.synchronize()
     r = result.cpu().numpy()
     return int(r[1]), int(r[0]), line_counts.cpu().numpy()
+
+
+def report_lines(py_time_us, nat_time_us, growth_bytes):
+    """Report line filter (section 5): ids of the lines with at least 1 % of
+    the time or of the memory, with their neighbours, ascending (numpy)."""
+    a = [np.ascontiguousarray(x, dtype=np.int64) for x in (py_time_us, nat_time_us, growth_bytes)]
+    L = a[0].shape[0]
+    if a[1].shape[0] != L or a[2].shape[0] != L:
+        raise ValueError("the three arrays must have one value per line")
+    out = np.zeros(max(L, 1), np.uint32)
+    k = ctypes.c_uint32(0)
+    p = ctypes.POINTER(ctypes.c_int64)
+    _check("report_lines", lib().report_lines(a[0].ctypes.data_as(p), a[1].ctypes.data_as(p), a[2].ctypes.data_as(p),
+                                              L, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                              ctypes.byref(k)))
+    return out[: k.value].copy()
 
 
 def _check(fn, code):

@@ -71,3 +71,29 @@ def test_record_layouts_match_header():
     assert smp.SAMPLE_DTYPE.itemsize == 24 + 8  # 32-byte sample
     assert smp.TRACKED_DTYPE.itemsize == 16
     assert ctypes.sizeof(smp.Params) == 32
+
+
+def test_report_lines_matches_oracle():
+    """The library's report line filter (host code) against the oracle's, on
+    skewed, flat, sparse and negative per-line values, edge sizes included."""
+    import oracle
+
+    rng = np.random.default_rng(7)
+    sizes = [0, 1, 2, 3, 99, 100, 101, 300, 5000, 20000]
+    for i, L in enumerate(sizes * 3):
+        kind = i // len(sizes)
+        if kind == 0:    # skewed
+            py = (rng.pareto(1.1, L) * 50).astype(np.int64)
+            nat = (rng.pareto(1.5, L) * 50).astype(np.int64)
+            gb = (rng.pareto(0.9, L) * 1e6).astype(np.int64)
+        elif kind == 1:  # flat with a few large lines, many zeros
+            py = np.where(rng.random(L) < 0.3, 1, 0).astype(np.int64)
+            nat = np.zeros(L, np.int64)
+            gb = np.where(rng.random(L) < 0.01, 1 << 40, 0).astype(np.int64)
+        else:            # signed values (per-line sums wrap modulo 2^64)
+            py = rng.integers(-1000, 1000, L).astype(np.int64)
+            nat = rng.integers(-10, 10, L).astype(np.int64)
+            gb = rng.integers(-(1 << 62), 1 << 62, L).astype(np.int64)
+        got = smp.report_lines(py, nat, gb)
+        want = oracle.report_lines(py, nat, gb)
+        assert got.tolist() == want.tolist(), (L, kind)
