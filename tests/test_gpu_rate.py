@@ -136,15 +136,19 @@ def test_rate_config2_full():
     assert len(r["samples"]) <= K
 
 
-def test_report_lines_on_a_gpu_profile(sampler):
+def test_report_lines_on_a_gpu_profile():
     """The report line filter on the per-line arrays of a GPU profile of the
     copy-and-timer mix (config 5's mix at 1e6 events): library and oracle
     select the same lines."""
     ev, kw = tg.config5(n=1_000_000)
     p = smp.make_params(kw["threshold"], kw["num_lines"], kw["copy_threshold"], kw["quantum_us"])
-    tid = sampler.submit_trace(to_dev(ev), p)
-    sampler.run(blocking=True)
-    g = sampler.fetch_profile(tid)
+    sampler = smp.Sampler(workspace=smp.sampler_fixed_bytes() + smp.workspace_bytes(len(ev), p) + (16 << 20))
+    try:
+        tid = sampler.submit_trace(to_dev(ev), p)
+        sampler.run(blocking=True)
+        g = sampler.fetch_profile(tid)
+    finally:
+        sampler.close()
     got = smp.report_lines(g["py_time_us"], g["nat_time_us"], g["growth_bytes"])
     want = oracle.report_lines(g["py_time_us"], g["nat_time_us"], g["growth_bytes"])
     assert got.tolist() == want.tolist()
