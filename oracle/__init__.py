@@ -174,3 +174,36 @@ def report_lines(py_time, nat_time, growth_bytes):
     k = lib().oracle_report_lines(a[0].ctypes.data_as(p), a[1].ctypes.data_as(p), a[2].ctypes.data_as(p), L,
                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
     return out[:k].copy()
+
+
+def _wrap64(v):
+    v &= (1 << 64) - 1
+    return v - (1 << 64) if v >> 63 else v
+
+
+def leak_report(samples, gate, py_time_us, nat_time_us):
+    """Leak report filter (section 3.4), in Python's exact integers.
+
+    The slope of overall memory growth: the least-squares line of the
+    sampled footprint F against the event index over the K samples; it
+    passes when its rise over the sampled span is at least 1 % of the peak
+    sampled footprint: 100 b (x_K - x_1) >= max F, b = (K Sxy - Sx Sy) /
+    (K Sxx - Sx^2).  K < 2 or a peak <= 0 never passes.  A line's leak is
+    reported when its likelihood gate is set and the slope passes.  The
+    elapsed time that a leak rate divides by is the trace's total Python plus
+    native time (the per-line values summed modulo 2^64, as they wrap).
+    Returns (slope_ok, reported per line, elapsed_us)."""
+    x = [int(v) for v in samples["event_idx"]]
+    y = [int(v) for v in samples["F"]]
+    K = len(x)
+    ok = False
+    if K >= 2 and max(y) > 0:
+        Sx, Sy = sum(x), sum(y)
+        Sxx = sum(v * v for v in x)
+        Sxy = sum(a * b for a, b in zip(x, y))
+        num = K * Sxy - Sx * Sy
+        den = K * Sxx - Sx * Sx
+        ok = den > 0 and 100 * num * (x[-1] - x[0]) >= max(y) * den
+    reported = (np.asarray(gate, np.uint8) != 0) & ok
+    elapsed = _wrap64(sum(int(a) + int(b) for a, b in zip(py_time_us, nat_time_us)))
+    return ok, reported.astype(np.uint8), elapsed

@@ -533,3 +533,60 @@ def test_report_lines_bounds(seed):
     both = oracle.report_lines(t, z, m)
     assert len(sel_t) <= 300 and len(sel_m) <= 300 and len(both) <= 600
     assert sorted(set(sel_t) | set(sel_m)) == both.tolist()
+
+
+# ------------------------------------------------ leak report (3.4) --
+
+def _samples(xs, ys):
+    s = np.zeros(len(xs), oracle.SAMPLE_DTYPE)
+    s["event_idx"] = xs
+    s["F"] = ys
+    return s
+
+
+def test_leak_report_slope_hand_cases():
+    """Section 3.4: leaks are reported only when overall memory grows by at
+    least 1 % (read as the fitted rise over the sampled span against the
+    peak sampled footprint)."""
+    g = np.ones(3, np.uint8)
+    z = np.zeros(3, np.int64)
+    ok, rep, _ = oracle.leak_report(_samples(range(10), [10 * i for i in range(10)]), g, z, z)
+    assert ok and rep.tolist() == [1, 1, 1]                  # a straight rise
+    ok, _, _ = oracle.leak_report(_samples(range(10), [50] * 10), g, z, z)
+    assert not ok                                              # flat: slope 0
+    ok, _, _ = oracle.leak_report(_samples(range(10), [90 - 10 * i for i in range(10)]), g, z, z)
+    assert not ok                                              # falling
+    ok, _, _ = oracle.leak_report(_samples([5], [100]), g, z, z)
+    assert not ok                                              # one sample
+    # two samples: slope (y1 - y0) / (x1 - x0), rise y1 - y0, peak max(y0, y1)
+    ok, _, _ = oracle.leak_report(_samples([0, 7], [1000, 1010]), g, z, z)
+    assert not ok                                              # rise 10 of peak 1010: 1000 < 1010
+    ok, _, _ = oracle.leak_report(_samples([0, 7], [990, 1000]), g, z, z)
+    assert ok                                                  # rise 10 of peak 1000: exactly 1 %
+    ok, _, _ = oracle.leak_report(_samples([0, 7], [991, 1000]), g, z, z)
+    assert not ok                                              # rise 9 of peak 1000: 900 < 1000
+    ok, rep, _ = oracle.leak_report(_samples(range(4), [0, 1, 2, 3]), np.array([1, 0, 1], np.uint8), z, z)
+    assert rep.tolist() == [1, 0, 1]                           # gate and slope
+    ok, _, el = oracle.leak_report(_samples([0], [0]), g, np.array([5, 6, 7]), np.array([1, 2, 3]))
+    assert el == 24
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_leak_report_slope_against_float_fit(seed):
+    """Away from the 1 % boundary the exact decision agrees with a
+    floating-point least-squares fit (numpy.polyfit), an independent
+    formulation."""
+    rng = np.random.default_rng(seed)
+    for _ in range(40):
+        K = int(rng.integers(2, 400))
+        x = np.sort(rng.choice(1 << 20, K, replace=False)).astype(np.int64)
+        trend = rng.normal(0, 2e-3)
+        y = (1e6 + trend * 1e6 * (x - x[0]) / max(1, x[-1] - x[0]) + rng.normal(0, 1e3, K)).astype(np.int64)
+        b = np.polyfit(x.astype(np.float64), y.astype(np.float64), 1)[0]
+        rise = b * (x[-1] - x[0])
+        ratio = 100 * rise / y.max()
+        if abs(ratio - 1) < 0.01:
+            continue
+        ok, _, _ = oracle.leak_report(_samples(x, y), np.ones(1, np.uint8), np.zeros(1, np.int64),
+                                      np.zeros(1, np.int64))
+        assert ok == (ratio >= 1), (K, ratio)
