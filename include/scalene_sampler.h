@@ -318,6 +318,27 @@ SMP_API int rate_run(const smp_event_t *ev, uint64_t n, int64_t threshold, uint3
 SMP_API int report_lines(const int64_t *py_time_us, const int64_t *nat_time_us, const int64_t *growth_bytes,
                          uint32_t num_lines, uint32_t *out_lines, uint32_t *n_out);
 
+/* ---- leak report filter (section 3.4) ---------------------------------
+ * Leaks are reported only when their likelihood passes its gate and overall
+ * memory grows by at least 1 %.  Reading of the growth test: the
+ * least-squares line of the sampled footprint F against the event index
+ * over the K samples passes when its rise over the sampled span is at least
+ * 1 % of the peak sampled footprint, 100 b (x_K - x_1) >= max F with
+ * b = (K Sxy - Sx Sy) / (K Sxx - Sx^2), decided exactly (K < 2 or a peak
+ * <= 0 never passes).  The leak rate of a line (bytes allocated at it per
+ * elapsed time; bytes per microsecond is MB/s) divides its growth_bytes by
+ * *elapsed_us, the trace's total Python plus native time.
+ *   samples, n_samples : the profile's samples in rank order (host)
+ *   gate               : num_lines report gates (SMP_G_LAP or SMP_G_LIT row)
+ *   py_time_us, nat_time_us : num_lines values (host)
+ *   slope_ok  : out, 1 if the growth test passes
+ *   reported  : out, num_lines flags: gate and growth test
+ *   elapsed_us: out, the sum of py_time_us + nat_time_us modulo 2^64
+ * Host-only; returns SMP_EINVAL for missing pointers or n_samples >= 2^32. */
+SMP_API int leak_report(const smp_sample_t *samples, uint64_t n_samples, const uint8_t *gate,
+                        const int64_t *py_time_us, const int64_t *nat_time_us, uint32_t num_lines,
+                        int32_t *slope_ok, uint8_t *reported, int64_t *elapsed_us);
+
 #ifdef __cplusplus
 }
 #endif

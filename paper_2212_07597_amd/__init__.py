@@ -31,7 +31,8 @@ TRACKED_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("ptr", "<u4"),
 EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", "fetch_profile",
             "trace_device_results", "submit_traces", "release_traces", "sampler_last_timing",
             "sampler_set_pass_events", "sampler_last_pass_timing", "sampler_last_counters", "sampler_fixed_bytes",
-            "sampler_destroy", "error_string", "rate_workspace_bytes", "rate_run", "report_lines")
+            "sampler_destroy", "error_string", "rate_workspace_bytes", "rate_run", "report_lines",
+            "leak_report")
 
 PASS_NAMES = ("summarize", "resolve", "chain", "scan", "emit")
 
@@ -133,6 +134,9 @@ def lib():
         L.report_lines.argtypes = [p64, p64, p64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                    ctypes.POINTER(ctypes.c_uint32)]
         L.report_lines.restype = i32
+        L.leak_report.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_uint8), p64, p64, ctypes.c_uint32,
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint8), p64]
+        L.leak_report.restype = i32
         _lib = L
     return _lib
 
@@ -208,6 +212,27 @@ def report_lines(py_time_us, nat_time_us, growth_bytes):
                                               L, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                               ctypes.byref(k)))
     return out[: k.value].copy()
+
+
+def leak_report(samples, gate, py_time_us, nat_time_us):
+    """Leak report filter (section 3.4): (growth test passed, reported flag
+    per line, elapsed microseconds) from a profile's samples (SAMPLE_DTYPE,
+    rank order), one row of its report gates and its time arrays."""
+    smp_ = np.ascontiguousarray(samples, dtype=SAMPLE_DTYPE)
+    g = np.ascontiguousarray(gate, dtype=np.uint8)
+    a = [np.ascontiguousarray(x, dtype=np.int64) for x in (py_time_us, nat_time_us)]
+    L = g.shape[0]
+    if a[0].shape[0] != L or a[1].shape[0] != L:
+        raise ValueError("gate and the time arrays must have one value per line")
+    rep = np.zeros(max(L, 1), np.uint8)
+    ok = ctypes.c_int32(0)
+    el = ctypes.c_int64(0)
+    p = ctypes.POINTER(ctypes.c_int64)
+    _check("leak_report", lib().leak_report(smp_.ctypes.data if smp_.size else None, smp_.shape[0],
+                                            g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), a[0].ctypes.data_as(p),
+                                            a[1].ctypes.data_as(p), L, ctypes.byref(ok),
+                                            rep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.byref(el)))
+    return bool(ok.value), rep[:L].copy(), int(el.value)
 
 
 def _check(fn, code):

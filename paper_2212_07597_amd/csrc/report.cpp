@@ -51,3 +51,130 @@ extern "C" SMP_API int report_lines(const int64_t* py_time_us, const int64_t* na
     *n_out = k;
     return SMP_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Leak report filter (section 3.4): leaks are reported only when overall
+// memory grows by at least 1 %.  Read as the least-squares line of the
+// sampled footprint F against the event index x over the K samples: it
+// passes when its rise over the sampled span, b (x_K - x_1) with
+// b = (K Sxy - Sx Sy) / (K Sxx - Sx^2), is at least 1 % of the peak sampled
+// footprint.  The sums fit in 128 bits (x < 2^32, |F| < 2^61, K < 2^32); the
+// comparison 100 num span >= peak den needs up to ~197 bits, done here on
+// four 64-bit limbs with signs kept apart.
+
+namespace {
+
+struct U256 {
+    uint64_t w[4];
+};
+
+U256 u256(unsigned __int128 v) { return U256{{(uint64_t)v, (uint64_t)(v >> 64), 0, 0}}; }
+
+U256 add(const U256& a, const U256& b) {
+    U256 r{};
+    unsigned __int128 c = 0;
+    for (int i = 0; i < 4; ++i) {
+        const unsigned __int128 s = (unsigned __int128)a.w[i] + b.w[i] + c;
+        r.w[i] = (uint64_t)s;
+        c = s >> 64;
+    }
+    return r;
+}
+
+U256 sub(const U256& a, const U256& b) {  // a >= b
+    U256 r{};
+    uint64_t borrow = 0;
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t d = a.w[i] - b.w[i] - borrow;
+        borrow = (a.w[i] < b.w[i] || (a.w[i] == b.w[i] && borrow)) ? 1 : 0;
+        r.w[i] = d;
+    }
+    return r;
+}
+
+int cmp(const U256& a, const U256& b) {
+    for (int i = 3; i >= 0; --i)
+        if (a.w[i] != b.w[i]) return a.w[i] < b.w[i] ? -1 : 1;
+    return 0;
+}
+
+bool is_zero(const U256& a) { return !(a.w[0] | a.w[1] | a.w[2] | a.w[3]); }
+
+U256 mul64(const U256& a, uint64_t b) {  // the product stays below 2^256 here
+    U256 r{};
+    unsigned __int128 c = 0;
+    for (int i = 0; i < 4; ++i) {
+        const unsigned __int128 p = (unsigned __int128)a.w[i] * b + c;
+        r.w[i] = (uint64_t)p;
+        c = p >> 64;
+    }
+    return r;
+}
+
+U256 mul128(unsigned __int128 a, unsigned __int128 b) {
+    const U256 lo = mul64(u256(a), (uint64_t)b);
+    const U256 hi = mul64(u256(a), (uint64_t)(b >> 64));
+    return add(lo, U256{{0, hi.w[0], hi.w[1], hi.w[2]}});
+}
+
+unsigned __int128 mag(__int128 v) { return v < 0 ? (unsigned __int128)(-(v + 1)) + 1 : (unsigned __int128)v; }
+
+}  // namespace
+
+extern "C" SMP_API int leak_report(const smp_sample_t* samples, uint64_t n_samples, const uint8_t* gate,
+                                   const int64_t* py_time_us, const int64_t* nat_time_us, uint32_t num_lines,
+                                   int32_t* slope_ok, uint8_t* reported, int64_t* elapsed_us) {
+    if (!slope_ok || !elapsed_us || (n_samples && !samples) ||
+        (num_lines && (!gate || !py_time_us || !nat_time_us || !reported)))
+        return SMP_EINVAL;
+    if (n_samples >= (1ull << 32)) return SMP_EINVAL;
+    bool ok = false;
+    if (n_samples >= 2) {
+        unsigned __int128 Sx = 0, Sxx = 0;
+        __int128 Sy = 0, Sxy = 0;
+        int64_t peak = samples[0].F;
+        for (uint64_t k = 0; k < n_samples; ++k) {
+            const uint64_t x = samples[k].event_idx;
+            const int64_t y = samples[k].F;
+            Sx += x;
+            Sxx += (unsigned __int128)x * x;
+            Sy += y;
+            Sxy += (__int128)x * y;
+            if (y > peak) peak = y;
+        }
+        const uint64_t K = n_samples;
+        const uint64_t x0 = samples[0].event_idx, x1 = samples[n_samples - 1].event_idx;
+        if (peak > 0 && x1 > x0) {
+            // num = K Sxy - Sx Sy as (sign, magnitude)
+            const bool a_neg = Sxy < 0, b_neg = Sy < 0;
+            const U256 A = mul128(K, mag(Sxy)), B = mul128(Sx, mag(Sy));
+            bool n_neg;
+            U256 N;
+            if (a_neg != b_neg) {
+                n_neg = a_neg;
+                N = add(A, B);
+            } else if (cmp(A, B) >= 0) {
+                n_neg = a_neg;
+                N = sub(A, B);
+            } else {
+                n_neg = !a_neg;
+                N = sub(B, A);
+            }
+            const U256 KSxx = mul128(K, Sxx), Sx2 = mul128(Sx, Sx);
+            if (!n_neg && !is_zero(N) && cmp(KSxx, Sx2) > 0) {
+                const U256 den = sub(KSxx, Sx2);
+                const U256 lhs = mul64(mul64(N, x1 - x0), 100);
+                const U256 rhs = mul64(den, (uint64_t)peak);
+                ok = cmp(lhs, rhs) >= 0;
+            }
+        }
+    }
+    *slope_ok = ok ? 1 : 0;
+    uint64_t el = 0;
+    for (uint32_t l = 0; l < num_lines; ++l) {
+        el += (uint64_t)py_time_us[l] + (uint64_t)nat_time_us[l];  // modulo 2^64, as the per-line sums
+        reported[l] = (ok && gate[l]) ? 1 : 0;
+    }
+    *elapsed_us = (int64_t)el;
+    return SMP_OK;
+}

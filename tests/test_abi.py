@@ -97,3 +97,43 @@ def test_report_lines_matches_oracle():
         got = smp.report_lines(py, nat, gb)
         want = oracle.report_lines(py, nat, gb)
         assert got.tolist() == want.tolist(), (L, kind)
+
+
+def test_leak_report_matches_oracle():
+    """The library's growth test (exact, on 256-bit integers of four limbs)
+    against the oracle's Python integers: random sample sets from tiny to
+    extreme magnitudes (event indices near 2^32, footprints near +-2^60),
+    and two-sample sets placed exactly on and around the 1 % boundary."""
+    import oracle
+
+    rng = np.random.default_rng(11)
+    L = 5
+    gate = np.array([1, 0, 1, 1, 0], np.uint8)
+    py = rng.integers(-(1 << 62), 1 << 62, L).astype(np.int64)
+    nat = rng.integers(-(1 << 62), 1 << 62, L).astype(np.int64)
+
+    def both(x, y):
+        s = np.zeros(len(x), smp.SAMPLE_DTYPE)
+        s["event_idx"] = x
+        s["F"] = y
+        got = smp.leak_report(s, gate, py, nat)
+        want = oracle.leak_report(s, gate, py, nat)
+        assert got[0] == want[0] and got[1].tolist() == want[1].tolist() and got[2] == want[2], (x[:4], y[:4])
+        return got[0]
+
+    seen = set()
+    for trial in range(300):
+        K = int(rng.integers(0, 3000 if trial % 10 else 20))
+        top = [1 << 10, 1 << 20, (1 << 32) - 1][trial % 3]
+        x = np.sort(rng.choice(top, min(K, top), replace=False)).astype(np.uint32)
+        mag_ = [1 << 20, 1 << 40, 1 << 60][(trial // 3) % 3]
+        base = int(rng.integers(-mag_, mag_))
+        drift = rng.normal(0, mag_ / 50)
+        y = np.clip(base + drift * np.linspace(0, 1, len(x)) + rng.normal(0, mag_ / 100, len(x)),
+                    -(1 << 60), 1 << 60).astype(np.int64)
+        seen.add(both(x, y))
+    assert seen == {True, False}
+    # exactly 1 %: rise r of peak 100 r passes, peak 100 r + 1 does not
+    for r in (1, 7, 1 << 20, 1 << 50):
+        for peak, want in ((100 * r, True), (100 * r + 1, False)):
+            assert both(np.array([3, (1 << 32) - 1], np.uint32), np.array([peak - r, peak], np.int64)) == want

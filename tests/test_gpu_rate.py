@@ -153,3 +153,26 @@ def test_report_lines_on_a_gpu_profile():
     want = oracle.report_lines(g["py_time_us"], g["nat_time_us"], g["growth_bytes"])
     assert got.tolist() == want.tolist()
     assert 0 < len(got) <= 600
+
+
+def test_leak_report_on_gpu_profiles():
+    """The leak report filter on GPU profiles (config 1; 1e7 events of the
+    config-2 lifetime mix, whose leaked objects make memory grow): library
+    and oracle agree on the growth test, the reported lines and the elapsed
+    time, for both likelihood readings' gates."""
+    cases = [tg.config1(seed=2), tg.config2(seed=3, n=10_000_000)]
+    for ev, kw in cases:
+        p = smp.make_params(kw["threshold"], kw["num_lines"])
+        sampler = smp.Sampler(workspace=smp.sampler_fixed_bytes() + smp.workspace_bytes(len(ev), p) + (16 << 20))
+        try:
+            tid = sampler.submit_trace(to_dev(ev), p)
+            sampler.run(blocking=True)
+            g = sampler.fetch_profile(tid)
+        finally:
+            sampler.close()
+        say(f"leak report: {len(ev)} events, {len(g['samples'])} samples")
+        for gate_name in smp.GATE_NAMES:
+            got = smp.leak_report(g["samples"], g[gate_name], g["py_time_us"], g["nat_time_us"])
+            want = oracle.leak_report(g["samples"], g[gate_name], g["py_time_us"], g["nat_time_us"])
+            assert got[0] == want[0] and got[2] == want[2]
+            assert got[1].tolist() == want[1].tolist()
