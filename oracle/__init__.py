@@ -207,3 +207,58 @@ def leak_report(samples, gate, py_time_us, nat_time_us):
     reported = (np.asarray(gate, np.uint8) != 0) & ok
     elapsed = _wrap64(sum(int(a) + int(b) for a, b in zip(py_time_us, nat_time_us)))
     return ok, reported.astype(np.uint8), elapsed
+
+
+def _rdp_keep(x, y, eps2):
+    """Ramer-Douglas-Peucker over the points (x[i], y[i]), exact: a point is
+    kept when its distance from the chord of its run exceeds eps, i.e.
+    cross^2 > eps^2 (dx^2 + dy^2); the farthest point of a run (the first
+    on ties) splits it.  Returns the kept indices, ascending."""
+    n = len(x)
+    if n <= 2:
+        return list(range(n))
+    keep = {0, n - 1}
+    runs = [(0, n - 1)]
+    while runs:
+        i, j = runs.pop()
+        if j - i < 2:
+            continue
+        dx, dy = x[j] - x[i], y[j] - y[i]
+        best, bk = -1, -1
+        for k in range(i + 1, j):
+            c = abs(dx * (y[k] - y[i]) - dy * (x[k] - x[i]))
+            if c > best:
+                best, bk = c, k
+        if best * best > eps2 * (dx * dx + dy * dy):
+            keep.add(bk)
+            runs.append((i, bk))
+            runs.append((bk, j))
+    return sorted(keep)
+
+
+def timeline_points(samples, num_lines, max_points=100):
+    """Per-line memory timelines (section 5): each line's samples in rank
+    order as points (event index, footprint), reduced by RDP with the
+    smallest eps in {0, 1, 2, 4, ..., 2^62} that leaves at most max_points
+    points.  Returns a keep flag per sample."""
+    lines = [int(v) for v in samples["line"]]
+    xs = [int(v) for v in samples["event_idx"]]
+    ys = [int(v) for v in samples["F"]]
+    by_line = {}
+    for r, l in enumerate(lines):
+        if l < num_lines:
+            by_line.setdefault(l, []).append(r)
+    keep = np.zeros(len(lines), np.uint8)
+    cands = [0] + [1 << e for e in range(63)]
+    for l, idx in by_line.items():
+        x = [xs[r] for r in idx]
+        y = [ys[r] for r in idx]
+        chosen = None
+        for eps in cands:   # the kept set only shrinks as eps grows
+            kept = _rdp_keep(x, y, eps * eps)
+            if len(kept) <= max_points:
+                chosen = kept
+                break
+        for k in chosen:
+            keep[idx[k]] = 1
+    return keep

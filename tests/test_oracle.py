@@ -590,3 +590,77 @@ def test_leak_report_slope_against_float_fit(seed):
         ok, _, _ = oracle.leak_report(_samples(x, y), np.ones(1, np.uint8), np.zeros(1, np.int64),
                                       np.zeros(1, np.int64))
         assert ok == (ratio >= 1), (K, ratio)
+
+
+# ------------------------------------- per-line timelines and RDP (5) --
+
+def _tl(xs, ys, lines=0, L=1, max_points=100):
+    s = np.zeros(len(xs), oracle.SAMPLE_DTYPE)
+    s["event_idx"] = xs
+    s["F"] = ys
+    s["line"] = lines
+    return oracle.timeline_points(s, L, max_points)
+
+
+def _float_rdp(x, y, eps):
+    """Textbook recursive RDP in floating point (an independent formulation)."""
+    def rec(i, j, out):
+        if j - i < 2:
+            return
+        dx, dy = x[j] - x[i], y[j] - y[i]
+        d = [abs(dx * (y[k] - y[i]) - dy * (x[k] - x[i])) / np.hypot(dx, dy) for k in range(i + 1, j)]
+        k = int(np.argmax(d)) + i + 1
+        if d[k - i - 1] > eps:
+            out.add(k)
+            rec(i, k, out)
+            rec(k, j, out)
+    out = {0, len(x) - 1}
+    rec(0, len(x) - 1, out)
+    return sorted(out)
+
+
+def test_timeline_hand_cases():
+    """Section 5: each line's footprint log reduced by RDP to about 100
+    points."""
+    assert _tl(range(5), [0, 10, 20, 30, 40]).tolist() == [1, 0, 0, 0, 1]     # collinear: the chord
+    assert _tl(range(5), [0, 0, 50, 0, 0]).tolist() == [1] * 5                # nothing collinear, <= 100
+    y = [7 * i for i in range(1000)]
+    y[400] += 1 << 40
+    k = _tl(range(1000), y)
+    assert np.flatnonzero(k).tolist() == [0, 399, 400, 401, 999]              # a line and one spike: its corners
+    assert _tl([3], [5]).tolist() == [1] and _tl([], []).tolist() == []
+
+
+def test_timeline_lines_are_independent():
+    rng = np.random.default_rng(3)
+    n = 900
+    x = np.arange(n) * 3
+    y = np.cumsum(rng.integers(-1000, 1000, n))
+    lines = rng.integers(0, 4, n)
+    both = _tl(x, y, lines, L=4)
+    for l in range(4):
+        m = lines == l
+        alone = _tl(x[m], y[m])
+        assert both[m].tolist() == alone.tolist()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_timeline_bound_and_minimal_eps(seed):
+    """At most 100 points per line, always the first and last sample; the
+    chosen eps is the smallest candidate that gets there, so the next smaller
+    one keeps more than 100; and the kept set equals a floating-point
+    recursive RDP at that eps (random walks: no ties at the threshold)."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(150, 1200))
+    x = np.cumsum(rng.integers(1, 50, n))
+    y = np.cumsum(rng.normal(0, 1e5, n)).astype(np.int64)
+    k = _tl(x, y)
+    kept = np.flatnonzero(k).tolist()
+    assert len(kept) <= 100 and kept[0] == 0 and kept[-1] == n - 1
+    xi, yi = [int(v) for v in x], [int(v) for v in y]
+    cands = [0] + [1 << e for e in range(63)]
+    eps = next(e for e in cands if len(oracle._rdp_keep(xi, yi, e * e)) <= 100)
+    prev = cands[cands.index(eps) - 1] if eps else None
+    if prev is not None:
+        assert len(oracle._rdp_keep(xi, yi, prev * prev)) > 100
+    assert kept == _float_rdp(np.array(x, float), np.array(y, float), float(eps))
