@@ -339,6 +339,24 @@ SMP_API int leak_report(const smp_sample_t *samples, uint64_t n_samples, const u
                         const int64_t *py_time_us, const int64_t *nat_time_us, uint32_t num_lines,
                         int32_t *slope_ok, uint8_t *reported, int64_t *elapsed_us);
 
+/* ---- per-line memory timelines (section 5) ----------------------------
+ * Each line's footprint log (its samples in rank order, as points (event
+ * index, footprint)) reduced by Ramer-Douglas-Peucker to at most max_points
+ * points (the paper uses 100).  A point is kept when its distance from the
+ * chord of its run exceeds eps, decided exactly (cross^2 > eps^2 len^2); the
+ * farthest point of a run, the first on ties, splits it; eps is the smallest
+ * of {0, 1, 2, 4, ..., 2^62} that leaves at most max_points points, so the
+ * random downsampling the paper applies after an approximate eps is never
+ * needed.  Samples whose line is >= num_lines belong to no timeline.
+ *   samples, n_samples : the profile's samples in rank order (host)
+ *   max_points         : >= 2
+ *   keep               : out, n_samples flags: 1 = the sample is a point of
+ *                        its line's reduced timeline
+ * Host-only; returns SMP_EINVAL for missing pointers, max_points < 2 or
+ * n_samples >= 2^32. */
+SMP_API int timeline_points(const smp_sample_t *samples, uint64_t n_samples, uint32_t num_lines,
+                            uint32_t max_points, uint8_t *keep);
+
 #ifdef __cplusplus
 }
 #endif

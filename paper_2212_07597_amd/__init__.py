@@ -32,7 +32,7 @@ EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", 
             "trace_device_results", "submit_traces", "release_traces", "sampler_last_timing",
             "sampler_set_pass_events", "sampler_last_pass_timing", "sampler_last_counters", "sampler_fixed_bytes",
             "sampler_destroy", "error_string", "rate_workspace_bytes", "rate_run", "report_lines",
-            "leak_report")
+            "leak_report", "timeline_points")
 
 PASS_NAMES = ("summarize", "resolve", "chain", "scan", "emit")
 
@@ -137,6 +137,8 @@ def lib():
         L.leak_report.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_uint8), p64, p64, ctypes.c_uint32,
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint8), p64]
         L.leak_report.restype = i32
+        L.timeline_points.argtypes = [vp, u64, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint8)]
+        L.timeline_points.restype = i32
         _lib = L
     return _lib
 
@@ -233,6 +235,17 @@ def leak_report(samples, gate, py_time_us, nat_time_us):
                                             a[1].ctypes.data_as(p), L, ctypes.byref(ok),
                                             rep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.byref(el)))
     return bool(ok.value), rep[:L].copy(), int(el.value)
+
+
+def timeline_points(samples, num_lines, max_points=100):
+    """Per-line memory timelines (section 5): a keep flag per sample, 1 for
+    the points of its line's RDP-reduced footprint log (<= max_points)."""
+    smp_ = np.ascontiguousarray(samples, dtype=SAMPLE_DTYPE)
+    keep = np.zeros(max(smp_.shape[0], 1), np.uint8)
+    _check("timeline_points", lib().timeline_points(smp_.ctypes.data if smp_.size else None, smp_.shape[0],
+                                                    int(num_lines), int(max_points),
+                                                    keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return keep[: smp_.shape[0]].copy()
 
 
 def _check(fn, code):

@@ -6,6 +6,7 @@
 // positive values.  One pass over the lines decides each line from its
 // neighbours' tests (a window of three), so the output comes out in order.
 #include <cstdint>
+#include <vector>
 
 #include "scalene_sampler.h"
 
@@ -176,5 +177,107 @@ extern "C" SMP_API int leak_report(const smp_sample_t* samples, uint64_t n_sampl
         reported[l] = (ok && gate[l]) ? 1 : 0;
     }
     *elapsed_us = (int64_t)el;
+    return SMP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Per-line memory timelines (section 5): each line's footprint log (its
+// samples in rank order, as points (event index, footprint)) reduced by
+// Ramer-Douglas-Peucker to at most max_points points.  A point is kept when
+// its distance from the chord of its run exceeds eps, decided exactly as
+// cross^2 > eps^2 (dx^2 + dy^2) on 256-bit integers; the farthest point of a
+// run (the first on ties) splits it.  eps is the smallest of
+// {0, 1, 2, 4, ..., 2^62} that leaves at most max_points points: the kept set
+// only shrinks as eps grows, so a binary search over the candidates finds it.
+
+namespace {
+
+struct Run {
+    uint32_t i, j;
+};
+
+// RDP over pts[0..n) at eps; marks kept points in keep (if given) and
+// returns their number.  stack: scratch for the runs.
+uint64_t rdp(const uint32_t* xs, const int64_t* ys, uint32_t n, uint64_t eps, uint8_t* keep, std::vector<Run>& stack) {
+    if (n <= 2) {
+        if (keep)
+            for (uint32_t k = 0; k < n; ++k) keep[k] = 1;
+        return n;
+    }
+    const unsigned __int128 e2 = (unsigned __int128)eps * eps;
+    uint64_t kept = 2;
+    if (keep) keep[0] = keep[n - 1] = 1;
+    stack.clear();
+    stack.push_back(Run{0, n - 1});
+    while (!stack.empty()) {
+        const Run r = stack.back();
+        stack.pop_back();
+        if (r.j - r.i < 2) continue;
+        const int64_t dx = (int64_t)xs[r.j] - (int64_t)xs[r.i];
+        const __int128 dy = (__int128)ys[r.j] - ys[r.i];
+        unsigned __int128 best = 0;
+        uint32_t bk = 0;
+        bool any = false;
+        for (uint32_t k = r.i + 1; k < r.j; ++k) {
+            const __int128 c = (__int128)dx * ((__int128)ys[k] - ys[r.i]) - dy * ((int64_t)xs[k] - (int64_t)xs[r.i]);
+            const unsigned __int128 a = mag(c);
+            if (!any || a > best) {
+                best = a;
+                bk = k;
+                any = true;
+            }
+        }
+        const unsigned __int128 len2 = (unsigned __int128)((__int128)dx * dx) + mag(dy) * mag(dy);
+        if (cmp(mul128(best, best), mul128(e2, len2)) > 0) {
+            ++kept;
+            if (keep) keep[bk] = 1;
+            stack.push_back(Run{r.i, bk});
+            stack.push_back(Run{bk, r.j});
+        }
+    }
+    return kept;
+}
+
+}  // namespace
+
+extern "C" SMP_API int timeline_points(const smp_sample_t* samples, uint64_t n_samples, uint32_t num_lines,
+                                       uint32_t max_points, uint8_t* keep) {
+    if (max_points < 2 || (n_samples && (!samples || !keep)) || n_samples >= (1ull << 32)) return SMP_EINVAL;
+    for (uint64_t r = 0; r < n_samples; ++r) keep[r] = 0;
+    if (!n_samples || !num_lines) return SMP_OK;
+    // group the samples by line, rank order kept (counting sort)
+    std::vector<uint32_t> start((size_t)num_lines + 1, 0), order(n_samples);
+    for (uint64_t r = 0; r < n_samples; ++r)
+        if (samples[r].line < num_lines) ++start[samples[r].line + 1];
+    for (uint32_t l = 0; l < num_lines; ++l) start[l + 1] += start[l];
+    std::vector<uint32_t> fill(start.begin(), start.end() - 1);
+    for (uint64_t r = 0; r < n_samples; ++r)
+        if (samples[r].line < num_lines) order[fill[samples[r].line]++] = (uint32_t)r;
+    std::vector<uint32_t> xs;
+    std::vector<int64_t> ys;
+    std::vector<uint8_t> mark;
+    std::vector<Run> stack;
+    for (uint32_t l = 0; l < num_lines; ++l) {
+        const uint32_t b = start[l], n = start[l + 1] - b;
+        if (!n) continue;
+        xs.resize(n);
+        ys.resize(n);
+        for (uint32_t k = 0; k < n; ++k) {
+            xs[k] = samples[order[b + k]].event_idx;
+            ys[k] = samples[order[b + k]].F;
+        }
+        // candidates c(0) = 0, c(e + 1) = 2^e: the first with at most max_points
+        auto cand = [](int i) -> uint64_t { return i == 0 ? 0 : (1ull << (i - 1)); };
+        int lo = 0, hi = 63;  // rdp at c(63) = 2^62 keeps the two endpoints only
+        while (lo < hi) {
+            const int mid = (lo + hi) / 2;
+            if (rdp(xs.data(), ys.data(), n, cand(mid), nullptr, stack) <= max_points) hi = mid;
+            else lo = mid + 1;
+        }
+        mark.assign(n, 0);
+        rdp(xs.data(), ys.data(), n, cand(lo), mark.data(), stack);
+        for (uint32_t k = 0; k < n; ++k)
+            if (mark[k]) keep[order[b + k]] = 1;
+    }
     return SMP_OK;
 }

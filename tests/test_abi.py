@@ -137,3 +137,28 @@ def test_leak_report_matches_oracle():
     for r in (1, 7, 1 << 20, 1 << 50):
         for peak, want in ((100 * r, True), (100 * r + 1, False)):
             assert both(np.array([3, (1 << 32) - 1], np.uint32), np.array([peak - r, peak], np.int64)) == want
+
+
+def test_timeline_points_match_oracle():
+    """The library's per-line RDP (iterative, binary search over eps, 256-bit
+    distance test) against the oracle's on random multi-line sample sets,
+    from small values to event indices near 2^32 and footprints near 2^60,
+    including lines with fewer than max_points samples and out-of-range
+    lines."""
+    import oracle
+
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        K = int(rng.integers(0, 4000))
+        L = int(rng.integers(1, 9))
+        x = np.sort(rng.choice((1 << 32) - 1 if trial % 2 else 1 << 16, K, replace=False)).astype(np.uint32)
+        scale = [1e2, 1e9, 1e16][trial % 3]
+        y = np.clip(np.cumsum(rng.normal(0, scale, K)), -(1 << 60), 1 << 60).astype(np.int64)
+        s = np.zeros(K, smp.SAMPLE_DTYPE)
+        s["event_idx"] = x
+        s["F"] = y
+        s["line"] = rng.integers(0, L + 1, K)  # line L is out of range: no timeline
+        mp = [100, 2, 7][trial % 3]
+        got = smp.timeline_points(s, L, mp)
+        want = oracle.timeline_points(s, L, mp)
+        assert got.tolist() == want.tolist(), (trial, K, L)

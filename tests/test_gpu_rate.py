@@ -176,3 +176,23 @@ def test_leak_report_on_gpu_profiles():
             want = oracle.leak_report(g["samples"], g[gate_name], g["py_time_us"], g["nat_time_us"])
             assert got[0] == want[0] and got[2] == want[2]
             assert got[1].tolist() == want[1].tolist()
+
+
+def test_timelines_on_a_gpu_profile():
+    """Per-line RDP timelines of a GPU profile (config 1, seed 4): library and
+    oracle keep the same samples, at most 100 per line."""
+    ev, kw = tg.config1(seed=4)
+    p = smp.make_params(kw["threshold"], kw["num_lines"])
+    sampler = smp.Sampler(workspace=smp.sampler_fixed_bytes() + smp.workspace_bytes(len(ev), p) + (16 << 20))
+    try:
+        tid = sampler.submit_trace(to_dev(ev), p)
+        sampler.run(blocking=True)
+        g = sampler.fetch_profile(tid)
+    finally:
+        sampler.close()
+    s = g["samples"]
+    got = smp.timeline_points(s, kw["num_lines"])
+    want = oracle.timeline_points(s, kw["num_lines"])
+    assert got.tolist() == want.tolist()
+    per_line = np.bincount(s["line"][got == 1], minlength=kw["num_lines"])
+    assert per_line.max() <= 100 and got.sum() > 0
