@@ -179,7 +179,7 @@ def main():
     if "config5" in want:
         extras["config5"] = bench_config5(smp, tg, torch, np)
     if "batched" in want:
-        extras["batched"] = bench_batched(smp, tg, torch, np)
+        extras["batched"] = bench_batched(smp, tg, torch, np, cpu=not args.no_cpu_baseline)
     if "served" in want:
         extras["served"] = bench_served(smp, tg, torch, np, args.served_requests)
 
@@ -307,9 +307,12 @@ def bench_config5(smp, tg, torch, np, steps=3):
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}}
 
 
-def bench_batched(smp, tg, torch, np, steps=3):
+def bench_batched(smp, tg, torch, np, steps=3, cpu=True):
     """Config 3: 1024 traces (log-uniform 1e3-1e6 events, T from {256 KiB,
-    1 MiB, 10 MiB}) in one launch, against a loop of one launch per trace."""
+    1 MiB, 10 MiB}) in one launch, against a loop of one launch per trace;
+    and, beside it, the oracle over the same traces on all host cores (a
+    thread pool, one trace per task; the oracle releases the interpreter
+    lock while it runs)."""
     log("batched: generating config 3")
     plan = tg.config3_plan()
     traces = [tg.config3_trace(n, T, seed) for (n, T, seed) in plan]
@@ -349,7 +352,27 @@ def bench_batched(smp, tg, torch, np, steps=3):
     del devs
     torch.cuda.empty_cache()
     kms_avg = sum(kms) / len(kms)
+    cpu_all = None
+    if cpu:
+        import concurrent.futures
+        import oracle
+        cores = min(16, os.cpu_count() or 1)  # the GPU machine's host share
+        log(f"batched: oracle on {cores} host threads")
+
+        def one(t):
+            ev, kw = t
+            return oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"])["status"]
+
+        t0 = time.perf_counter()
+        with concurrent.futures.ThreadPoolExecutor(max_workers=cores) as ex:
+            st = list(ex.map(one, sorted(traces, key=lambda t: -len(t[0]))))
+        tc = time.perf_counter() - t0
+        if any(v != 0 for v in st):
+            raise RuntimeError("oracle status")
+        cpu_all = {"value": round(total / tc, 1), "unit": "events/s", "cores": cores, "kind": "oracle",
+                   "sample": "all 1024 config-3 traces once, one trace per task, longest first"}
     return {"workload": "config3: 1024 traces, lengths 10^(3+3u), config-1 mix, 1000 lines, T in {256K,1M,10M}",
+            "cpu_baseline_all_cores": cpu_all,
             "events": total, "batched_events_per_s": round(total / tb, 1), "batched_ms": round(tb * 1e3, 3),
             "batched_kernel_ms": round(kms_avg, 3),
             "batched_pass_ms": {k: round(sum(r[k] for r in pass_runs[1:]) / max(len(pass_runs) - 1, 1), 4)
