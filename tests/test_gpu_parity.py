@@ -14,11 +14,11 @@ import pytest
 import oracle
 import paper_2212_07597_amd as smp
 import tracegen as tg
+from parity_util import compare
 
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-KEYS = ("final_F", "peak_F", "peak_sampled_F", "threshold_used", "K", "H")
 
 
 def say(msg):
@@ -35,26 +35,6 @@ def sampler():
     s.close()
     del s
     torch.cuda.empty_cache()
-
-
-def compare(g, o, label=""):
-    assert g["status"] == o["status"], (label, g["status"], o["status"])
-    if o["status"] != oracle.OK:
-        return
-    for k in KEYS:
-        assert g[k] == o[k], (label, k, g[k], o[k])
-    gs, os_ = g["samples"], o["samples"]
-    assert gs.shape == os_.shape, (label, gs.shape, os_.shape)
-    for f in ("event_idx", "line", "F", "py", "nat"):
-        if not np.array_equal(gs[f], os_[f]):
-            bad = np.flatnonzero(gs[f] != os_[f])[:5]
-            raise AssertionError(f"{label}: samples.{f} differ at {bad}: gpu {gs[bad]} oracle {os_[bad]}")
-    for f in ("event_idx", "line", "ptr", "freed"):
-        assert np.array_equal(g["tracked"][f], o["tracked"][f]), (label, "tracked", f)
-    for name in oracle.HIST_NAMES + ("lap_num", "lap_den", "lit_num", "lit_den", "lap_gate", "lit_gate"):
-        if not np.array_equal(g[name], o[name]):
-            bad = np.flatnonzero(g[name] != o[name])[:5]
-            raise AssertionError(f"{label}: {name} differs at lines {bad}: gpu {g[name][bad]} oracle {o[name][bad]}")
 
 
 def run_batch(sampler, cases):
@@ -312,6 +292,44 @@ def test_batch_submit_and_release(sampler):
     assert got == [(o["K"], smp.SMP_OK) for o in want]
     with pytest.raises(smp.SamplerError):
         sampler.release_traces(ids)  # already released
+
+
+def test_run_splits_over_4096_traces(sampler):
+    """One run() over 5,000 pending traces: more than one launch's
+    descriptor table holds (4,096), so the batch is split over two run
+    slots.  Every trace must still equal the oracle."""
+    say("run() over 5000 traces (split over two slots)")
+    rng = np.random.default_rng(4096)
+    cases = []
+    for i in range(5000):
+        n = int(rng.integers(0, 1500))
+        T = (64 * tg.KiB, 256 * tg.KiB, tg.MiB)[i % 3]
+        ev = tg.mix(10_000 + i, n, num_lines=32, zipf_s=1.1) if n else tg.make_events([])
+        cases.append((f"split t{i}", ev, dict(threshold=T, num_lines=32)))
+    check_batch(sampler, cases)
+
+
+def test_ten_runs_reuse_busy_slots(sampler):
+    """Ten non-blocking run() calls before any fetch: the sampler has eight
+    run slots, so the ninth and tenth launches wait for and reuse the
+    oldest busy slot.  Every trace of every launch must equal the oracle."""
+    say("ten non-blocking runs before any fetch (slot reuse)")
+    import torch
+    runs = []
+    for r in range(10):
+        batch = []
+        for k in range(3):
+            n = 200_000 + 150_000 * k + 7 * r
+            ev, kw = tg.config1(seed=700 + 10 * r + k, n=n)
+            dev = torch.from_numpy(ev.view(np.uint8)).to("cuda")
+            tid = sampler.submit_trace(dev, smp.make_params(kw["threshold"], kw["num_lines"]))
+            batch.append((tid, ev, kw))
+        sampler.run(blocking=False)
+        runs.append(batch)
+    for r, batch in enumerate(runs):
+        for tid, ev, kw in batch:
+            g = sampler.fetch_profile(tid)
+            compare(g, oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"]), f"run {r}")
 
 
 def test_budget_admission(sampler):
