@@ -301,6 +301,25 @@ SMP_API uint64_t rate_workspace_bytes(uint64_t n_events);
 SMP_API int rate_run(const smp_event_t *ev, uint64_t n, int64_t threshold, uint32_t num_lines, void *workspace,
                      uint64_t workspace_bytes, int64_t *line_counts, uint64_t *result, void *hip_stream);
 
+/* ---- rate-based sampling without allocation ----------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rate_run
+ * with its scratch in a device array inside the library instead of a
+ * workspace argument.  The library holds one such array of
+ * 256 + 8 * (SMP_RATE_NOALLOC_MAX_EVENTS / 512) bytes (8 MiB + 256 B) on
+ * each GPU it runs on, until the process ends; the call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine) and clears what
+ * must start at zero with a kernel.  Every call on one GPU shares that GPU's
+ * array and leaves its contents behind: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and must be
+ * serialised by the caller.  The array's device address is looked up on a
+ * device's first call, with that device current.
+ * Arguments, results and errors as rate_run, with n <= SMP_RATE_NOALLOC_MAX_EVENTS;
+ * a larger n returns SMP_ETOOBIG and launches nothing. */
+#define SMP_RATE_NOALLOC_MAX_EVENTS (1ull << 29)
+SMP_API int rate_run_noalloc(const smp_event_t *ev, uint64_t n, int64_t threshold, uint32_t num_lines,
+                             int64_t *line_counts, uint64_t *result, void *hip_stream);
+
 /* ---- report line filter (section 5) -----------------------------------
  * The lines a profile shows: those with at least 1 % of the execution time
  * or at least 1 % of the memory, each with the line before and the line

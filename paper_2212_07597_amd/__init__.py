@@ -31,7 +31,7 @@ TRACKED_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("ptr", "<u4"),
 EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", "fetch_profile",
             "trace_device_results", "submit_traces", "release_traces", "sampler_last_timing",
             "sampler_set_pass_events", "sampler_last_pass_timing", "sampler_last_counters", "sampler_fixed_bytes",
-            "sampler_destroy", "error_string", "rate_workspace_bytes", "rate_run", "report_lines",
+            "sampler_destroy", "error_string", "rate_workspace_bytes", "rate_run", "rate_run_noalloc", "report_lines",
             "leak_report", "timeline_points")
 
 PASS_NAMES = ("summarize", "resolve", "chain", "scan", "emit")
@@ -130,6 +130,8 @@ def lib():
         L.rate_workspace_bytes.restype = u64
         L.rate_run.argtypes = [vp, u64, ctypes.c_int64, ctypes.c_uint32, vp, u64, vp, vp, vp]
         L.rate_run.restype = i32
+        L.rate_run_noalloc.argtypes = [vp, u64, ctypes.c_int64, ctypes.c_uint32, vp, vp, vp]
+        L.rate_run_noalloc.restype = i32
         p64 = ctypes.POINTER(ctypes.c_int64)
         L.report_lines.argtypes = [p64, p64, p64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                    ctypes.POINTER(ctypes.c_uint32)]
@@ -198,6 +200,32 @@ def rate_run(events, threshold, num_lines, *, workspace=None, line_counts=None, 
     stream.synchronize()
     r = result.cpu().numpy()
     return int(r[1]), int(r[0]), line_counts.cpu().numpy()
+
+
+RATE_NOALLOC_MAX_EVENTS = 1 << 29
+
+
+def rate_run_noalloc(events, threshold, num_lines, line_counts, result, stream=None):
+    """rate_run with the library's own scratch (the C entry point allocates
+    nothing): ``line_counts`` (int64, num_lines) and ``result`` (int64, 2)
+    are caller-owned CUDA tensors, written when the stream reaches them.
+    Calls that overlap on one GPU race (they share its scratch)."""
+    import torch
+
+    if not (isinstance(events, torch.Tensor) and events.is_cuda and events.dtype == torch.uint8):
+        raise TypeError("events must be a CUDA uint8 tensor of 24-byte records")
+    if events.numel() % 24:
+        raise ValueError("events must hold whole 24-byte records")
+    for t, name, k in ((line_counts, "line_counts", int(num_lines)), (result, "result", 2)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int64 and t.numel() >= k
+                and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous CUDA int64 tensor of at least {k} values")
+    n = events.numel() // 24
+    if stream is None:
+        stream = torch.cuda.current_stream(events.device)
+    _check("rate_run_noalloc", lib().rate_run_noalloc(events.data_ptr() if n else None, n, int(threshold),
+                                                      int(num_lines), line_counts.data_ptr(), result.data_ptr(),
+                                                      stream.cuda_stream))
 
 
 def report_lines(py_time_us, nat_time_us, growth_bytes):

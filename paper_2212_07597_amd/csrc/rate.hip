@@ -13,6 +13,8 @@
 // quotient, added per line through an LDS cache.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "scalene_sampler.h"
 #include "sampler_device.h"
 
@@ -222,27 +224,21 @@ __global__ __launch_bounds__(BLOCK) void k_rate_count(const uint8_t* __restrict_
 
 int g_count_grid = 0;
 
-}  // namespace
-}  // namespace smp
-
-using namespace smp;
-
-extern "C" {
-
-SMP_API uint64_t rate_workspace_bytes(uint64_t n_events) {
-    return RATE_HDR + 8 * ((n_events + SEG - 1) / SEG);
+bool rate_args_ok(const smp_event_t* ev, uint64_t n, int64_t threshold, uint32_t num_lines, int64_t* line_counts,
+                  uint64_t* result) {
+    return threshold >= 1 && threshold < ((int64_t)1 << 60) && num_lines != 0 && n < 0xFFFFFFFFull && (!n || ev) &&
+           line_counts && result;
 }
 
-SMP_API int rate_run(const smp_event_t* ev, uint64_t n, int64_t threshold, uint32_t num_lines, void* workspace,
-                     uint64_t workspace_bytes, int64_t* line_counts, uint64_t* result, void* hip_stream) {
-    if (threshold < 1 || threshold >= ((int64_t)1 << 60) || num_lines == 0 || n >= 0xFFFFFFFFull ||
-        (n && !ev) || !workspace || !line_counts || !result || workspace_bytes < rate_workspace_bytes(n))
-        return SMP_EINVAL;
-    hipStream_t s = (hipStream_t)hip_stream;
-    uint64_t* flags = (uint64_t*)workspace;
-    uint64_t* vol = (uint64_t*)((uint8_t*)workspace + RATE_HDR);
+// The launch sequence of one call, with its scratch at ws (RATE_HDR bytes of
+// header, then 8 bytes per segment).
+int rate_launch(const smp_event_t* ev, uint64_t n, int64_t threshold, uint32_t num_lines, void* ws,
+                int64_t* line_counts, uint64_t* result, hipStream_t s) {
+    uint64_t* flags = (uint64_t*)ws;
+    uint64_t* vol = (uint64_t*)((uint8_t*)ws + RATE_HDR);
     const uint64_t nseg = (n + SEG - 1) / SEG;
     const uint32_t cl = num_lines > 2 ? num_lines : 2;
+    // a kernel, not a memset, clears the counts, the result and the flags
     k_rate_clear<<<dim3((cl + 255) / 256), dim3(256), 0, s>>>(line_counts, num_lines, result, flags);
     if (hipGetLastError() != hipSuccess) return SMP_EDEVICE;
     if (nseg == 0) {
@@ -266,6 +262,62 @@ SMP_API int rate_run(const smp_event_t* ev, uint64_t n, int64_t threshold, uint3
     k_rate_count<<<dim3(grid), dim3(BLOCK), 0, s>>>(e, n, nseg, P, num_lines, threshold, vol, flags, line_counts,
                                                     result);
     return hipGetLastError() == hipSuccess ? SMP_OK : SMP_EDEVICE;
+}
+
+}  // namespace
+}  // namespace smp
+
+// Scratch of the no-allocation entry point: one copy per GPU, held until the
+// process ends, shared by every call on that GPU.  Host code never uses this
+// name as an address (on the host it only names the symbol); the device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr uint64_t RATE_SCRATCH_BYTES = smp::RATE_HDR + 8 * (SMP_RATE_NOALLOC_MAX_EVENTS / smp::SEG);
+static __device__ __align__(256) uint8_t scratch[RATE_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch (looked up on the device's first
+// call, with that device current).
+int scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return SMP_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SMP_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SMP_OK;
+}
+}  // namespace
+
+using namespace smp;
+
+extern "C" {
+
+SMP_API uint64_t rate_workspace_bytes(uint64_t n_events) {
+    return RATE_HDR + 8 * ((n_events + SEG - 1) / SEG);
+}
+
+SMP_API int rate_run(const smp_event_t* ev, uint64_t n, int64_t threshold, uint32_t num_lines, void* workspace,
+                     uint64_t workspace_bytes, int64_t* line_counts, uint64_t* result, void* hip_stream) {
+    if (!rate_args_ok(ev, n, threshold, num_lines, line_counts, result) || !workspace ||
+        workspace_bytes < rate_workspace_bytes(n))
+        return SMP_EINVAL;
+    return rate_launch(ev, n, threshold, num_lines, workspace, line_counts, result, (hipStream_t)hip_stream);
+}
+
+SMP_API int rate_run_noalloc(const smp_event_t* ev, uint64_t n, int64_t threshold, uint32_t num_lines,
+                             int64_t* line_counts, uint64_t* result, void* hip_stream) {
+    if (!rate_args_ok(ev, n, threshold, num_lines, line_counts, result)) return SMP_EINVAL;
+    if (n > SMP_RATE_NOALLOC_MAX_EVENTS) return SMP_ETOOBIG;
+    void* ws = nullptr;
+    if (int rc = scratch_address(&ws)) return rc;
+    return rate_launch(ev, n, threshold, num_lines, ws, line_counts, result, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

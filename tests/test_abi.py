@@ -162,3 +162,22 @@ def test_timeline_points_match_oracle():
         got = smp.timeline_points(s, L, mp)
         want = oracle.timeline_points(s, L, mp)
         assert got.tolist() == want.tolist(), (trial, K, L)
+
+
+def test_rate_noalloc_refuses_sizes_over_its_scratch_on_the_host():
+    # the size and argument checks come before any device call, so this runs
+    # without a GPU: one dummy record pointer with a count above the maximum
+    dummy = (ctypes.c_uint8 * 24)()
+    out = (ctypes.c_int64 * 4)()
+    res = (ctypes.c_uint64 * 2)()
+    L = smp.lib()
+    rc = L.rate_run_noalloc(ctypes.addressof(dummy), smp.RATE_NOALLOC_MAX_EVENTS + 1, 10, 4,
+                            ctypes.addressof(out), ctypes.addressof(res), None)
+    assert rc == smp.SMP_ETOOBIG
+    # invalid arguments: threshold 0, no line counts
+    assert L.rate_run_noalloc(ctypes.addressof(dummy), 1, 0, 4, ctypes.addressof(out), ctypes.addressof(res),
+                              None) == smp.SMP_EINVAL
+    assert L.rate_run_noalloc(ctypes.addressof(dummy), 1, 10, 4, None, ctypes.addressof(res), None) == smp.SMP_EINVAL
+    # the header's maximum and the binding's agree
+    src = open(HEADER).read()
+    assert "#define SMP_RATE_NOALLOC_MAX_EVENTS (1ull << 29)" in src and smp.RATE_NOALLOC_MAX_EVENTS == 1 << 29
