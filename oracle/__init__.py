@@ -81,9 +81,6 @@ def lib():
         L.oracle_rate.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32,
                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]
         L.oracle_rate.restype = ctypes.c_int
-        p64c = ctypes.POINTER(ctypes.c_int64)
-        L.oracle_report_lines.argtypes = [p64c, p64c, p64c, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
-        L.oracle_report_lines.restype = ctypes.c_uint32
         L.oracle_leak_scores.restype = None
         _lib = L
     return _lib
@@ -164,16 +161,36 @@ def rate(events, threshold, num_lines, options=0):
     return int(st), int(K.value), counts
 
 
-def report_lines(py_time, nat_time, growth_bytes):
-    """Report line filter (section 5): the ids of the lines with at least 1 %
-    of the time or of the growth bytes, and their neighbours, ascending."""
-    a = [np.ascontiguousarray(x, dtype=np.int64) for x in (py_time, nat_time, growth_bytes)]
-    L = a[0].shape[0]
-    out = np.zeros(max(L, 1), np.uint32)
-    p = ctypes.POINTER(ctypes.c_int64)
-    k = lib().oracle_report_lines(a[0].ctypes.data_as(p), a[1].ctypes.data_as(p), a[2].ctypes.data_as(p), L,
-                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
-    return out[:k].copy()
+def report_lines(py_time, nat_time, growth_bytes, max_qualifying=100):
+    """Report line filter (section 5): the lines with at least 1 % of the
+    execution time or at least 1 % of the memory, each with the line before
+    and the line after it, never more than 300 lines in all.  A line's time
+    is py_time + nat_time, its memory its growth bytes; only positive values
+    count, in the totals and as shares.  The paper's bound holds for one
+    criterion (at most 100 lines can hold 1 % of one total); with both, the
+    100 qualifying lines with the largest share are kept, a line's share
+    being the larger of its time share and its memory share (ties: the lower
+    line id).  Exact rational arithmetic; returns the ids ascending."""
+    from fractions import Fraction
+
+    L = len(py_time)
+    t = [int(py_time[l]) + int(nat_time[l]) for l in range(L)]
+    m = [int(growth_bytes[l]) for l in range(L)]
+    tot_t = sum(x for x in t if x > 0)
+    tot_m = sum(x for x in m if x > 0)
+    share = {}
+    for l in range(L):
+        by_time = t[l] > 0 and 100 * t[l] >= tot_t
+        by_mem = m[l] > 0 and 100 * m[l] >= tot_m
+        if by_time or by_mem:
+            st = Fraction(t[l], tot_t) if t[l] > 0 else Fraction(0)
+            sm = Fraction(m[l], tot_m) if m[l] > 0 else Fraction(0)
+            share[l] = max(st, sm)
+    kept = sorted(share, key=lambda l: (-share[l], l))[:max_qualifying]
+    out = set()
+    for l in kept:
+        out.update(c for c in (l - 1, l, l + 1) if 0 <= c < L)
+    return np.array(sorted(out), dtype=np.uint32)
 
 
 def _wrap64(v):

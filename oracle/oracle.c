@@ -357,41 +357,3 @@ OR_EXPORT int oracle_rate(const void *events, uint64_t n, int64_t T, uint32_t L,
     }
     return overflow ? OR_EOVERFLOW : OR_OK;
 }
-
-/*
- * Report line filter (section 5): a profile shows only the lines that take
- * at least 1 % of the execution time or at least 1 % of the memory, together
- * with the line before and the line after each.  Readings: a line's time is
- * its Python plus native time (timer samples), its memory the bytes of its
- * growth samples; "at least 1 %" is 100 x >= total over the lines' positive
- * values (a line with x <= 0 never qualifies, a zero total selects nothing);
- * neighbours are the line ids one below and one above, inside [0, L).
- * Writes the selected ids in increasing order to out (L entries) and returns
- * their number.
- */
-OR_EXPORT uint32_t oracle_report_lines(const int64_t *py_time, const int64_t *nat_time, const int64_t *growth,
-                                       uint32_t L, uint32_t *out) {
-    __int128 tt = 0, tm = 0;
-    for (uint32_t l = 0; l < L; ++l) {
-        const __int128 t = (__int128)py_time[l] + nat_time[l];
-        if (t > 0) tt += t;
-        if (growth[l] > 0) tm += growth[l];
-    }
-    uint8_t *keep = (uint8_t *)calloc(L ? L : 1, 1);
-    if (!keep) return 0;
-    for (uint32_t l = 0; l < L; ++l) {
-        const __int128 t = (__int128)py_time[l] + nat_time[l];
-        const int by_time = t > 0 && 100 * t >= tt;
-        const int by_mem = growth[l] > 0 && 100 * (__int128)growth[l] >= tm;
-        if (by_time || by_mem) {
-            keep[l] = 1;
-            if (l > 0) keep[l - 1] = 1;
-            if (l + 1 < L) keep[l + 1] = 1;
-        }
-    }
-    uint32_t k = 0;
-    for (uint32_t l = 0; l < L; ++l)
-        if (keep[l]) out[k++] = l;
-    free(keep);
-    return k;
-}

@@ -1,57 +1,11 @@
-// report.cpp - the report line filter (section 5), host side: a profile
-// shows only the lines that take at least 1 % of the execution time or at
-// least 1 % of the memory, together with the line before and the line after
-// each.  A line's time is its Python plus native time, its memory the bytes
-// of its growth samples; "at least 1 %" is 100 x >= the total of the lines'
-// positive values.  One pass over the lines decides each line from its
-// neighbours' tests (a window of three), so the output comes out in order.
+// report.cpp - host-side report layer over fetched profiles: the report
+// line filter (section 5), the leak report filter (section 3.4) and the
+// per-line memory timelines (section 5).
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
 #include "scalene_sampler.h"
-
-namespace {
-
-struct Shares {
-    unsigned __int128 time = 0, mem = 0;
-};
-
-inline __int128 line_time(const int64_t* py, const int64_t* nat, uint32_t l) {
-    return (__int128)py[l] + (__int128)nat[l];
-}
-
-}  // namespace
-
-extern "C" SMP_API int report_lines(const int64_t* py_time_us, const int64_t* nat_time_us, const int64_t* growth_bytes,
-                                    uint32_t num_lines, uint32_t* out_lines, uint32_t* n_out) {
-    if (!n_out) return SMP_EINVAL;
-    *n_out = 0;
-    if (num_lines == 0) return SMP_OK;
-    if (!py_time_us || !nat_time_us || !growth_bytes || !out_lines) return SMP_EINVAL;
-    Shares tot;
-    for (uint32_t l = 0; l < num_lines; ++l) {
-        const __int128 t = line_time(py_time_us, nat_time_us, l);
-        if (t > 0) tot.time += (unsigned __int128)t;
-        if (growth_bytes[l] > 0) tot.mem += (unsigned __int128)growth_bytes[l];
-    }
-    auto qualifies = [&](uint32_t l) -> bool {
-        const __int128 t = line_time(py_time_us, nat_time_us, l);
-        if (t > 0 && (unsigned __int128)t * 100u >= tot.time) return true;
-        const int64_t m = growth_bytes[l];
-        return m > 0 && (unsigned __int128)m * 100u >= tot.mem;
-    };
-    // q_prev, q_cur, q_next: the tests of lines l-1, l, l+1
-    bool q_prev = false, q_cur = qualifies(0);
-    uint32_t k = 0;
-    for (uint32_t l = 0; l < num_lines; ++l) {
-        const bool q_next = l + 1 < num_lines && qualifies(l + 1);
-        if (q_prev || q_cur || q_next) out_lines[k++] = l;
-        q_prev = q_cur;
-        q_cur = q_next;
-    }
-    *n_out = k;
-    return SMP_OK;
-}
 
 // ---------------------------------------------------------------------------
 // Leak report filter (section 3.4): leaks are reported only when overall
@@ -121,6 +75,81 @@ U256 mul128(unsigned __int128 a, unsigned __int128 b) {
 unsigned __int128 mag(__int128 v) { return v < 0 ? (unsigned __int128)(-(v + 1)) + 1 : (unsigned __int128)v; }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Report line filter (section 5): a profile shows only the lines that take at
+// least 1 % of the execution time or at least 1 % of the memory, each with
+// the line before and the line after it, and never more than 300 lines.  A
+// line's time is its Python plus native time, its memory the bytes of its
+// growth samples; "at least 1 %" is 100 x >= the total of the lines'
+// positive values.  Each criterion alone admits at most 100 lines, the two
+// together up to 200, so when more than 100 qualify the 100 with the largest
+// share stay (a line's share: the larger of its time and memory shares,
+// compared exactly; equal shares: the lower id), which keeps the bound.
+
+namespace {
+
+constexpr size_t MAX_QUALIFYING = 100;
+
+// a fraction num/den (den > 0) of one criterion's total
+struct Share {
+    unsigned __int128 num, den;
+};
+
+bool share_less(const Share& a, const Share& b) { return cmp(mul128(a.num, b.den), mul128(b.num, a.den)) < 0; }
+
+}  // namespace
+
+extern "C" SMP_API int report_lines(const int64_t* py_time_us, const int64_t* nat_time_us, const int64_t* growth_bytes,
+                                    uint32_t num_lines, uint32_t* out_lines, uint32_t* n_out) {
+    if (!n_out) return SMP_EINVAL;
+    *n_out = 0;
+    if (num_lines == 0) return SMP_OK;
+    if (!py_time_us || !nat_time_us || !growth_bytes || !out_lines) return SMP_EINVAL;
+    auto line_time = [&](uint32_t l) { return (__int128)py_time_us[l] + (__int128)nat_time_us[l]; };
+    unsigned __int128 tot_time = 0, tot_mem = 0;
+    for (uint32_t l = 0; l < num_lines; ++l) {
+        const __int128 t = line_time(l);
+        if (t > 0) tot_time += (unsigned __int128)t;
+        if (growth_bytes[l] > 0) tot_mem += (unsigned __int128)growth_bytes[l];
+    }
+    std::vector<uint32_t> q;
+    for (uint32_t l = 0; l < num_lines; ++l) {
+        const __int128 t = line_time(l);
+        const int64_t m = growth_bytes[l];
+        if ((t > 0 && (unsigned __int128)t * 100u >= tot_time) || (m > 0 && (unsigned __int128)m * 100u >= tot_mem))
+            q.push_back(l);
+    }
+    if (q.size() > MAX_QUALIFYING) {
+        auto share = [&](uint32_t l) {
+            const __int128 t = line_time(l);
+            const int64_t m = growth_bytes[l];
+            const Share ts{t > 0 ? (unsigned __int128)t : 0, tot_time ? tot_time : 1};
+            const Share ms{m > 0 ? (unsigned __int128)m : 0, tot_mem ? tot_mem : 1};
+            return share_less(ts, ms) ? ms : ts;
+        };
+        std::vector<std::pair<Share, uint32_t>> ranked;
+        ranked.reserve(q.size());
+        for (uint32_t l : q) ranked.emplace_back(share(l), l);
+        std::sort(ranked.begin(), ranked.end(), [](const auto& a, const auto& b) {
+            if (share_less(b.first, a.first)) return true;   // larger share first
+            if (share_less(a.first, b.first)) return false;
+            return a.second < b.second;                        // then the lower id
+        });
+        q.clear();
+        for (size_t i = 0; i < MAX_QUALIFYING; ++i) q.push_back(ranked[i].second);
+        std::sort(q.begin(), q.end());
+    }
+    // the kept lines and their neighbours, ascending and once each
+    uint32_t k = 0;
+    for (uint32_t l : q) {
+        const uint32_t lo = l > 0 ? l - 1 : 0, hi = l + 1 < num_lines ? l + 1 : l;
+        for (uint32_t c = lo; c <= hi; ++c)
+            if (k == 0 || c > out_lines[k - 1]) out_lines[k++] = c;
+    }
+    *n_out = k;
+    return SMP_OK;
+}
 
 extern "C" SMP_API int leak_report(const smp_sample_t* samples, uint64_t n_samples, const uint8_t* gate,
                                    const int64_t* py_time_us, const int64_t* nat_time_us, uint32_t num_lines,

@@ -80,7 +80,7 @@ def test_report_lines_matches_oracle():
 
     rng = np.random.default_rng(7)
     sizes = [0, 1, 2, 3, 99, 100, 101, 300, 5000, 20000]
-    for i, L in enumerate(sizes * 3):
+    for i, L in enumerate(sizes * 4):
         kind = i // len(sizes)
         if kind == 0:    # skewed
             py = (rng.pareto(1.1, L) * 50).astype(np.int64)
@@ -90,10 +90,20 @@ def test_report_lines_matches_oracle():
             py = np.where(rng.random(L) < 0.3, 1, 0).astype(np.int64)
             nat = np.zeros(L, np.int64)
             gb = np.where(rng.random(L) < 0.01, 1 << 40, 0).astype(np.int64)
-        else:            # signed values (per-line sums wrap modulo 2^64)
+        elif kind == 2:  # signed values (per-line sums wrap modulo 2^64)
             py = rng.integers(-1000, 1000, L).astype(np.int64)
             nat = rng.integers(-10, 10, L).astype(np.int64)
             gb = rng.integers(-(1 << 62), 1 << 62, L).astype(np.int64)
+        else:            # over 100 lines qualify: 100 at exactly 1 % of the time, and 40 at
+                         # 2 % and 20 at 1 % of the memory (ties of equal shares across criteria)
+            py = np.zeros(L, np.int64)
+            nat = np.zeros(L, np.int64)
+            gb = np.zeros(L, np.int64)
+            if L >= 100:
+                py[rng.choice(L, 100, replace=False)] = 7
+                ids = rng.choice(L, min(L, 60), replace=False)
+                gb[ids[:40]] = 2 << 30
+                gb[ids[40:]] = 1 << 30
         got = smp.report_lines(py, nat, gb)
         want = oracle.report_lines(py, nat, gb)
         assert got.tolist() == want.tolist(), (L, kind)
