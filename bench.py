@@ -8,13 +8,18 @@ events) + run + release on the sampler's stream.  Inputs are resident in HBM
 when the timed region starts.
 
 Prints one JSON line with events/s, the roofline figures of the dominant
-kernel (the slowest of the three passes over the records, summarize / chain /
-emit, each of which reads every 24-byte record once: algorithmic bytes =
-24 B x events over that kernel's own HIP-event duration in the timed steps)
-and the CPU oracle timed on the host as a baseline.  The per-pass breakdown
+kernel (the slowest of the five sampling passes; its algorithmic bytes are
+the 24-byte record of every event, over that kernel's own HIP-event duration
+in the timed steps), the whole launch against the same bytes, and the CPU
+oracle timed on one pinned host core as a baseline.  The per-pass breakdown
 (pass_ms, kernel_ms) comes from untimed steps that record events around
 every pass; the timed steps record only the two around the dominant pass,
-because each event between two kernels idles the GPU for a few microseconds.
+because each event between two kernels idles the GPU for a few
+microseconds.  An end-to-end figure (pinned host events -> HBM, the launch,
+and the full profile copied back) is reported beside it, never as `value`.
+
+``--only config5|batched|served`` runs one extra measurement alone and
+prints its JSON (for profiling one workload at a time).
 """
 from __future__ import annotations
 
@@ -22,6 +27,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -31,17 +37,19 @@ sys.path.insert(0, ROOT)
 METRIC = "trace events/s + HBM GB/s (batched/served vs plain); p50/p99 trace latency"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_EVENT = 24
+# the GPU machine gives one GPU's process a share of 16 host CPUs
+HOST_CPU_SHARE = 16
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload="config2"):
     """HBM bytes per launch of `kernel` on this workload, from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated against a
     plain copy), or None if that summary was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", "config2_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.md")
     try:
         text = open(path).read()
     except OSError:
@@ -51,13 +59,90 @@ def measured_traffic(kernel):
         key, sep, val = line.partition(": ")
         if sep and key in ("kernel", "traffic_bytes_per_launch", "kernel_sources_sha256"):
             kv[key] = val.strip()
+    if kv.get("kernel") != kernel or kv.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
+def kernel_sources_sha256():
     h = hashlib.sha256()
     for f in ("sampler_kernels.hip", "sampler_device.h"):
         with open(os.path.join(ROOT, "paper_2212_07597_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if kv.get("kernel") != kernel or kv.get("kernel_sources_sha256") != h.hexdigest():
-        return None
-    return int(kv["traffic_bytes_per_launch"])
+    return h.hexdigest()
+
+
+def host_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram_gib = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                ram_gib = round(int(line.split()[1]) / (1 << 20), 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_allowed": len(os.sched_getaffinity(0)),
+            "ram_gib": ram_gib}
+
+
+def pinned_median_rate(fn, n_events, min_runs=5, min_seconds=10.0):
+    """Run fn() (one oracle pass over n_events events) with this thread
+    pinned to one CPU, at least min_runs times and min_seconds long; return
+    (median events/s over the runs, runs, the CPU)."""
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[0]
+    os.sched_setaffinity(0, {core})
+    try:
+        rates = []
+        t_all = time.perf_counter()
+        while len(rates) < min_runs or time.perf_counter() - t_all < min_seconds:
+            t0 = time.perf_counter()
+            fn()
+            rates.append(n_events / (time.perf_counter() - t0))
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    return statistics.median(rates), len(rates), core
+
+
+def roofline(pass_ms, n_events, kernel_ms, workload, dom=None):
+    """Dominant kernel (the slowest sampling pass unless named) and the whole
+    launch, both against the algorithmic 24 bytes per event; traffic from the
+    workload's committed counter summary."""
+    dom = dom or max(pass_ms, key=lambda k: pass_ms[k])
+    traffic = measured_traffic("k_" + dom, workload)
+    algo = BYTES_PER_EVENT * n_events
+    ach = algo / (pass_ms[dom] * 1e-3) / 1e9
+    whole = algo / (kernel_ms * 1e-3) / 1e9
+    return dom, {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                 "traffic_unit": "HBM bytes per launch", "algorithmic_bytes": algo,
+                 "whole_launch": {"kernel_ms": round(kernel_ms, 4), "achieved": round(whole, 1),
+                                  "frac": round(whole / HBM_PEAK_GBS, 4)}}
+
+
+def tuner(args):
+    """f(sampler, workload, n_traces, total_events) -> the launch parameters
+    used (autotuned unless --no-tune) for the report."""
+    def run(sampler, workload, n_traces, total_events):
+        if args.no_tune:
+            sampler.set_tuning()
+            return {"tuning": sampler.get_tuning(), "autotuned": False}
+        from paper_2212_07597_amd import autotune
+        t0 = time.perf_counter()
+        r = autotune.tune(sampler, workload, autotune.size_class(n_traces, total_events),
+                          cache_path=args.tuning_cache, log=log)
+        return {"autotuned": True, "key": r["key"], "chosen": r["tuning"], "resolved": sampler.get_tuning(),
+                "kernel_ms_tuned": r["ms"], "from_cache": r["from_cache"], "candidates_ms": r["tried"],
+                "search_s": round(time.perf_counter() - t0, 2)}
+    return run
 
 
 def main():
@@ -70,9 +155,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extras", action="store_true", help="skip every extra measurement (same as --extras '')")
-    ap.add_argument("--extras", default="rate,config5,batched,served",
-                    help="comma-separated extra measurements: rate, config5, batched, served")
+    ap.add_argument("--extras", default="e2e,rate,config5,batched,served",
+                    help="comma-separated extra measurements: e2e, rate, config5, batched, served")
+    ap.add_argument("--only", choices=("config5", "batched", "served"),
+                    help="run this one extra measurement alone and print its JSON")
+    ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the autotuner's")
+    ap.add_argument("--tuning-cache", default=None, help="autotuner cache file (default: the user's cache directory)")
     ap.add_argument("--served-requests", type=int, default=1000)
+    ap.add_argument("--served-rates", default="200,1000,5000", help="arrival rates (requests/s) of the served run")
+    ap.add_argument("--served-no-plain", action="store_true", help="skip the one-launch-per-request comparison")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -88,6 +179,17 @@ def main():
     import paper_2212_07597_amd as smp
     import tracegen as tg
 
+    cpu = not args.no_cpu_baseline
+    if args.only:
+        if args.only == "config5":
+            out = bench_config5(smp, tg, torch, np, cpu=cpu, tune=tuner(args))
+        elif args.only == "batched":
+            out = bench_batched(smp, tg, torch, np, cpu=cpu, tune=tuner(args))
+        else:
+            out = bench_served(smp, tg, torch, np, args.served_requests, served_rates(args), not args.served_no_plain)
+        print(json.dumps(out), flush=True)
+        return
+
     log(f"generating config 2 ({args.events} events)")
     t0 = time.time()
     ev, kw = tg.config2(seed=args.seed, n=args.events)
@@ -95,9 +197,10 @@ def main():
     n = ev.shape[0]
     dev = torch.from_numpy(ev.view(np.uint8)).to("cuda")
     params = smp.make_params(kw["threshold"], kw["num_lines"])
-    need = smp.workspace_bytes(n, params, ev_on_device=True)
+    want = set() if args.no_extras else {x for x in args.extras.split(",") if x}
+    # room for a device copy of the events too (the end-to-end steps)
+    need = smp.workspace_bytes(n, params, ev_on_device="e2e" not in want)
     s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + need + (1 << 20))
-    stream = s.stream
 
     def step():
         tid = s.submit_trace(dev, params)
@@ -112,14 +215,16 @@ def main():
             raise RuntimeError(f"trace status {status}")
         last["K"] = K
 
+    tuned = tuner(args)(s, lambda: release(step()), 1, n)
+
     log("warmup")
     for _ in range(args.warmup):
         release(step())
     torch.cuda.synchronize()
 
     # Per-pass breakdown (untimed): events around every pass.  It names the
-    # dominant record pass; the timed loop then records only the two events
-    # around that pass, since each event between kernels idles the GPU.
+    # dominant pass; the timed loop then records only the two events around
+    # that pass, since each event between kernels idles the GPU.
     pass_ms, main_list, launch_list = [], [], []
     for _ in range(max(args.warmup, 3)):
         tid = step()
@@ -129,8 +234,7 @@ def main():
         release(tid)
     passes = {k: sum(p[k] for p in pass_ms) / len(pass_ms) for k in smp.PASS_NAMES}
     main_ms = sum(main_list) / len(main_list)
-    record_passes = ("summarize", "chain", "emit")
-    dominant = max(record_passes, key=lambda k: passes[k])
+    dominant = max(passes, key=lambda k: passes[k])
     di = smp.PASS_NAMES.index(dominant)
     s.set_pass_events((1 << di) | (1 << (di + 1)))
 
@@ -144,44 +248,65 @@ def main():
         release(tid)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    # The same steps with only the start event: the launch sequence replays
+    # as a HIP graph (reported beside the headline, whose loop records the
+    # events around the dominant pass and so launches plainly).
+    s.set_pass_events(0x40)
+    for _ in range(3):
+        release(step())
+    torch.cuda.synchronize()
+    graph_launch = []
+    t_g = time.perf_counter()
+    for _ in range(args.steps):
+        tid = step()
+        graph_launch.append(s.last_timing()[1])
+        release(tid)
+    torch.cuda.synchronize()
+    elapsed_g = time.perf_counter() - t_g
     s.set_pass_events(0x7F)
     K = last["K"]
+    s_stats = s.launch_stats()
 
     ms_per_step = elapsed * 1e3 / args.steps
     value = n * args.steps / elapsed
     launch_ms = sum(launch_list) / len(launch_list)
     dom_timed = sum(dom_ms) / len(dom_ms)
-    achieved = BYTES_PER_EVENT * n / (dom_timed * 1e-3) / 1e9
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        log("cpu baseline (oracle)")
-        reps = 0
-        t0 = time.perf_counter()
-        while True:
-            r = oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"])
-            reps += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds:
-                break
-        dt = time.perf_counter() - t0
-        assert r["K"] == K, (r["K"], K)
-        cpu = {"value": round(n * reps / dt, 1), "unit": "events/s", "cores": 1, "kind": "oracle",
-               "sample": f"the full config-2 trace ({n} events), {reps} sequential pass(es), one host thread"}
+    timed_passes = dict(passes)
+    timed_passes[dominant] = dom_timed
+    _, roof = roofline(timed_passes, n, main_ms, "config2", dom=dominant)
 
     extras = {}
-    want = set() if args.no_extras else {x for x in args.extras.split(",") if x}
+    if "e2e" in want:
+        extras["end_to_end"] = bench_e2e(smp, torch, np, s, ev, params, K)
+
+    cpu_base = None
+    if cpu:
+        import oracle
+        log("cpu baseline (oracle, one pinned core)")
+        got = {}
+
+        def one():
+            got["r"] = oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"])
+
+        rate, runs, core = pinned_median_rate(one, n, min_runs=5, min_seconds=args.cpu_seconds)
+        assert got["r"]["K"] == K, (got["r"]["K"], K)
+        cpu_base = {"value": round(rate, 1), "unit": "events/s", "cores": 1, "kind": "oracle",
+                    "sample": f"the full config-2 trace ({n} events); median of {runs} sequential passes "
+                              f"(>= 5 and >= {args.cpu_seconds:g} s), one thread pinned to CPU {core}",
+                    "host": host_info()}
+
     if "rate" in want:
         extras["rate"] = bench_rate(smp, tg, torch, np, s, dev, n, kw, K)
     s.close()
     del dev
     torch.cuda.empty_cache()
     if "config5" in want:
-        extras["config5"] = bench_config5(smp, tg, torch, np)
+        extras["config5"] = bench_config5(smp, tg, torch, np, cpu=cpu, tune=tuner(args))
     if "batched" in want:
-        extras["batched"] = bench_batched(smp, tg, torch, np, cpu=not args.no_cpu_baseline)
+        extras["batched"] = bench_batched(smp, tg, torch, np, cpu=cpu, tune=tuner(args))
     if "served" in want:
-        extras["served"] = bench_served(smp, tg, torch, np, args.served_requests)
+        extras["served"] = bench_served(smp, tg, torch, np, args.served_requests, served_rates(args),
+                                        not args.served_no_plain)
 
     out = {
         "metric": METRIC,
@@ -201,15 +326,46 @@ def main():
                    "events": n, "samples": K, "seed": args.seed, "path": "plain one-trace-per-launch",
                    "kernel_ms": round(main_ms, 4), "launch_sequence_ms": round(launch_ms, 4),
                    "pass_ms": {k: round(v, 4) for k, v in passes.items()},
-                   "dominant_pass_ms_timed": round(dom_timed, 4)},
-        "roofline": {"bound": "hbm", "kernel": "k_" + dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("k_" + dominant), "traffic_unit": "HBM bytes per launch",
-                     "algorithmic_bytes": BYTES_PER_EVENT * n},
-        "cpu_baseline": cpu,
+                   "dominant_pass_ms_timed": round(dom_timed, 4), "tuning": tuned,
+                   "graph_replay": {"ms_per_step": round(elapsed_g * 1e3 / args.steps, 4),
+                                    "events_per_s": round(n * args.steps / elapsed_g, 1),
+                                    "launch_sequence_ms": round(statistics.median(graph_launch), 4)},
+                   "launches": s_stats},
+        "roofline": roof,
+        "cpu_baseline": cpu_base,
     }
     out.update(extras)
     print(json.dumps(out), flush=True)
+
+
+def bench_e2e(smp, torch, np, s, ev, params, K, reps=3):
+    """End to end on the headline trace: events in pinned host memory copied
+    to HBM (submit_trace), the launch, and the whole profile copied back
+    (fetch_profile: samples, tracked list, per-line arrays).  Phases are
+    timed one after another with a wait between them; median of reps."""
+    log("end to end (pinned host events, full profile fetch)")
+    host = torch.from_numpy(ev.view(np.uint8)).pin_memory()
+    rows = []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tid = s.submit_trace(host, params)
+        s.stream.synchronize()
+        t1 = time.perf_counter()
+        s.run(blocking=True)
+        t2 = time.perf_counter()
+        prof = s.fetch_profile(tid)
+        t3 = time.perf_counter()
+        if prof["status"] != smp.SMP_OK or prof["K"] != K:
+            raise RuntimeError("end-to-end profile differs from the device-resident one")
+        rows.append((t1 - t0, t2 - t1, t3 - t2, t3 - t0))
+    rows = rows[1:]  # the first pass warms the pinned pages and the copy engines
+    med = [statistics.median(r[i] for r in rows) * 1e3 for i in range(4)]
+    n = len(ev)
+    return {"workload": "config2, events in pinned host memory; H2D + run + fetch of the whole profile",
+            "h2d_ms": round(med[0], 3), "run_ms": round(med[1], 3), "fetch_ms": round(med[2], 3),
+            "ms": round(med[3], 3), "events_per_s": round(n / (med[3] * 1e-3), 1),
+            "h2d_gbs": round(BYTES_PER_EVENT * n / (med[0] * 1e-3) / 1e9, 1), "reps": reps}
 
 
 def bench_rate(smp, tg, torch, np, s, dev, n, kw, K_thr, steps=10):
@@ -265,15 +421,15 @@ def bench_rate(smp, tg, torch, np, s, dev, n, kw, K_thr, steps=10):
                                   "max_rate_over_threshold": round(ratios[-1], 2)}}
 
 
-def bench_config5(smp, tg, torch, np, steps=3):
+def bench_config5(smp, tg, torch, np, steps=3, cpu=True, tune=None):
     """Config 5: one trace of 5e8 events (config-1 mix with 10 % copy and 1 %
     timer events, 1e6 lines Zipf 1.05, T = Tc = 64 MiB, quantum 10,000 us),
-    resident in HBM; plain one-trace-per-launch steps as in the main line."""
+    resident in HBM; plain one-trace-per-launch steps as in the main line;
+    the oracle on one pinned core (median of 3 passes over the full trace)."""
     log("config 5: generating 5e8 events")
     ev, kw = tg.config5()
     n = len(ev)
     dev = torch.from_numpy(ev.view(np.uint8)).to("cuda")
-    del ev
     p = smp.make_params(kw["threshold"], kw["num_lines"], copy_threshold=kw["copy_threshold"],
                         quantum_us=kw["quantum_us"])
     s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + smp.workspace_bytes(n, p, ev_on_device=True) + (1 << 20))
@@ -287,6 +443,7 @@ def bench_config5(smp, tg, torch, np, steps=3):
             raise RuntimeError(f"config 5 trace status {status}")
         return out + (K,)
 
+    tuned = tune(s, step, 1, n) if tune else None
     step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -296,23 +453,40 @@ def bench_config5(smp, tg, torch, np, steps=3):
     del dev
     torch.cuda.empty_cache()
     passes = {k: sum(r[0][k] for r in runs) / len(runs) for k in smp.PASS_NAMES}
-    dominant = max(("summarize", "chain", "emit"), key=lambda k: passes[k])
-    achieved = BYTES_PER_EVENT * n / (passes[dominant] * 1e-3) / 1e9
+    kernel_ms = sum(r[1] for r in runs) / len(runs)
+    _, roof = roofline(passes, n, kernel_ms, "config5")
+    K = runs[-1][2]
+    cpu_base = None
+    if cpu:
+        import oracle
+        log("config 5: oracle on one pinned core")
+        got = {}
+
+        def one():
+            got["r"] = oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"],
+                                  copy_threshold=kw["copy_threshold"], quantum_us=kw["quantum_us"])
+
+        rate, nrun, core = pinned_median_rate(one, n, min_runs=3, min_seconds=0.0)
+        if got["r"]["K"] != K:
+            raise RuntimeError("config 5: oracle and GPU sample counts differ")
+        cpu_base = {"value": round(rate, 1), "unit": "events/s", "cores": 1, "kind": "oracle",
+                    "sample": f"the full config-5 trace ({n} events); median of {nrun} passes, one thread pinned "
+                              f"to CPU {core}", "host": host_info()}
+    del ev
     return {"workload": "config5: one trace, 5e8 events, config-1 mix + 10% copy + 1% timer events, 1e6 lines "
                         "Zipf 1.05, T=Tc=64 MiB, quantum 10000 us",
-            "events": n, "samples": runs[-1][2], "ms_per_step": round(dt * 1e3, 3), "events_per_s": round(n / dt, 1),
-            "kernel_ms": round(sum(r[1] for r in runs) / len(runs), 4),
+            "events": n, "samples": K, "ms_per_step": round(dt * 1e3, 3), "events_per_s": round(n / dt, 1),
+            "kernel_ms": round(kernel_ms, 4),
             "pass_ms": {k: round(v, 4) for k, v in passes.items()},
-            "roofline": {"bound": "hbm", "kernel": "k_" + dominant, "achieved": round(achieved, 1),
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}}
+            "roofline": roof, "tuning": tuned, "cpu_baseline": cpu_base}
 
 
-def bench_batched(smp, tg, torch, np, steps=3, cpu=True):
+def bench_batched(smp, tg, torch, np, steps=3, cpu=True, tune=None):
     """Config 3: 1024 traces (log-uniform 1e3-1e6 events, T from {256 KiB,
     1 MiB, 10 MiB}) in one launch, against a loop of one launch per trace;
-    and, beside it, the oracle over the same traces on all host cores (a
-    thread pool, one trace per task; the oracle releases the interpreter
-    lock while it runs)."""
+    and, beside it, the oracle over the same traces on one pinned core and
+    on the host's CPU share (a thread pool, one trace per task; the oracle
+    releases the interpreter lock while it runs)."""
     log("batched: generating config 3")
     plan = tg.config3_plan()
     traces = [tg.config3_trace(n, T, seed) for (n, T, seed) in plan]
@@ -322,15 +496,26 @@ def bench_batched(smp, tg, torch, np, steps=3, cpu=True):
     need = sum(smp.workspace_bytes(len(ev), p) for (ev, _), p in zip(traces, params))
     s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + need + (64 << 20))
 
-    pass_runs = []
+    phases = []
 
     def batched():
+        t0 = time.perf_counter()
+        ids = s.submit_traces(devs, params)
+        t1 = time.perf_counter()
+        s.run(blocking=True)
+        t2 = time.perf_counter()
+        km, launch = s.last_timing()
+        s.release_traces(ids)
+        t3 = time.perf_counter()
+        phases.append((t1 - t0, t2 - t1, t3 - t2, launch))
+        return km
+
+    def one_batch():
         ids = s.submit_traces(devs, params)
         s.run(blocking=True)
-        km, _ = s.last_timing()
-        pass_runs.append(s.last_pass_timing())
         s.release_traces(ids)
-        return km
+
+    tuned = tune(s, one_batch, len(devs), total) if tune else None
 
     def plain():
         for d, p in zip(devs, params):
@@ -338,11 +523,24 @@ def bench_batched(smp, tg, torch, np, steps=3, cpu=True):
             s.run(blocking=True)
             s.release(tid)
 
+    # per-pass breakdown (untimed): events around every pass, plain launches
+    pass_runs, kms = [], []
+    for _ in range(3):
+        kms.append(batched())
+        pass_runs.append(s.last_pass_timing())
+    # timed: only the launch's start event, so its launch sequence replays
+    # as a HIP graph once captured
+    s.set_pass_events(0x40)
+    batched()
     batched()
     torch.cuda.synchronize()
+    phases.clear()
     t0 = time.perf_counter()
-    kms = [batched() for _ in range(steps)]
+    for _ in range(steps):
+        batched()
     tb = (time.perf_counter() - t0) / steps
+    s.set_pass_events(0x7F)
+    s_stats = s.launch_stats()
     plain()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -352,41 +550,68 @@ def bench_batched(smp, tg, torch, np, steps=3, cpu=True):
     del devs
     torch.cuda.empty_cache()
     kms_avg = sum(kms) / len(kms)
-    cpu_all = None
+    passes = {k: sum(r[k] for r in pass_runs) / len(pass_runs) for k in smp.PASS_NAMES}
+    _, roof = roofline(passes, total, kms_avg, "config3")
+    cpu_one = cpu_all = None
     if cpu:
         import concurrent.futures
         import oracle
-        cores = min(16, os.cpu_count() or 1)  # the GPU machine's host share
-        log(f"batched: oracle on {cores} host threads")
 
         def one(t):
             ev, kw = t
             return oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"])["status"]
 
-        t0 = time.perf_counter()
-        with concurrent.futures.ThreadPoolExecutor(max_workers=cores) as ex:
-            st = list(ex.map(one, sorted(traces, key=lambda t: -len(t[0]))))
-        tc = time.perf_counter() - t0
-        if any(v != 0 for v in st):
-            raise RuntimeError("oracle status")
-        cpu_all = {"value": round(total / tc, 1), "unit": "events/s", "cores": cores, "kind": "oracle",
-                   "sample": "all 1024 config-3 traces once, one trace per task, longest first"}
+        log("batched: oracle on one pinned core")
+
+        def all_traces():
+            for t in traces:
+                if one(t) != 0:
+                    raise RuntimeError("oracle status")
+
+        rate, nrun, core = pinned_median_rate(all_traces, total, min_runs=5, min_seconds=0.0)
+        cpu_one = {"value": round(rate, 1), "unit": "events/s", "cores": 1, "kind": "oracle",
+                   "sample": f"all 1024 config-3 traces in order; median of {nrun} passes, one thread pinned to "
+                             f"CPU {core}"}
+        workers = min(HOST_CPU_SHARE, len(os.sched_getaffinity(0)))
+        log(f"batched: oracle on {workers} host threads")
+        order = sorted(traces, key=lambda t: -len(t[0]))
+        rates = []
+        with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+            for _ in range(3):
+                t0 = time.perf_counter()
+                st = list(ex.map(one, order))
+                rates.append(total / (time.perf_counter() - t0))
+                if any(v != 0 for v in st):
+                    raise RuntimeError("oracle status")
+        cpu_all = {"value": round(statistics.median(rates), 1), "unit": "events/s", "cores": workers,
+                   "kind": "oracle",
+                   "sample": f"all 1024 config-3 traces, one trace per task, longest first, on a pool of {workers} "
+                             f"threads (the host CPU share of one GPU, capped at {HOST_CPU_SHARE}); median of 3",
+                   "host": host_info()}
     return {"workload": "config3: 1024 traces, lengths 10^(3+3u), config-1 mix, 1000 lines, T in {256K,1M,10M}",
-            "cpu_baseline_all_cores": cpu_all,
+            "cpu_baseline_one_core": cpu_one, "cpu_baseline_all_cores": cpu_all,
             "events": total, "batched_events_per_s": round(total / tb, 1), "batched_ms": round(tb * 1e3, 3),
             "batched_kernel_ms": round(kms_avg, 3),
-            "batched_pass_ms": {k: round(sum(r[k] for r in pass_runs[1:]) / max(len(pass_runs) - 1, 1), 4)
-                                for k in smp.PASS_NAMES},
-            "batched_kernel_hbm_gbs": round(BYTES_PER_EVENT * total / (kms_avg * 1e-3) / 1e9, 1),
+            "batched_phase_ms": {k: round(statistics.median(p[i] for p in phases) * (1 if i == 3 else 1e3), 3)
+                                 for i, k in enumerate(("submit_traces", "run_blocking", "release_traces",
+                                                        "launch_sequence_gpu"))},
+            "batched_pass_ms": {k: round(v, 4) for k, v in passes.items()},
+            "roofline": roof, "tuning": tuned, "launches": s_stats,
             "plain_events_per_s": round(total / tp, 1), "plain_ms": round(tp * 1e3, 3),
             "speedup_vs_plain": round(tp / tb, 2)}
 
 
-def bench_served(smp, tg, torch, np, n_req, rates=(200.0, 1000.0, 5000.0)):
+def served_rates(args):
+    return tuple(float(x) for x in args.served_rates.split(",") if x)
+
+
+def bench_served(smp, tg, torch, np, n_req, rates=(200.0, 1000.0, 5000.0), plain=True):
     """Config 4: Poisson arrivals, LogNormal(ln 5e4, 1.5) lengths capped at
     2e7, config-1 mix, T = 1 MiB, events in pinned host memory (each request
     crosses PCIe), 32 GiB admission budget.  Served (continuous batching)
-    against plain (one launch per request, in order)."""
+    against plain (one launch per request, in order).  The PCIe part of the
+    latency is reported beside it: the pinned host-to-device copy rate
+    measured here, and each request's copy time at that rate."""
     from paper_2212_07597_amd import serve
     log(f"served: generating {n_req} requests")
     plan = tg.config4_plan(base_seed=4, n_req=n_req, rate=1000.0)
@@ -397,19 +622,38 @@ def bench_served(smp, tg, torch, np, n_req, rates=(200.0, 1000.0, 5000.0)):
     p = smp.make_params(pool[0][2]["threshold"], pool[0][2]["num_lines"])
     budget = 32 << 30
     s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + budget + (1 << 20))
+    # pinned host-to-device copy rate (256 MiB, median of 5)
+    src = torch.empty(256 << 20, dtype=torch.uint8).pin_memory()
+    dst = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    bw = []
+    for _ in range(6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dst.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        bw.append((256 << 20) / (time.perf_counter() - t0))
+    h2d = statistics.median(bw[1:])
+    del src, dst
+    copy_ms = np.array([BYTES_PER_EVENT * x[1] / h2d * 1e3 for x in pool])
     out = {"workload": "config4: Poisson arrivals, LogNormal(ln 5e4, 1.5) lengths capped at 2e7, config-1 mix, "
                        "T=1 MiB, pinned host events, 32 GiB budget",
-           "requests": n_req, "events": int(sum(x[1] for x in pool)), "rates": {}}
+           "requests": n_req, "events": int(sum(x[1] for x in pool)),
+           "h2d": {"gbs": round(h2d / 1e9, 2), "request_copy_ms_p50": round(float(np.percentile(copy_ms, 50)), 4),
+                   "request_copy_ms_p99": round(float(np.percentile(copy_ms, 99)), 4),
+                   "note": "pinned host-to-device copy time of each request's events at the measured rate; "
+                           "part of every served and plain latency"},
+           "rates": {}}
     for rate in rates:
         arr = tg.config4_plan(base_seed=40 + int(rate), n_req=n_req, rate=rate)
         reqs = [serve.Request(i, a, pool[i][0], p, pool[i][1]) for i, (_, a, _) in enumerate(arr)]
         log(f"served: rate {rate}/s")
         o_s, mk_s = serve.serve(s, reqs, max_inflight=4)
-        o_p, mk_p = serve.serve_plain(s, reqs)
-        st_s, st_p = serve.latency_stats(o_s), serve.latency_stats(o_p)
-        out["rates"][str(int(rate))] = {
-            "served": {**st_s, "events_per_s": round(out["events"] / (mk_s / 1e9), 1)},
-            "plain": {**st_p, "events_per_s": round(out["events"] / (mk_p / 1e9), 1)}}
+        st_s = serve.latency_stats(o_s)
+        out["rates"][str(int(rate))] = {"served": {**st_s, "events_per_s": round(out["events"] / (mk_s / 1e9), 1)}}
+        if plain:
+            o_p, mk_p = serve.serve_plain(s, reqs)
+            st_p = serve.latency_stats(o_p)
+            out["rates"][str(int(rate))]["plain"] = {**st_p, "events_per_s": round(out["events"] / (mk_p / 1e9), 1)}
     s.close()
     return out
 

@@ -255,9 +255,38 @@ SMP_API int sampler_last_pass_timing(smp_sampler_t *s, float *pass_ms);
 /* Diagnostics: the 32 control words of the last launch (word 1: abort flag,
  * words 2 and 3: tiles taken by the resolve and scan passes, word 4:
  * segments the chain pass followed through their records (the resolve pass
- * finishes the others), word 5: tracked-bitmap blocks taken by the ranking
- * of the tracked list). */
+ * finishes the others); the other words are 0). */
 SMP_API int sampler_last_counters(smp_sampler_t *s, uint64_t *out32);
+
+/* Launch parameters of later runs.  None changes any result (every
+ * choice computes the same profile); they trade work between passes:
+ *   chain_cap  : distinct chains the summary pass follows through a segment
+ *                before it gives up and leaves the segment to be followed
+ *                from its actual entry (1..64, default 16)
+ *   chain_grid : workgroups of the chain pass (0 = as many as the device
+ *                holds at once, the default)
+ *   emit_grid  : workgroups of the emit pass (0 = the same default)
+ *   graphs     : 1 (default) = a run slot replays a launch sequence whose
+ *                shape (trace count, segment, tile, block and line totals,
+ *                grids, timing events) it launched before as a HIP graph,
+ *                captured on the second launch of that shape; launches that
+ *                record timing events between passes (sampler_set_pass_events
+ *                bits 0-5) are always plain; 0 = plain launches only
+ * sampler_set_tuning returns SMP_EINVAL for values out of range;
+ * sampler_get_tuning reports the current ones with the defaults resolved. */
+typedef struct {
+    uint32_t chain_cap;
+    uint32_t chain_grid;
+    uint32_t emit_grid;
+    uint32_t graphs;
+} smp_tuning_t;
+SMP_API int sampler_set_tuning(smp_sampler_t *s, const smp_tuning_t *t);
+SMP_API int sampler_get_tuning(smp_sampler_t *s, smp_tuning_t *t);
+
+/* Launch counts since the sampler was created: out3[0] launch sequences
+ * issued plainly, out3[1] graphs captured, out3[2] graph replays (a capture
+ * is followed by its first replay). */
+SMP_API int sampler_launch_stats(smp_sampler_t *s, uint64_t *out3);
 
 /* Bytes of the workspace the sampler keeps for itself (descriptor tables,
  * counters); the rest is the trace budget. */
@@ -328,8 +357,11 @@ SMP_API int rate_run_noalloc(const smp_event_t *ev, uint64_t n, int64_t threshol
  * fetch_profile returns them; "at least 1 %" is 100 x >= the total of the
  * lines' positive values (a line with x <= 0 never qualifies; a zero total
  * selects nothing); neighbours are the ids one below and one above, inside
- * [0, num_lines).  At most 100 lines can hold 1 % each, so one criterion
- * selects at most 300 lines and the two together at most 600.
+ * [0, num_lines).  The paper bounds a profile at 300 lines: at most 100
+ * lines can hold 1 % of one total, but the two criteria together can admit
+ * 200, so when more than 100 qualify the 100 with the largest share stay (a
+ * line's share: the larger of its time share and its memory share, compared
+ * exactly; equal shares keep the lower id) before neighbours are added.
  *   py_time_us, nat_time_us, growth_bytes : host arrays of num_lines values
  *   out_lines : host array with room for num_lines ids, written in
  *               increasing order; *n_out receives their number

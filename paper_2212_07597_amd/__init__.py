@@ -31,6 +31,7 @@ TRACKED_DTYPE = np.dtype([("event_idx", "<u4"), ("line", "<u4"), ("ptr", "<u4"),
 EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", "fetch_profile",
             "trace_device_results", "submit_traces", "release_traces", "sampler_last_timing",
             "sampler_set_pass_events", "sampler_last_pass_timing", "sampler_last_counters", "sampler_fixed_bytes",
+            "sampler_set_tuning", "sampler_get_tuning", "sampler_launch_stats",
             "sampler_destroy", "error_string", "rate_workspace_bytes", "rate_run", "rate_run_noalloc", "report_lines",
             "leak_report", "timeline_points")
 
@@ -72,6 +73,15 @@ class Profile(ctypes.Structure):
         ("n_tracked", ctypes.c_uint64),
         ("status", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+    ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("chain_cap", ctypes.c_uint32),
+        ("chain_grid", ctypes.c_uint32),
+        ("emit_grid", ctypes.c_uint32),
+        ("graphs", ctypes.c_uint32),
     ]
 
 
@@ -120,6 +130,12 @@ def lib():
         L.sampler_set_pass_events.restype = i32
         L.sampler_last_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
         L.sampler_last_counters.restype = i32
+        L.sampler_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.sampler_set_tuning.restype = i32
+        L.sampler_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.sampler_get_tuning.restype = i32
+        L.sampler_launch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.sampler_launch_stats.restype = i32
         L.sampler_fixed_bytes.argtypes = []
         L.sampler_fixed_bytes.restype = u64
         L.sampler_destroy.argtypes = [vp]
@@ -458,6 +474,22 @@ class Sampler:
         buf = (ctypes.c_float * len(PASS_NAMES))()
         _check("sampler_last_pass_timing", lib().sampler_last_pass_timing(self.h, buf))
         return dict(zip(PASS_NAMES, (float(x) for x in buf)))
+
+    def set_tuning(self, chain_cap=16, chain_grid=0, emit_grid=0, graphs=1):
+        """Launch parameters of later runs (no effect on results)."""
+        _check("sampler_set_tuning", lib().sampler_set_tuning(self.h, ctypes.byref(
+            Tuning(int(chain_cap), int(chain_grid), int(emit_grid), int(graphs)))))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check("sampler_get_tuning", lib().sampler_get_tuning(self.h, ctypes.byref(t)))
+        return {"chain_cap": t.chain_cap, "chain_grid": t.chain_grid, "emit_grid": t.emit_grid, "graphs": t.graphs}
+
+    def launch_stats(self):
+        """(plain launch sequences, graphs captured, graph replays) so far."""
+        buf = (ctypes.c_uint64 * 3)()
+        _check("sampler_launch_stats", lib().sampler_launch_stats(self.h, buf))
+        return {"plain": int(buf[0]), "captured": int(buf[1]), "replayed": int(buf[2])}
 
     def last_counters(self):
         buf = (ctypes.c_uint64 * 32)()

@@ -17,11 +17,10 @@ constexpr int WAVES = 4;                 // wavefronts per workgroup of the per-
 constexpr int BLOCK = 64 * WAVES;
 constexpr int TILE = 1024;               // segments per tile
 constexpr int TWAVES = TILE / 64;
-constexpr int CHAIN_SLOTS = 32;          // LDS histogram cache slots per workgroup: chain pass (copy, timer)
 constexpr int EMIT_SLOTS = 128;          // emit pass (samples)
 constexpr int TRACK_SLOTS = 64;          // and tracked-list pass (mallocs, frees)
 constexpr int NCNT = 12;                 // counters cached per slot
-constexpr int CHAIN_CAP = 32;            // chains followed by the all-entry analysis
+constexpr int CHAIN_CAP_MAX = 64;        // chains the all-entry analysis can follow (one per lane)
 
 constexpr int64_t MAX_ABS_DELTA = (int64_t)1 << 52;
 constexpr int64_t MAX_ABS_F = (int64_t)1 << 61;
@@ -107,7 +106,7 @@ struct Desc {
     uint32_t L;
     uint32_t options;
     int32_t tc_shift;        // log2(Tc) if Tc is a power of two, else -1
-    uint32_t pad0;
+    uint32_t chain_cap;      // chains the all-entry analysis follows before it gives a segment a SIM map (<= 64)
     uint64_t seg_begin;      // first global segment index of this trace
     uint64_t nseg;
     uint64_t tile_begin;     // first global tile index of this trace

@@ -15,12 +15,12 @@
 namespace smp {
 int chain_grid_limit();
 int emit_grid_limit();
+int track_grid_limit();
 hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, unsigned long long* ctl, hipStream_t s);
 hipError_t launch_pass(int pass, const Desc* desc, int ntraces, uint64_t nseg_total, uint64_t ntile_total,
                        unsigned long long* ctl, int grid_limit, hipStream_t s);
 hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines,
-                         unsigned long long* ctl, hipStream_t s);
-hipError_t launch_gather_scalars(const Desc* desc, int ntraces, Scalars* out, hipStream_t s);
+                         unsigned long long* ctl, int track_grid, Scalars* gather, hipStream_t s);
 }  // namespace smp
 
 using namespace smp;
@@ -156,6 +156,14 @@ struct TraceRec {
 // the last pass, bit 6 the launch's start event.
 constexpr uint32_t PASS_EVENTS_ALL = 0x7F;
 constexpr int START_EVENT_BIT = NPASS + 1;
+constexpr uint32_t PASS_EVENT_BITS = (1u << (NPASS + 1)) - 1;  // the events between passes
+
+// Shape of one launch sequence: everything its kernel arguments and grids
+// depend on besides the slot's own buffers.
+struct LaunchKey {
+    uint64_t cnt, seg, tile, blk, zero, lines, ev_mask, chain_grid, emit_grid, track_grid;
+    bool operator==(const LaunchKey& o) const { return memcmp(this, &o, sizeof(LaunchKey)) == 0; }
+};
 
 struct RunSlot {
     Desc* host_desc = nullptr;   // pinned staging
@@ -173,6 +181,11 @@ struct RunSlot {
     uint32_t ev_mask = 0;               // which e_pass events this launch recorded
     bool busy = false;
     uint64_t seq = 0;
+    LaunchKey last_key{};               // shape of the slot's previous launch
+    bool last_valid = false;
+    hipGraphExec_t gexec = nullptr;     // the captured launch sequence of shape gkey
+    LaunchKey gkey{};
+    bool gkey_valid = false;
 };
 
 }  // namespace
@@ -190,11 +203,14 @@ struct smp_sampler {
     RunSlot slots[RUN_SLOTS];
     uint64_t next_id = 1;
     uint64_t run_seq = 0;
-    int grid_chain = 0, grid_emit = 0;
+    int grid_chain = 0, grid_emit = 0, grid_track = 0;
     bool failed = false;
     float last_main_ms = 0, last_total_ms = 0;
     float last_pass_ms[NPASS] = {};
     uint32_t pass_events = PASS_EVENTS_ALL;  // timing events to record (all by default)
+    smp_tuning_t tuning{16, 0, 0, 1};
+    bool graphs_ok = true;                   // off after a failed capture
+    uint64_t n_plain = 0, n_captured = 0, n_replayed = 0;
     uint64_t last_seq = 0;
 };
 
@@ -349,7 +365,8 @@ int sampler_create(int device, void* hip_stream, uint64_t mem_budget, void* work
     }
     s->grid_chain = chain_grid_limit();
     s->grid_emit = emit_grid_limit();
-    if (s->grid_chain <= 0 || s->grid_emit <= 0) {
+    s->grid_track = track_grid_limit();
+    if (s->grid_chain <= 0 || s->grid_emit <= 0 || s->grid_track <= 0) {
         sampler_destroy(s);
         return SMP_EDEVICE;
     }
@@ -374,6 +391,7 @@ void sampler_destroy(smp_sampler_t* s) {
         for (auto& e : r.e_pass)
             if (e) (void)hipEventDestroy(e);
         if (r.e_end) (void)hipEventDestroy(r.e_end);
+        if (r.gexec) (void)hipGraphExecDestroy(r.gexec);
     }
     delete s;
 }
@@ -422,6 +440,69 @@ int submit_trace(smp_sampler_t* s, const smp_event_t* ev, uint64_t n, const smp_
     return SMP_OK;
 }
 
+// The kernels of one launch, in stream order on r.stream, with the timing
+// events between passes that k asks for (captured into a graph when called
+// between hipStreamBeginCapture and hipStreamEndCapture, which is done only
+// for launches without such events).
+static hipError_t issue_launch(RunSlot& r, const LaunchKey& k) {
+    hipError_t e = hipSuccess;
+    auto ok = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+        return e == hipSuccess;
+    };
+    auto record = [&](hipEvent_t ev) { return hipEventRecord(ev, r.stream); };
+    const int cnt = (int)k.cnt;
+    if (!ok(launch_clear(r.dev_desc, cnt, k.zero, r.dev_ticket, r.stream))) return e;
+    for (int p = 0; p < NPASS; ++p) {
+        if ((k.ev_mask >> p) & 1u && !ok(record(r.e_pass[p]))) return e;
+        const int lim = p == 2 ? (int)k.chain_grid : (int)k.emit_grid;
+        if (!ok(launch_pass(p, r.dev_desc, cnt, k.seg, k.tile, r.dev_ticket, lim, r.stream))) return e;
+    }
+    if ((k.ev_mask >> NPASS) & 1u && !ok(record(r.e_pass[NPASS]))) return e;
+    if (!ok(launch_finish(r.dev_desc, cnt, k.blk, k.lines, r.dev_ticket, (int)k.track_grid, r.dev_scal, r.stream)))
+        return e;
+    ok(hipMemcpyAsync(r.host_scal, r.dev_scal, sizeof(Scalars) * k.cnt, hipMemcpyDeviceToHost, r.stream));
+    return e;
+}
+
+// Capture the launch sequence of key k into the slot's graph (updating the
+// instantiated graph in place when it allows).  On any failure graphs are
+// switched off for the sampler and the caller launches plainly.
+static bool capture_graph(smp_sampler* s, RunSlot& r, const LaunchKey& k) {
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(r.stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        s->graphs_ok = false;
+        return false;
+    }
+    const hipError_t ei = issue_launch(r, k);
+    const hipError_t ee = hipStreamEndCapture(r.stream, &g);
+    bool ok = ei == hipSuccess && ee == hipSuccess && g != nullptr;
+    if (ok && r.gexec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        if (hipGraphExecUpdate(r.gexec, g, &err_node, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(r.gexec);
+            r.gexec = nullptr;
+        }
+    }
+    if (ok && !r.gexec) ok = hipGraphInstantiate(&r.gexec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+        (void)hipGetLastError();
+        if (r.gexec) (void)hipGraphExecDestroy(r.gexec);
+        r.gexec = nullptr;
+        r.gkey_valid = false;
+        s->graphs_ok = false;
+        return false;
+    }
+    r.gkey = k;
+    r.gkey_valid = true;
+    ++s->n_captured;
+    return true;
+}
+
 int run(smp_sampler_t* s, int blocking) {
     if (!s) return SMP_EINVAL;
     if (s->failed) return SMP_EDEVICE;
@@ -433,12 +514,38 @@ int run(smp_sampler_t* s, int blocking) {
     size_t done = 0;
     while (done < pend.size()) {
         const size_t cnt = std::min<size_t>(MAX_TRACES_PER_RUN, pend.size() - done);
-        // pick the oldest slot
-        int si = 0;
-        for (int i = 1; i < RUN_SLOTS; ++i)
-            if (!s->slots[i].busy && (s->slots[si].busy || s->slots[i].seq < s->slots[si].seq)) si = i;
-        if (s->slots[si].busy) {
+        // the launch's shape
+        LaunchKey key{};
+        key.cnt = cnt;
+        for (size_t k = 0; k < cnt; ++k) {
+            const TraceRec& t = *pend[done + k];
+            key.seg += t.lay.nseg;
+            key.tile += t.lay.ntile;
+            key.blk += t.lay.nblk;
+            key.zero += t.lay.zero_end - t.lay.zero;
+            key.lines += t.params.num_lines;
+        }
+        key.ev_mask = s->pass_events;
+        key.chain_grid = s->tuning.chain_grid ? s->tuning.chain_grid : (uint64_t)s->grid_chain;
+        key.emit_grid = s->tuning.emit_grid ? s->tuning.emit_grid : (uint64_t)s->grid_emit;
+        key.track_grid = (uint64_t)s->grid_track;
+        // A free slot that launched this shape before (its graph or its
+        // descriptors may be reused), else the free slot used longest ago,
+        // else the busy slot launched longest ago (waited for below).
+        int si = -1;
+        for (int i = 0; i < RUN_SLOTS; ++i) {
+            const RunSlot& c = s->slots[i];
+            if (!c.busy && ((c.gkey_valid && c.gkey == key) || (c.last_valid && c.last_key == key)) &&
+                (si < 0 || c.seq > s->slots[si].seq))
+                si = i;
+        }
+        if (si < 0) {
             for (int i = 0; i < RUN_SLOTS; ++i)
+                if (!s->slots[i].busy && (si < 0 || s->slots[i].seq < s->slots[si].seq)) si = i;
+        }
+        if (si < 0) {
+            si = 0;
+            for (int i = 1; i < RUN_SLOTS; ++i)
                 if (s->slots[i].seq < s->slots[si].seq) si = i;
         }
         RunSlot& r = s->slots[si];
@@ -458,6 +565,7 @@ int run(smp_sampler_t* s, int blocking) {
             D.L = t.params.num_lines;
             D.options = t.params.options;
             D.tc_shift = -1;
+            D.chain_cap = s->tuning.chain_cap;
             if ((D.Tc & (D.Tc - 1)) == 0) D.tc_shift = __builtin_ctzll((uint64_t)D.Tc);
             D.seg_begin = seg;
             D.nseg = t.lay.nseg;
@@ -506,17 +614,28 @@ int run(smp_sampler_t* s, int blocking) {
         }
         // an event between two kernels costs a few microseconds of idle GPU
         r.ev_mask = s->pass_events;
+        // A shape this slot launched before is replayed as a HIP graph (the
+        // kernels read the descriptors uploaded above; no memset nodes: the
+        // clearing is a kernel); a new shape, or a launch that records timing
+        // events between its passes, is launched plainly.  The start and end
+        // events are recorded outside the graph.
         if ((r.ev_mask >> START_EVENT_BIT) & 1u) HIPCHK(hipEventRecord(r.e_start, r.stream));
-        HIPCHK(launch_clear(r.dev_desc, (int)cnt, zero, r.dev_ticket, r.stream));
-        for (int p = 0; p < NPASS; ++p) {
-            if ((r.ev_mask >> p) & 1u) HIPCHK(hipEventRecord(r.e_pass[p], r.stream));
-            const int lim = p == 2 ? s->grid_chain : s->grid_emit;
-            HIPCHK(launch_pass(p, r.dev_desc, (int)cnt, seg, tile, r.dev_ticket, lim, r.stream));
+        bool graphed = false;
+        if (s->tuning.graphs && s->graphs_ok && (key.ev_mask & PASS_EVENT_BITS) == 0) {
+            if (r.gkey_valid && r.gkey == key)
+                graphed = true;
+            else if (r.last_valid && r.last_key == key)
+                graphed = capture_graph(s, r, key);
         }
-        if ((r.ev_mask >> NPASS) & 1u) HIPCHK(hipEventRecord(r.e_pass[NPASS], r.stream));
-        HIPCHK(launch_finish(r.dev_desc, (int)cnt, blk, lines, r.dev_ticket, r.stream));
-        HIPCHK(launch_gather_scalars(r.dev_desc, (int)cnt, r.dev_scal, r.stream));
-        HIPCHK(hipMemcpyAsync(r.host_scal, r.dev_scal, sizeof(Scalars) * cnt, hipMemcpyDeviceToHost, r.stream));
+        if (graphed) {
+            HIPCHK(hipGraphLaunch(r.gexec, r.stream));
+            ++s->n_replayed;
+        } else {
+            HIPCHK(issue_launch(r, key));
+            ++s->n_plain;
+        }
+        r.last_key = key;
+        r.last_valid = true;
         HIPCHK(hipEventRecord(r.e_end, r.stream));
         r.busy = true;
         done += cnt;
@@ -657,6 +776,30 @@ int sampler_last_timing(smp_sampler_t* s, float* main_kernel_ms, float* total_ms
 int sampler_set_pass_events(smp_sampler_t* s, uint32_t mask) {
     if (!s || (mask & ~PASS_EVENTS_ALL) != 0) return SMP_EINVAL;
     s->pass_events = mask;
+    return SMP_OK;
+}
+
+int sampler_set_tuning(smp_sampler_t* s, const smp_tuning_t* t) {
+    if (!s || !t || t->chain_cap < 1 || t->chain_cap > (uint32_t)CHAIN_CAP_MAX || t->chain_grid > (1u << 20) ||
+        t->emit_grid > (1u << 20) || t->graphs > 1)
+        return SMP_EINVAL;
+    s->tuning = *t;
+    return SMP_OK;
+}
+
+int sampler_get_tuning(smp_sampler_t* s, smp_tuning_t* t) {
+    if (!s || !t) return SMP_EINVAL;
+    *t = s->tuning;
+    if (!t->chain_grid) t->chain_grid = (uint32_t)s->grid_chain;
+    if (!t->emit_grid) t->emit_grid = (uint32_t)s->grid_emit;
+    return SMP_OK;
+}
+
+int sampler_launch_stats(smp_sampler_t* s, uint64_t* out3) {
+    if (!s || !out3) return SMP_EINVAL;
+    out3[0] = s->n_plain;
+    out3[1] = s->n_captured;
+    out3[2] = s->n_replayed;
     return SMP_OK;
 }
 

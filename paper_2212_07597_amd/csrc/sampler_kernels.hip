@@ -107,6 +107,56 @@ __device__ __forceinline__ void hist_flush(HistCache<NS>& hc, const Desc* desc) 
     }
 }
 
+// Per-workgroup LDS cache of the copy and timer counters of up to
+// AUX_SLOTS (trace, line) keys (copy: sampled and exact bytes; timer: Python
+// and native time), larger than the general cache because these events are
+// many and their lines Zipf-spread; a slot held by another line sends the
+// update to global atomics.
+constexpr int AUX_SLOTS = 512;
+struct AuxCache {
+    unsigned long long key[AUX_SLOTS];
+    unsigned long long cnt[AUX_SLOTS][4];  // copy sampled, copy exact, Python time, native time
+};
+
+__device__ __forceinline__ void aux_init(AuxCache& ac) {
+    for (int i = threadIdx.x; i < AUX_SLOTS; i += blockDim.x) {
+        ac.key[i] = EMPTY_KEY;
+        for (int c = 0; c < 4; ++c) ac.cnt[i][c] = 0;
+    }
+}
+
+__device__ __forceinline__ void aux_add(AuxCache& ac, const Desc& D, uint32_t t, uint32_t line, bool copy, int64_t v0,
+                                        int64_t v1) {
+    const unsigned long long key = ((unsigned long long)t << 32) | line;
+    const uint32_t h = (line * 2654435761u) ^ (t * 0x9E3779B9u);
+    const int slot = (int)(h >> 23) & (AUX_SLOTS - 1);
+    unsigned long long k = ac.key[slot];
+    if (k == EMPTY_KEY) k = atomicCAS(&ac.key[slot], EMPTY_KEY, key);
+    const int c0 = copy ? 0 : 2;
+    if (k == EMPTY_KEY || k == key) {
+        if (v0) atomicAdd(&ac.cnt[slot][c0], (unsigned long long)v0);
+        if (v1) atomicAdd(&ac.cnt[slot][c0 + 1], (unsigned long long)v1);
+    } else {
+        const int h0 = copy ? H_CS : H_PT, h1 = copy ? H_CE : H_NT;
+        if (v0) g_add((uint64_t*)&D.hist[(size_t)h0 * D.L + line], (uint64_t)v0);
+        if (v1) g_add((uint64_t*)&D.hist[(size_t)h1 * D.L + line], (uint64_t)v1);
+    }
+}
+
+__device__ __forceinline__ void aux_flush(AuxCache& ac, const Desc* desc) {
+    static constexpr int planes[4] = {H_CS, H_CE, H_PT, H_NT};
+    for (int i = threadIdx.x; i < AUX_SLOTS; i += blockDim.x) {
+        const unsigned long long key = ac.key[i];
+        if (key == EMPTY_KEY) continue;
+        const Desc& D = desc[(uint32_t)(key >> 32)];
+        const uint32_t line = (uint32_t)key;
+        for (int c = 0; c < 4; ++c) {
+            const unsigned long long v = ac.cnt[i][c];
+            if (v) g_add((uint64_t*)&D.hist[(size_t)planes[c] * D.L + line], v);
+        }
+    }
+}
+
 // last trace whose first segment index is <= x
 __device__ __forceinline__ int find_trace_seg(const Desc* desc, int lo, int ntraces, uint64_t x) {
     int hi = ntraces - 1;
@@ -333,8 +383,9 @@ struct SegMap {
 };
 
 // All-entry analysis of a segment without forced events (F: relative
-// prefixes in LDS).
-__device__ SegMap analyse_segment(const int64_t* F, int64_t T, int64_t sumF) {
+// prefixes in LDS), following at most cap distinct chains at once (cap <= 64,
+// one per lane; more make the map SIM).
+__device__ SegMap analyse_segment(const int64_t* F, int64_t T, int64_t sumF, int cap) {
     const int l = lane_id();
     SegMap m;
     // Entries in [Lo, Hi] have not sampled yet; chain c (lane c < nch) holds
@@ -383,7 +434,7 @@ __device__ SegMap analyse_segment(const int64_t* F, int64_t T, int64_t sumF) {
                 U |= 1ull << c;
                 int64_t ref = readlane64(f, c);
                 if (follow(f, T, ref, c, U)) {
-                    if (nal >= CHAIN_CAP) {
+                    if (nal >= cap) {
                         ovf = true;
                         break;
                     }
@@ -809,7 +860,7 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
         m.kind = MAP_TOTAL;
         m.fnode = fnode;
     } else {
-        m = analyse_segment(lF_, T, cF);
+        m = analyse_segment(lF_, T, cF, (int)D.chain_cap);
         if (m.kind == MAP_SIM && prefixes_kept(D)) {
             SMP_GLOBAL int64_t* o = kept_prefixes(D, j);
 #pragma unroll
@@ -979,6 +1030,7 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     __shared__ int64_t ring[RING][SEG];
     __shared__ int r_ready[RING];  // walk-order SIM index held by each slot
     __shared__ int s_prod, s_cons, s_abort;
+    __shared__ int w_wide[TWAVES];
     __shared__ int64_t s_entry;
     const int tid = threadIdx.x, wv = tid >> 6, l = lane_id();
     if (tid == 0) {
@@ -1023,9 +1075,12 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
         w_sum[1][wv] = iP;
         w_sum[2][wv] = iC;
     }
+    // SIM maps whose no-sample interval holds at least half of the entries
+    const int nwide_w = __popcll(ballot(valid && kind == MAP_SIM && hi - lo >= D.T));
     if (l == 0) {
         w_tot[wv] = tot;
         w_sim[wv] = sim;
+        w_wide[wv] = nwide_w;
     }
     __syncthreads();
     int64_t oF = 0, oP = 0, oC = 0, tF = 0, tP = 0, tC = 0;
@@ -1045,10 +1100,11 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     // prefixes relative to the tile start (the tile's own prefix is added at the end)
     const int64_t rF = oF + iF - af, rP = oP + iP - ap, rC = oC + iC - ac;
     // SIM segments in walk order: (ft, nval) first, then [0, ft)
-    int nA = 0, nsim = 0;
+    int nA = 0, nsim = 0, nwide = 0;
     for (int w = 0; w < TWAVES; ++w) {
         nA += __popcll(w_sim[w] & range_mask(w, ft + 1, nval));
         nsim += __popcll(w_sim[w]);
+        nwide += w_wide[w];
     }
     // publish the tile's sums (inclusive right away for the first tile)
     if (tid < 3) st_status(ts.at(W_AF + tid, k), pack(tid == 0 ? tF : (tid == 1 ? tP : tC), 1));
@@ -1056,6 +1112,13 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     const int64_t T = D.T;
 
     const bool kept = prefixes_kept(D);
+    // Sparse tile: most SIM maps leave at least half of the entries without a
+    // sample, so the walker stops at few of them (T far above what a segment
+    // moves).  Producers pre-scanning every SIM segment would fall behind the
+    // walker, and their loads would queue in the CU's memory pipeline ahead
+    // of the walker's own (each stop of the walker waits for one): here the
+    // other waves stay idle and the walker reads the kept prefixes itself.
+    const bool sparse = kept && nsim > 0 && 4 * nwide >= 3 * nsim;
     if (wv == 0) {
         // ---- the walker ----
         int q = 0;  // SIM segments passed, in walk order
@@ -1102,8 +1165,8 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                         int64_t r = readlane64(kf, stop);
                         if ((sim >> stop) & 1) {
                             const int slot = q % RING;
-                            if (kept && __hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE,
-                                                          __HIP_MEMORY_SCOPE_WORKGROUP) != q) {
+                            if (sparse || (kept && __hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE,
+                                                                     __HIP_MEMORY_SCOPE_WORKGROUP) != q)) {
                                 // its producer is behind: read the kept prefixes instead of waiting
                                 r = walk_kept(D, k * TILE + g0 + stop, T, xs);
                             } else {
@@ -1162,8 +1225,8 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                 if (!ok) g_or32(&D.scal->err, 8u);
             }
         }
-        // ---- producers: pre-scan SIM segments in walk order ----
-        for (;;) {
+        // ---- producers: pre-scan SIM segments in walk order (dense tiles only) ----
+        if (!sparse) for (;;) {
             // every lane takes part (lane 0 adds 1, the others 0): a lane-0-only
             // region here lets the compiler split the wave across loop trips
             const int pidx = __builtin_amdgcn_readfirstlane(
@@ -1330,8 +1393,8 @@ __device__ __forceinline__ void load_head(const Desc& D, int64_t j, ChainHead& h
 // entry offset; record its samples, count, best growth sample and the Python
 // footprint at its last sample.  Copy and timer events are counted here.
 __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
-    __shared__ HistCache<CHAIN_SLOTS> hc;
-    hist_init(hc);
+    __shared__ AuxCache ac;
+    aux_init(ac);
     __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int l = lane_id();
@@ -1467,19 +1530,24 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         // time += quantum, native time += delay).  Only segments that hold such
         // events re-read their records here.
         if (flg & 4) {
+            // every window's words loaded before the first use
+            gu8_t* base = (gu8_t*)(D.ev + (size_t)a * 24);  // wave-uniform
+            uint64_t ad[NW];
+            uint32_t aln[NW], afw[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                gu8_t* p = record_addr(base, nv, w);
+                ad[w] = *(gu64_t*)p;
+                aln[w] = *(gu32_t*)(p + 12);
+                afw[w] = *(gu32_t*)(p + 16);
+            }
             int64_t cc = C0;
+#pragma unroll
             for (int w = 0; w < NW; ++w) {
                 const int k = w * 64 + l;
-                uint64_t r0 = 0, r1 = 0, r2 = 0;
-                if (k < nv) {
-                    gu64_t* rp = record(D, a + k);
-                    r0 = rp[0];
-                    r1 = rp[1];
-                    r2 = rp[2];
-                }
-                const int64_t delta = (int64_t)r0;
-                const uint32_t line = (uint32_t)(r1 >> 32);
-                const uint32_t kind = ((uint32_t)r2 >> 1) & 3;
+                const int64_t delta = (int64_t)ad[w];
+                const uint32_t line = aln[w];
+                const uint32_t kind = (afw[w] >> 1) & 3;
                 const bool lok = k < nv && line < D.L;
                 const bool cp = lok && kind == 1 && delta >= 0 && delta < MAX_ABS_DELTA;
                 const bool tm = lok && kind == 2 && delta >= 0 && delta <= (int64_t)0xFFFFFFFFll;
@@ -1487,7 +1555,6 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
                 const int64_t sc_ = wave_incl_sum(dc) + cc;
                 cc = readlane64(sc_, 63);
                 if (cp || tm) {
-                    int c0 = C_PT, c1 = C_NT;
                     int64_t v0 = D.q, v1 = delta;
                     if (cp) {
                         const uint64_t cout = (uint64_t)sc_, cin = cout - (uint64_t)dc;
@@ -1496,12 +1563,10 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
                             nsmp = (cout >> D.tc_shift) - (cin >> D.tc_shift);
                         else
                             nsmp = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
-                        c0 = C_CS;
-                        c1 = C_CE;
                         v0 = (int64_t)(nsmp * (uint64_t)D.Tc);
                         v1 = dc;
                     }
-                    hist_add(hc, D, (uint32_t)t, line, c0, v0, c1, v1, -1, 0, -1, 0);
+                    aux_add(ac, D, (uint32_t)t, line, cp, v0, v1);
                 }
             }
         }
@@ -1560,7 +1625,7 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
     }
     if (have_t && l == 0 && peakS > 0) g_max(&desc[cur_t].scal->peak_S, (int64_t)peakS);
     __syncthreads();
-    hist_flush(hc, desc);
+    aux_flush(ac, desc);
 }
 
 // --------------------------------------------------------------- scan pass
@@ -2017,117 +2082,102 @@ __device__ bool count_lookback(const uint64_t* st, int64_t b, uint64_t& excl, un
 }
 
 // Ordered tracked list (the samples that set a new high-water mark, section
-// 3.4), in two steps.  k_track_rank: each compaction block of a trace's
-// tracked bitmap counts its set bits, takes the count before it from a
-// look-back over the trace's earlier blocks (status words in D.blk, cleared
-// per launch; blocks are taken by ticket, so every block waited on is
-// running or done) and writes the sample rank of each of its tracked samples
-// at its place in the list (stores only); the block holding the bitmap's
-// last word writes H.  k_track_fill then completes each entry in parallel.
-__global__ __launch_bounds__(256) void k_track_rank(const Desc* __restrict__ desc, int ntraces, uint64_t nblk_total,
-                                                    unsigned long long* ctl) {
-    __shared__ uint64_t s_tk, s_excl;
-    __shared__ uint64_t w_cnt[4];
-    const int tid = threadIdx.x, l = lane_id(), wv = tid >> 6;
-    if (tid == 0) s_tk = g_add_rtn((uint64_t*)&ctl[5], 1ull);
-    __syncthreads();
-    const uint64_t b = s_tk;
-    if (b >= nblk_total) return;
-    const Desc& D = desc[find_trace_blk(desc, ntraces, b)];
-    const uint64_t lb = b - D.blk_begin;
-    const uint64_t Kr = *gp(&D.scal->K);
-    const uint64_t K = Kr < D.n ? Kr : D.n;
-    const uint64_t nwords = (K + 63) >> 6;
-    const uint64_t w0 = lb * CBLK_WORDS;
-    if (w0 >= nwords) return;  // the whole block: no tracked sample here (H stays 0 if none at all)
-    // each thread owns 4 consecutive words
-    constexpr int PER = CBLK_WORDS / 256;
-    uint64_t words[PER];
-    uint64_t c = 0;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const uint64_t wi = w0 + (uint64_t)tid * PER + i;
-        words[i] = wi < nwords ? gp(D.tracked_bits)[wi] : 0;
-        c += __popcll(words[i]);
-    }
-    const uint64_t ci = (uint64_t)wave_incl_sum((int64_t)c);
-    if (l == 63) w_cnt[wv] = ci;
-    __syncthreads();
-    uint64_t woff = 0, total = 0;
-    for (int w = 0; w < 4; ++w) {
-        if (w < wv) woff += w_cnt[w];
-        total += w_cnt[w];
-    }
-    uint64_t* st = D.blk;
-    if (wv == 0) {
-        uint64_t excl = 0;
-        bool ok = true;
-        if (lb == 0) {
-            if (l == 0) st_status(st, pack((int64_t)total, 2));
-        } else {
-            if (l == 0) st_status(st + lb, pack((int64_t)total, 1));
-            ok = count_lookback(st, (int64_t)lb, excl, ctl);
-            if (l == 0) st_status(st + lb, pack((int64_t)(excl + total), 2));
-        }
-        if (l == 0) {
-            s_excl = excl;
-            if (!ok) g_or32(&D.scal->err, 8u);
-        }
-    }
-    __syncthreads();
-    if (tid == 0 && w0 + CBLK_WORDS >= nwords) *gp(&D.scal->H) = s_excl + total;
-    uint64_t h = s_excl + woff + ci - c;
-    SMP_GLOBAL uint32_t* tq = (SMP_GLOBAL uint32_t*)D.tracked;
-    for (int i = 0; i < PER; ++i) {
-        uint64_t m = words[i];
-        const uint64_t wi = w0 + (uint64_t)tid * PER + i;
-        while (m) {
-            const int bit = __builtin_ctzll(m);
-            m &= m - 1;
-            const uint64_t r = wi * 64 + bit;
-            if (r >= K) break;  // only reachable after an internal fault
-            tq[4 * h] = (uint32_t)r;
-            ++h;
-        }
-    }
-}
-
-// Entry h of the tracked list (rank r from k_track_rank): event, line and
-// ptr_id of the tracked sample, whether a free reclaimed it (section 3.4),
-// and the per-line (mallocs, frees) counts.  The last tracked object counts
-// as reclaimed only with RESOLVE_AT_END.
-__global__ __launch_bounds__(256) void k_track_fill(const Desc* __restrict__ desc, int ntraces, uint64_t nblk_total) {
+// 3.4) in one pass: the entries in rank order, each with the event, line and
+// ptr_id of its sample and whether a free reclaimed it, and the per-line
+// (mallocs, frees) counts.  Grid-stride over the compaction blocks of every
+// trace's tracked bitmap (only the blocks that hold words below the trace's
+// sample count do work), each workgroup taking its blocks in increasing
+// order.  A block counts its set bits, publishes that count (status words in
+// D.blk, cleared per launch), takes the count before it from a look-back
+// over the trace's earlier blocks and writes its entries; the block holding
+// the bitmap's last word writes H.  The grid never exceeds what the device
+// holds at once, so every block a look-back waits on belongs to a running
+// workgroup that reaches it in order.  Every reclaimed object is counted
+// here; the last one of a trace (unresolved unless RESOLVE_AT_END) is taken
+// back out by k_finish.
+__global__ __launch_bounds__(256) void k_track(const Desc* __restrict__ desc, int ntraces, uint64_t nblk_total,
+                                               unsigned long long* ctl) {
     __shared__ HistCache<TRACK_SLOTS> hc;
+    __shared__ uint64_t s_excl;
+    __shared__ uint64_t w_cnt[4];
     hist_init(hc);
     __syncthreads();
-    const uint64_t b = blockIdx.x;
-    if (b < nblk_total) {
+    const int tid = threadIdx.x, l = lane_id(), wv = tid >> 6;
+    constexpr int PER = CBLK_WORDS / 256;  // each thread owns PER consecutive words
+    for (uint64_t b = blockIdx.x; b < nblk_total; b += gridDim.x) {
         const uint32_t t = (uint32_t)find_trace_blk(desc, ntraces, b);
         const Desc& D = desc[t];
         const uint64_t lb = b - D.blk_begin;
-        const uint64_t H = *gp(&D.scal->H);
         const uint64_t Kr = *gp(&D.scal->K);
         const uint64_t K = Kr < D.n ? Kr : D.n;
-        // the counts through this block and through the one before it (only
-        // blocks that hold bitmap words published one)
-        const bool active = lb * CBLK_WORDS < ((K + 63) >> 6);
-        const uint64_t h1 = active ? (uint64_t)unpack(ld_status(D.blk + lb)) : 0;
-        const uint64_t h0 = active && lb > 0 ? (uint64_t)unpack(ld_status(D.blk + lb - 1)) : 0;
-        const bool resolve_last = (D.options & 2u) != 0;
-        SMP_GLOBAL uint32_t* tq = (SMP_GLOBAL uint32_t*)D.tracked;
-        for (uint64_t h = h0 + threadIdx.x; h < h1 && h < H; h += blockDim.x) {
-            const uint64_t r = tq[4 * h];
-            if (r >= K) continue;  // only reachable after an internal fault
-            const Sample s = load_sample(D.samples + r);
-            const uint32_t freed =
-                s.event_idx < D.n ? (uint32_t)((gp(D.freed_bits)[s.event_idx >> 6] >> (s.event_idx & 63)) & 1) : 0u;
-            tq[4 * h] = s.event_idx;
-            tq[4 * h + 1] = s.line;
-            tq[4 * h + 2] = gp(D.sample_ptr)[r];
-            tq[4 * h + 3] = freed;
-            if (s.line < D.L)
-                hist_add(hc, D, t, s.line, C_LM, 1, C_LF, (freed && (h + 1 < H || resolve_last)) ? 1 : 0, -1, 0, -1, 0);
+        const uint64_t nwords = (K + 63) >> 6;
+        const uint64_t w0 = lb * CBLK_WORDS;
+        if (w0 >= nwords) continue;  // (workgroup-uniform) no sample of this trace in the block
+        uint64_t words[PER];
+        uint64_t c = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint64_t wi = w0 + (uint64_t)tid * PER + i;
+            words[i] = wi < nwords ? gp(D.tracked_bits)[wi] : 0;
+            c += __popcll(words[i]);
         }
+        const uint64_t ci = (uint64_t)wave_incl_sum((int64_t)c);
+        if (l == 63) w_cnt[wv] = ci;
+        __syncthreads();
+        uint64_t woff = 0, total = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < wv) woff += w_cnt[w];
+            total += w_cnt[w];
+        }
+        uint64_t* st = D.blk;
+        if (wv == 0) {
+            uint64_t excl = 0;
+            bool ok = true;
+            if (lb == 0) {
+                if (l == 0) st_status(st, pack((int64_t)total, 2));
+            } else {
+                if (l == 0) st_status(st + lb, pack((int64_t)total, 1));
+                ok = count_lookback(st, (int64_t)lb, excl, ctl);
+                if (l == 0) st_status(st + lb, pack((int64_t)(excl + total), 2));
+            }
+            if (l == 0) {
+                s_excl = excl;
+                if (!ok) g_or32(&D.scal->err, 8u);
+            }
+        }
+        __syncthreads();
+        const uint64_t h0 = s_excl, h1 = s_excl + total;
+        if (tid == 0 && w0 + CBLK_WORDS >= nwords) *gp(&D.scal->H) = h1;
+        // First the sample rank of each entry (tracked samples cluster, so a
+        // thread may own many), then the entries, spread over all threads.
+        uint64_t h = h0 + woff + ci - c;
+        SMP_GLOBAL uint32_t* tq = (SMP_GLOBAL uint32_t*)D.tracked;
+        for (int i = 0; i < PER; ++i) {
+            uint64_t m = words[i];
+            const uint64_t wi = w0 + (uint64_t)tid * PER + i;
+            while (m) {
+                const int bit = __builtin_ctzll(m);
+                m &= m - 1;
+                const uint64_t r = wi * 64 + bit;
+                tq[4 * h] = r < K ? (uint32_t)r : 0xFFFFFFFFu;  // (r >= K only after an internal fault)
+                ++h;
+            }
+        }
+        __syncthreads();
+        for (uint64_t hh = h0 + tid; hh < h1; hh += 256) {
+            const uint32_t r = tq[4 * hh];
+            if (r >= K) continue;
+            const Sample smp_ = load_sample(D.samples + r);
+            const uint32_t freed = smp_.event_idx < D.n
+                                       ? (uint32_t)((gp(D.freed_bits)[smp_.event_idx >> 6] >> (smp_.event_idx & 63)) & 1)
+                                       : 0u;
+            tq[4 * hh] = smp_.event_idx;
+            tq[4 * hh + 1] = smp_.line;
+            tq[4 * hh + 2] = gp(D.sample_ptr)[r];
+            tq[4 * hh + 3] = freed;
+            if (smp_.line < D.L) hist_add(hc, D, t, smp_.line, C_LM, 1, C_LF, (int64_t)freed, -1, 0, -1, 0);
+        }
+        __syncthreads();  // w_cnt and s_excl are reused by the next block
     }
     __syncthreads();
     hist_flush(hc, desc);
@@ -2145,10 +2195,19 @@ __device__ int64_t gcd64(int64_t x, int64_t y) {
     return x;
 }
 
-// Exact reduced rationals: Laplace's rule of succession (m-f+1)/(m+2) and the
-// formula as printed (m-2f+1)/(m-f+2); gate: likelihood > 0.95 (section 3.4).
-__global__ void k_leak_finalize(const Desc* __restrict__ desc, int ntraces, uint64_t total_lines) {
+// After the tracked list: per line, exact reduced rationals of the leak
+// likelihood (section 3.4) - Laplace's rule of succession (m-f+1)/(m+2) and
+// the formula as printed (m-2f+1)/(m-f+2) - and their gates, likelihood >
+// 0.95.  The last tracked object of a trace stays unresolved (its free does
+// not count) unless RESOLVE_AT_END, so the thread of its line takes it back
+// out of that line's frees.  Threads below 8 x ntraces also gather every
+// trace's scalars (final from here on) into one array for a single copy out.
+__global__ void k_finish(const Desc* __restrict__ desc, int ntraces, uint64_t total_lines, Scalars* gather) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (uint64_t)ntraces * 8) {
+        const uint64_t t = i >> 3, w = i & 7;  // 8 words per Scalars
+        gp((uint64_t*)(gather + t))[w] = gp((const uint64_t*)desc[t].scal)[w];
+    }
     if (i >= total_lines) return;
     int lo = 0, hi = ntraces - 1;
     while (lo < hi) {
@@ -2158,8 +2217,19 @@ __global__ void k_leak_finalize(const Desc* __restrict__ desc, int ntraces, uint
     const Desc& D = desc[lo];
     const uint64_t line = i - D.line_begin;
     if (line >= D.L) return;
-    const int64_t m = gp(D.hist)[(size_t)H_LEAK_M * D.L + line];
-    const int64_t f = gp(D.hist)[(size_t)H_LEAK_F * D.L + line];
+    SMP_GLOBAL int64_t* hist = gp(D.hist);
+    const int64_t m = hist[(size_t)H_LEAK_M * D.L + line];
+    int64_t f = hist[(size_t)H_LEAK_F * D.L + line];
+    if (m > 0 && (D.options & 2u) == 0) {
+        const uint64_t H = *gp(&D.scal->H);
+        if (H > 0) {
+            const SMP_GLOBAL uint32_t* last = (const SMP_GLOBAL uint32_t*)(D.tracked + (H - 1));
+            if (last[1] == (uint32_t)line && last[3] != 0) {
+                f -= 1;
+                hist[(size_t)H_LEAK_F * D.L + line] = f;
+            }
+        }
+    }
     SMP_GLOBAL int64_t* out = gp(D.leak);
     SMP_GLOBAL uint8_t* gates = gp(D.gates);
     if (m <= 0) {
@@ -2197,6 +2267,8 @@ static int occupancy_grid(const void* fn, int block) {
 
 int chain_grid_limit() { return occupancy_grid((const void*)k_chain, BLOCK); }
 int emit_grid_limit() { return occupancy_grid((const void*)k_emit, EMIT_BLOCK); }
+// workgroups of k_track the device holds at once (its look-back needs all of them resident)
+int track_grid_limit() { return occupancy_grid((const void*)k_track, 256); }
 
 hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, unsigned long long* ctl, hipStream_t s) {
     const uint64_t blocks = (total_bytes + (1ull << 16) - 1) >> 16;
@@ -2224,29 +2296,14 @@ hipError_t launch_pass(int pass, const Desc* desc, int ntraces, uint64_t nseg_to
     return hipGetLastError();
 }
 
-// Every trace's scalars into one array (copied to the host with one transfer).
-__global__ void k_gather_scalars(const Desc* __restrict__ desc, int ntraces, Scalars* out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ntraces * 8) return;
-    const int t = i >> 3, w = i & 7;  // 8 words per Scalars
-    gp((uint64_t*)(out + t))[w] = gp((const uint64_t*)desc[t].scal)[w];
-}
-
-hipError_t launch_gather_scalars(const Desc* desc, int ntraces, Scalars* out, hipStream_t s) {
-    k_gather_scalars<<<dim3((unsigned)((ntraces * 8 + 255) / 256)), dim3(256), 0, s>>>(desc, ntraces, out);
-    return hipGetLastError();
-}
-
 hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines,
-                         unsigned long long* ctl, hipStream_t s) {
+                         unsigned long long* ctl, int track_grid, Scalars* gather, hipStream_t s) {
     if (nblk_total) {
-        k_track_rank<<<dim3((unsigned)nblk_total), dim3(256), 0, s>>>(desc, ntraces, nblk_total, ctl);
-        k_track_fill<<<dim3((unsigned)nblk_total), dim3(256), 0, s>>>(desc, ntraces, nblk_total);
+        const unsigned g = (unsigned)(nblk_total < (uint64_t)track_grid ? nblk_total : (uint64_t)track_grid);
+        k_track<<<dim3(g), dim3(256), 0, s>>>(desc, ntraces, nblk_total, ctl);
     }
-    if (total_lines) {
-        const uint64_t blocks = (total_lines + 255) / 256;
-        k_leak_finalize<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(desc, ntraces, total_lines);
-    }
+    const uint64_t items = total_lines > (uint64_t)ntraces * 8 ? total_lines : (uint64_t)ntraces * 8;
+    k_finish<<<dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s>>>(desc, ntraces, total_lines, gather);
     return hipGetLastError();
 }
 

@@ -332,6 +332,78 @@ def test_ten_runs_reuse_busy_slots(sampler):
             compare(g, oracle.run(ev, threshold=kw["threshold"], num_lines=kw["num_lines"]), f"run {r}")
 
 
+def graph_cases():
+    rng = np.random.default_rng(2024)
+    cases = [(f"g tiny{i}", tiny_trace(rng, int(rng.integers(1, 60))), dict(threshold=int(rng.integers(1, 40)),
+                                                                          num_lines=5)) for i in range(6)]
+    for seed, n in ((61, 50_000), (62, 300_000), (63, 1_100_000)):
+        ev, kw = tg.config1(seed=seed, n=n)
+        cases.append((f"g c1 s{seed}", ev, dict(threshold=kw["threshold"], num_lines=kw["num_lines"])))
+    # a slow drift: segments whose chains never collapse
+    drift = next(ev for name, ev, _ in adversarial_cases() if name.startswith("drift"))
+    cases.append(("g drift", drift, dict(threshold=40_000, num_lines=7)))
+    return cases
+
+
+def test_graph_replays_equal_oracle(sampler):
+    """The same batch shape launched five times without timing events
+    between passes: the first launch is plain, the second captures the
+    launch sequence as a HIP graph, the later ones replay it.  Eager torch
+    work and synchronisations run between the replays; every launch's
+    profiles must equal the oracle's, and the start and end events around
+    the graph must time this launch.  A launch that asks for events between
+    passes is plain again, and also exact."""
+    say("graph capture and replays")
+    import torch
+    cases = graph_cases()
+    want = [oracle.run(ev, **kw) for _, ev, kw in cases]
+    before = sampler.launch_stats()
+    x = torch.arange(1 << 20, device="cuda", dtype=torch.int64)
+    try:
+        sampler.set_pass_events(0x40)  # the launch's start event only
+        for rep in range(5):
+            outs = run_batch(sampler, cases)
+            main_ms, total_ms = sampler.last_timing()
+            assert main_ms == -1 and 0 < total_ms < 50, (rep, main_ms, total_ms)
+            for (label, _, _), g, o in zip(cases, outs, want):
+                compare(g, o, f"{label} launch {rep}")
+            # eager work on the device between replays
+            y = (x * 3 + rep).sum()
+            torch.cuda.synchronize()
+            assert int(y) == 3 * ((1 << 20) * ((1 << 20) - 1) // 2) + rep * (1 << 20)
+        mid = sampler.launch_stats()
+        assert mid["captured"] - before["captured"] >= 1, (before, mid)
+        assert mid["replayed"] - before["replayed"] >= 3, (before, mid)
+        sampler.set_pass_events(0x7F)
+        outs = run_batch(sampler, cases)
+        assert sampler.launch_stats()["plain"] == mid["plain"] + 1
+        assert all(v > 0 for v in sampler.last_pass_timing().values())
+        for (label, _, _), g, o in zip(cases, outs, want):
+            compare(g, o, f"{label} with pass events")
+    finally:
+        sampler.set_pass_events(0x7F)
+
+
+@pytest.mark.parametrize("tuning", [dict(chain_cap=1), dict(chain_cap=8, chain_grid=1, emit_grid=1),
+                                    dict(chain_cap=64, chain_grid=3, emit_grid=7, graphs=0),
+                                    dict(chain_cap=48, chain_grid=4096, emit_grid=4096)])
+def test_results_do_not_depend_on_tuning(sampler, tuning):
+    say(f"parity under tuning {tuning}")
+    cases = graph_cases() + multi_tile_cases()[:2]
+    try:
+        sampler.set_tuning(**tuning)
+        got = sampler.get_tuning()
+        for k, v in tuning.items():
+            assert got[k] == v, (k, got)
+        check_batch(sampler, cases)
+    finally:
+        sampler.set_tuning()
+    with pytest.raises(smp.SamplerError):
+        sampler.set_tuning(chain_cap=65)
+    with pytest.raises(smp.SamplerError):
+        sampler.set_tuning(chain_cap=0)
+
+
 def test_budget_admission(sampler):
     say("admission by budget")
     import torch
