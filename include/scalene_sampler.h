@@ -408,6 +408,19 @@ SMP_API int leak_report(const smp_sample_t *samples, uint64_t n_samples, const u
 SMP_API int timeline_points(const smp_sample_t *samples, uint64_t n_samples, uint32_t num_lines,
                             uint32_t max_points, uint8_t *keep);
 
+/* The same timelines by the paper's own procedure (section 5): RDP with an
+ * approximate eps, the line's footprint range over max_points (integer
+ * division), then every log still longer than max_points randomly
+ * downsampled to exactly max_points of its RDP points.  The subset is a
+ * uniform one drawn by selection sampling (Knuth, TAOCP vol. 2, 3.4.2,
+ * Algorithm S): with m of k = max_points chosen, the t-th of the N RDP points
+ * is chosen when floor(x (N - t) / 2^64) < k - m, x the next output of
+ * splitmix64 (Steele, Lea and Flood, 2014) started at state seed + line
+ * (modulo 2^64), so a seed fixes the result.  Arguments and errors as
+ * timeline_points. */
+SMP_API int timeline_points_sampled(const smp_sample_t *samples, uint64_t n_samples, uint32_t num_lines,
+                                    uint32_t max_points, uint64_t seed, uint8_t *keep);
+
 #ifdef __cplusplus
 }
 #endif

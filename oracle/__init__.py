@@ -279,3 +279,60 @@ def timeline_points(samples, num_lines, max_points=100):
         for k in chosen:
             keep[idx[k]] = 1
     return keep
+
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(state):
+    """The splitmix64 generator (Steele, Lea and Flood, 2014): yields its
+    outputs from the given 64-bit state."""
+    while True:
+        state = (state + 0x9E3779B97F4A7C15) & _M64
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+        yield z ^ (z >> 31)
+
+
+def select_uniform(candidates, k, gen):
+    """Selection sampling (Knuth, TAOCP vol. 2, 3.4.2, Algorithm S): a
+    uniform k-subset of candidates, in order.  The t-th of N candidates is
+    taken with probability (k - m) / (N - t), m the number taken so far,
+    drawn as floor(x (N - t) / 2^64) < k - m for x the next output of gen."""
+    n = len(candidates)
+    out = []
+    for t, c in enumerate(candidates):
+        if len(out) == k:
+            break
+        x = next(gen)
+        if (x * (n - t)) >> 64 < k - len(out):
+            out.append(c)
+    return out
+
+
+def timeline_points_sampled(samples, num_lines, max_points=100, seed=0):
+    """Per-line memory timelines by the paper's procedure (section 5): RDP
+    with an approximate eps, the line's footprint range over max_points
+    (integer division), then every log still longer than max_points
+    downsampled at random to exactly max_points of its RDP points (uniform,
+    by selection sampling on splitmix64 started at seed + line).  Returns a
+    keep flag per sample."""
+    lines = [int(v) for v in samples["line"]]
+    xs = [int(v) for v in samples["event_idx"]]
+    ys = [int(v) for v in samples["F"]]
+    by_line = {}
+    for r, l in enumerate(lines):
+        if l < num_lines:
+            by_line.setdefault(l, []).append(r)
+    keep = np.zeros(len(lines), np.uint8)
+    for l, idx in by_line.items():
+        x = [xs[r] for r in idx]
+        y = [ys[r] for r in idx]
+        eps = (max(y) - min(y)) // max_points
+        kept = _rdp_keep(x, y, eps * eps)
+        if len(kept) > max_points:
+            kept = select_uniform(kept, max_points, splitmix64((seed + l) & _M64))
+        for k in kept:
+            keep[idx[k]] = 1
+    return keep

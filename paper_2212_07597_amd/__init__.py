@@ -33,7 +33,7 @@ EXPORTED = ("workspace_bytes", "sampler_create", "submit_trace", "run", "poll", 
             "sampler_set_pass_events", "sampler_last_pass_timing", "sampler_last_counters", "sampler_fixed_bytes",
             "sampler_set_tuning", "sampler_get_tuning", "sampler_launch_stats",
             "sampler_destroy", "error_string", "rate_workspace_bytes", "rate_run", "rate_run_noalloc", "report_lines",
-            "leak_report", "timeline_points")
+            "leak_report", "timeline_points", "timeline_points_sampled")
 
 PASS_NAMES = ("summarize", "resolve", "chain", "scan", "emit")
 
@@ -157,6 +157,9 @@ def lib():
         L.leak_report.restype = i32
         L.timeline_points.argtypes = [vp, u64, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint8)]
         L.timeline_points.restype = i32
+        L.timeline_points_sampled.argtypes = [vp, u64, ctypes.c_uint32, ctypes.c_uint32, u64,
+                                              ctypes.POINTER(ctypes.c_uint8)]
+        L.timeline_points_sampled.restype = i32
         _lib = L
     return _lib
 
@@ -289,6 +292,19 @@ def timeline_points(samples, num_lines, max_points=100):
     _check("timeline_points", lib().timeline_points(smp_.ctypes.data if smp_.size else None, smp_.shape[0],
                                                     int(num_lines), int(max_points),
                                                     keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return keep[: smp_.shape[0]].copy()
+
+
+def timeline_points_sampled(samples, num_lines, max_points=100, seed=0):
+    """Per-line memory timelines by the paper's procedure (section 5): RDP at
+    an approximate eps, then a seeded random downsampling of longer logs to
+    exactly max_points points.  A keep flag per sample."""
+    smp_ = np.ascontiguousarray(samples, dtype=SAMPLE_DTYPE)
+    keep = np.zeros(max(smp_.shape[0], 1), np.uint8)
+    _check("timeline_points_sampled",
+           lib().timeline_points_sampled(smp_.ctypes.data if smp_.size else None, smp_.shape[0], int(num_lines),
+                                         int(max_points), int(seed) & ((1 << 64) - 1),
+                                         keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
     return keep[: smp_.shape[0]].copy()
 
 

@@ -310,3 +310,76 @@ extern "C" SMP_API int timeline_points(const smp_sample_t* samples, uint64_t n_s
     }
     return SMP_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Per-line memory timelines by the paper's own procedure (section 5): RDP
+// with an approximate eps, then a random downsampling of every log that is
+// still longer than max_points to exactly max_points points.  The eps of a
+// line is its footprint range over max_points (integer division).  The
+// downsampling keeps a uniform random subset of the RDP points by selection
+// sampling (Knuth, TAOCP vol. 2, section 3.4.2, Algorithm S): with m of k
+// points chosen, the t-th of the N candidates is chosen when
+// floor(x (N - t) / 2^64) < k - m, x the next output of splitmix64 (Steele,
+// Lea and Flood, 2014) whose state starts at seed + line, modulo 2^64.
+
+namespace {
+
+uint64_t splitmix64_next(uint64_t& state) {
+    uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" SMP_API int timeline_points_sampled(const smp_sample_t* samples, uint64_t n_samples, uint32_t num_lines,
+                                               uint32_t max_points, uint64_t seed, uint8_t* keep) {
+    if (max_points < 2 || (n_samples && (!samples || !keep)) || n_samples >= (1ull << 32)) return SMP_EINVAL;
+    for (uint64_t r = 0; r < n_samples; ++r) keep[r] = 0;
+    if (!n_samples || !num_lines) return SMP_OK;
+    std::vector<uint32_t> start((size_t)num_lines + 1, 0), order(n_samples);
+    for (uint64_t r = 0; r < n_samples; ++r)
+        if (samples[r].line < num_lines) ++start[samples[r].line + 1];
+    for (uint32_t l = 0; l < num_lines; ++l) start[l + 1] += start[l];
+    std::vector<uint32_t> fill(start.begin(), start.end() - 1);
+    for (uint64_t r = 0; r < n_samples; ++r)
+        if (samples[r].line < num_lines) order[fill[samples[r].line]++] = (uint32_t)r;
+    std::vector<uint32_t> xs;
+    std::vector<int64_t> ys;
+    std::vector<uint8_t> mark;
+    std::vector<Run> stack;
+    for (uint32_t l = 0; l < num_lines; ++l) {
+        const uint32_t b = start[l], n = start[l + 1] - b;
+        if (!n) continue;
+        xs.resize(n);
+        ys.resize(n);
+        int64_t ymin = samples[order[b]].F, ymax = ymin;
+        for (uint32_t k = 0; k < n; ++k) {
+            xs[k] = samples[order[b + k]].event_idx;
+            ys[k] = samples[order[b + k]].F;
+            ymin = ys[k] < ymin ? ys[k] : ymin;
+            ymax = ys[k] > ymax ? ys[k] : ymax;
+        }
+        const uint64_t eps = (uint64_t)((unsigned __int128)((__int128)ymax - ymin) / max_points);
+        mark.assign(n, 0);
+        const uint64_t kept = rdp(xs.data(), ys.data(), n, eps, mark.data(), stack);
+        if (kept > max_points) {
+            uint64_t state = seed + l, chosen = 0, t = 0;
+            for (uint32_t k = 0; k < n; ++k) {
+                if (!mark[k]) continue;
+                bool take = false;
+                if (chosen < max_points) {
+                    const uint64_t x = splitmix64_next(state);
+                    take = (uint64_t)(((unsigned __int128)x * (kept - t)) >> 64) < max_points - chosen;
+                }
+                ++t;
+                if (take) ++chosen;
+                else mark[k] = 0;
+            }
+        }
+        for (uint32_t k = 0; k < n; ++k)
+            if (mark[k]) keep[order[b + k]] = 1;
+    }
+    return SMP_OK;
+}

@@ -191,3 +191,28 @@ def test_rate_noalloc_refuses_sizes_over_its_scratch_on_the_host():
     # the header's maximum and the binding's agree
     src = open(HEADER).read()
     assert "#define SMP_RATE_NOALLOC_MAX_EVENTS (1ull << 29)" in src and smp.RATE_NOALLOC_MAX_EVENTS == 1 << 29
+
+
+def test_timeline_points_sampled_matches_oracle():
+    """The library's RDP-plus-downsampling timelines against the oracle's:
+    random walks on several lines, limits small enough that the random step
+    applies, several seeds, magnitudes up to event indices near 2^32 and
+    footprints near 2^60."""
+    import oracle
+
+    rng = np.random.default_rng(5)
+    for case in range(40):
+        n = int(rng.integers(0, 600))
+        L = int(rng.integers(1, 6))
+        s = np.zeros(n, smp.SAMPLE_DTYPE)
+        s["event_idx"] = np.sort(rng.integers(0, 1 << (32 if case % 3 == 0 else 20), n))
+        scale = 1 << (60 if case % 4 == 0 else 20)
+        s["F"] = np.clip(np.cumsum(rng.integers(-scale // 64, scale // 64, n)), -(1 << 60), 1 << 60)
+        s["line"] = rng.integers(0, L + 1, n)  # line L is out of range
+        maxp = int(rng.choice([2, 3, 10, 100]))
+        seed = int(rng.integers(0, 1 << 63))
+        got = smp.timeline_points_sampled(s, L, maxp, seed)
+        want = oracle.timeline_points_sampled(s, L, maxp, seed)
+        assert got.tolist() == want.tolist(), case
+        for line in range(L):
+            assert got[s["line"] == line].sum() <= maxp

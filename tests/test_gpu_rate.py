@@ -196,3 +196,11 @@ def test_timelines_on_a_gpu_profile():
     assert got.tolist() == want.tolist()
     per_line = np.bincount(s["line"][got == 1], minlength=kw["num_lines"])
     assert per_line.max() <= 100 and got.sum() > 0
+    # the paper's own procedure: RDP at an approximate eps, then seeded
+    # downsampling of longer logs to exactly 100 points
+    for seed in (0, 77):
+        got = smp.timeline_points_sampled(s, kw["num_lines"], 100, seed)
+        want = oracle.timeline_points_sampled(s, kw["num_lines"], 100, seed)
+        assert got.tolist() == want.tolist(), seed
+        per_line = np.bincount(s["line"][got == 1], minlength=kw["num_lines"])
+        assert per_line.max() <= 100 and got.sum() > 0

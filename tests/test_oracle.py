@@ -700,3 +700,68 @@ def test_timeline_bound_and_minimal_eps(seed):
     if prev is not None:
         assert len(oracle._rdp_keep(xi, yi, prev * prev)) > 100
     assert kept == _float_rdp(np.array(x, float), np.array(y, float), float(eps))
+
+
+# ------------------------------------- timelines, the paper's procedure (5) --
+
+def test_splitmix64_matches_its_published_outputs():
+    """The first outputs of splitmix64 from state 0, as published with the
+    generator, and the input generator's own implementation (written
+    separately) for other states."""
+    import tracegen as tg
+    g = oracle.splitmix64(0)
+    assert [next(g) for _ in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    for s in (1, 12345, (1 << 64) - 1, 0x9E3779B97F4A7C15):
+        assert next(oracle.splitmix64(s)) == tg.lib().tg_splitmix64(s)
+
+
+def test_selection_sampling_is_uniform():
+    """Algorithm S takes exactly k of N candidates, in order, and every
+    k-subset is equally likely: over 20,000 seeds each of the 10 subsets of
+    2 out of 5 appears 2,000 times give or take ~42 (one standard
+    deviation); a bias of a few per cent in any draw would show."""
+    from collections import Counter
+    counts = Counter()
+    for seed in range(20_000):
+        sel = oracle.select_uniform(list(range(5)), 2, oracle.splitmix64(seed))
+        assert len(sel) == 2 and sel == sorted(sel)
+        counts[tuple(sel)] += 1
+    assert len(counts) == 10
+    assert all(abs(c - 2000) < 250 for c in counts.values()), counts
+    assert oracle.select_uniform(list(range(7)), 7, oracle.splitmix64(3)) == list(range(7))
+    assert oracle.select_uniform(list(range(7)), 0, oracle.splitmix64(3)) == []
+
+
+def test_timeline_points_sampled_follows_the_paper():
+    """Section 5: RDP with an approximate eps, then logs still longer than
+    the limit downsampled at random to exactly the limit."""
+    def samples(points):
+        s = np.zeros(len(points), oracle.SAMPLE_DTYPE)
+        for i, (line, x, y) in enumerate(points):
+            s[i] = (x, line, y, 0, 0)
+        return s
+    # a zigzag of 40 points 1000 apart with range 1000 and a limit of 10:
+    # eps = 100; every corner lies ~1000 from its chord, so RDP keeps all 40
+    # and the random step keeps exactly 10 of them, chosen by the seed
+    zig = [(0, 1000 * i, 1000 if i % 2 else 0) for i in range(40)]
+    k1 = oracle.timeline_points_sampled(samples(zig), 1, max_points=10, seed=1)
+    k2 = oracle.timeline_points_sampled(samples(zig), 1, max_points=10, seed=2)
+    assert k1.sum() == 10 and k2.sum() == 10 and not np.array_equal(k1, k2)
+    # a straight ramp: RDP keeps the two ends only, the random step never
+    # applies and the seed does not matter
+    ramp = [(0, 1000 * i, 5000 * i) for i in range(40)]
+    for seed in range(3):
+        assert np.flatnonzero(oracle.timeline_points_sampled(samples(ramp), 1, 10, seed)).tolist() == [0, 39]
+    # eps = range // limit: points (0,0) (1000,b) (2000,0) (3000,0) (4000,100)
+    # have range 100, so eps = 10 with a limit of 10.  The chord of the whole
+    # run puts (3000,0) farthest (kept); on the chord (0,0)-(3000,0) the point
+    # (1000,b) lies exactly b away: kept only when b > 10 (strict), and then
+    # (2000,0) lies 5.5 from its new chord and is dropped.
+    for b, want in ((10, [0, 3, 4]), (11, [0, 1, 3, 4])):
+        pts = [(0, 0, 0), (0, 1000, b), (0, 2000, 0), (0, 3000, 0), (0, 4000, 100)]
+        assert np.flatnonzero(oracle.timeline_points_sampled(samples(pts), 1, 10, 0)).tolist() == want, b
+    # lines are separate: line 0 is downsampled, line 1 keeps its RDP points
+    # (a short zigzag: every point kept, 5 <= 10), line 2 is out of range
+    mix = zig + [(1, 1000 * i, 1000 if i % 2 else 0) for i in range(5)] + [(2, 5, 5)]
+    k = oracle.timeline_points_sampled(samples(mix), 2, max_points=10, seed=9)
+    assert k[:40].sum() == 10 and k[40:45].tolist() == [1] * 5 and k[45] == 0
