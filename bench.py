@@ -164,6 +164,7 @@ def main():
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--served-rates", default="200,1000,5000", help="arrival rates (requests/s) of the served run")
     ap.add_argument("--served-no-plain", action="store_true", help="skip the one-launch-per-request comparison")
+    ap.add_argument("--batched-no-plain", action="store_true", help="skip the one-launch-per-trace comparison")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -184,7 +185,7 @@ def main():
         if args.only == "config5":
             out = bench_config5(smp, tg, torch, np, cpu=cpu, tune=tuner(args))
         elif args.only == "batched":
-            out = bench_batched(smp, tg, torch, np, cpu=cpu, tune=tuner(args))
+            out = bench_batched(smp, tg, torch, np, cpu=cpu, tune=tuner(args), plain_compare=not args.batched_no_plain)
         else:
             out = bench_served(smp, tg, torch, np, args.served_requests, served_rates(args), not args.served_no_plain)
         print(json.dumps(out), flush=True)
@@ -481,7 +482,7 @@ def bench_config5(smp, tg, torch, np, steps=3, cpu=True, tune=None):
             "roofline": roof, "tuning": tuned, "cpu_baseline": cpu_base}
 
 
-def bench_batched(smp, tg, torch, np, steps=3, cpu=True, tune=None):
+def bench_batched(smp, tg, torch, np, steps=3, cpu=True, tune=None, plain_compare=True):
     """Config 3: 1024 traces (log-uniform 1e3-1e6 events, T from {256 KiB,
     1 MiB, 10 MiB}) in one launch, against a loop of one launch per trace;
     and, beside it, the oracle over the same traces on one pinned core and
@@ -541,11 +542,13 @@ def bench_batched(smp, tg, torch, np, steps=3, cpu=True, tune=None):
     tb = (time.perf_counter() - t0) / steps
     s.set_pass_events(0x7F)
     s_stats = s.launch_stats()
-    plain()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain()
-    tp = time.perf_counter() - t0
+    tp = None
+    if plain_compare:
+        plain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain()
+        tp = time.perf_counter() - t0
     s.close()
     del devs
     torch.cuda.empty_cache()
@@ -597,8 +600,8 @@ def bench_batched(smp, tg, torch, np, steps=3, cpu=True, tune=None):
                                                         "launch_sequence_gpu"))},
             "batched_pass_ms": {k: round(v, 4) for k, v in passes.items()},
             "roofline": roof, "tuning": tuned, "launches": s_stats,
-            "plain_events_per_s": round(total / tp, 1), "plain_ms": round(tp * 1e3, 3),
-            "speedup_vs_plain": round(tp / tb, 2)}
+            "plain_events_per_s": round(total / tp, 1) if tp else None, "plain_ms": round(tp * 1e3, 3) if tp else None,
+            "speedup_vs_plain": round(tp / tb, 2) if tp else None}
 
 
 def served_rates(args):

@@ -976,18 +976,29 @@ __device__ __forceinline__ int64_t walk_prefixes(const int64_t* F, int64_t T, in
     return cr.ref - fend;
 }
 
-// The same from the kept prefixes in HBM (all windows loaded at once).
-__device__ __forceinline__ int64_t walk_kept(const Desc& D, int64_t j, int64_t T, int64_t x) {
+// The kept prefixes of segment j into registers (the loads are issued here;
+// the first use of f waits for them).
+__device__ __forceinline__ void load_kept(const Desc& D, int64_t j, int64_t (&f)[NW]) {
     const int l = lane_id();
     const SMP_GLOBAL int64_t* F = kept_prefixes(D, j);
-    int64_t f[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) f[w] = F[w * 64 + l];
+}
+
+// Exit offset from entry offset x, following prefixes held in registers.
+__device__ __forceinline__ int64_t walk_regs(const int64_t (&f)[NW], int64_t T, int64_t x) {
     int64_t lsp = 0;
     ChainRun cr{x, 0, 0, -1, INT64_MIN, -1, 0};
 #pragma unroll
     for (int w = 0; w < NW; ++w) chain_window<false>(f[w], 0, T, cr, lsp, w, -1);
     return cr.ref - readlane64(f[NW - 1], 63);
+}
+
+// The same from the kept prefixes in HBM (all windows loaded at once).
+__device__ __forceinline__ int64_t walk_kept(const Desc& D, int64_t j, int64_t T, int64_t x) {
+    int64_t f[NW];
+    load_kept(D, j, f);
+    return walk_regs(f, T, x);
 }
 
 // Index of the r-th set bit (r < popcount(m)).
@@ -1123,17 +1134,13 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
         // ---- the walker ----
         int q = 0;  // SIM segments passed, in walk order
         bool ok = true;
-        // Follow the chain through segments [b, e) of the tile from entry
-        // offset x and return the exit.  64 segments at a time, one per lane,
-        // with S the group's exclusive sums of af.  A segment with a total
-        // map always exits at kf; after the last such segment j before lane
-        // i the entry of i is kf_j - (S_i - S_j - af_j), and before any, from
-        // a position i0 with entry x, it is x - (S_i - S_i0) -- as long as no
-        // other segment in between changes the chain.  So one ballot finds
-        // the next segment whose entry lies outside its no-sample interval
-        // [lo, hi], and only that one needs work (its constant exit, or a
-        // walk through its pre-scanned prefixes).  Modular arithmetic: exact
-        // wherever the entry is in (-T, T), as it is up to that segment.
+        // Sparse tiles: the kept prefixes of the predicted next stop, loaded
+        // into pf while the current stop is resolved (pf_lane: its tile lane,
+        // -1 if none).  At a stop they are written to ring slot 0 (unused in
+        // sparse tiles; the write waits only for loads the stop needs) and
+        // the registers take the next prediction's loads at once.
+        int64_t pf[NW];
+        int pf_lane = -1;
         auto walk = [&](int b, int e, int64_t x) -> int64_t {
             for (int g0 = b & ~63; g0 < e && ok; g0 += 64) {
                 const int i = g0 + l;
@@ -1157,16 +1164,83 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                     q += __popcll(sim & range_mask(0, i0, stop));
                     // release the slots passed over before any wait below (a
                     // producer may be waiting for them); every lane stores the
-                    // same value (no lane-0-only region inside the loop)
-                    __hip_atomic_store(&s_cons, q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    // same value (no lane-0-only region inside the loop).  A
+                    // sparse tile has no producers, and the release would wait
+                    // for every load in flight (the prefetch of the next stop).
+                    if (!sparse) __hip_atomic_store(&s_cons, q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                     if (stop > i0) x = readlane64(xo, stop - 1);
                     if (stop < ge) {
                         const int64_t xs = readlane64(xi, stop);
                         int64_t r = readlane64(kf, stop);
-                        if ((sim >> stop) & 1) {
+                        if ((sim >> stop) & 1 && sparse) {
+                            // The exit lies in [xs + T, max] - af for an
+                            // entry below lo (one sample at the first node
+                            // reaching xs + T; more only where the segment
+                            // moves T or more), in [min, xs - T] - af above hi
+                            // (max = lo + T - 1, min = hi - T + 1).  The next
+                            // stop is predicted as the first later segment
+                            // whose no-sample interval does not hold that
+                            // whole range, shifted by the footprint changes in
+                            // between (this group, else the next one).  A
+                            // prediction only decides what is loaded early.
+                            const int64_t lo_c = readlane64(lo, stop), hi_c = readlane64(hi, stop);
+                            const int64_t af_c = readlane64(af, stop);
+                            uint64_t A, B;
+                            if (xs < lo_c) {
+                                A = (uint64_t)xs + (uint64_t)T - (uint64_t)af_c;
+                                B = (uint64_t)lo_c + (uint64_t)(T - 1) - (uint64_t)af_c;
+                            } else {
+                                A = (uint64_t)hi_c - (uint64_t)(T - 1) - (uint64_t)af_c;
+                                B = (uint64_t)xs - (uint64_t)T - (uint64_t)af_c;
+                            }
+                            const uint64_t base = (uint64_t)readlane64(S, stop) + (uint64_t)af_c;
+                            int p = -1;
+                            {
+                                const uint64_t d = (uint64_t)S - base;
+                                const bool cand = l > stop && l < ge &&
+                                                  (is_tot || !((int64_t)(A - d) >= lo && (int64_t)(B - d) <= hi));
+                                const uint64_t cm = ballot(cand);
+                                if (cm) {
+                                    const int pl = ctz64(cm);
+                                    if ((sim >> pl) & 1) p = g0 + pl;
+                                } else if (g0 + 64 < e) {
+                                    const int i2 = g0 + 64 + l;
+                                    const bool v2 = i2 < e;
+                                    const int64_t lo2 = m_lo[v2 ? i2 : 0], hi2 = m_hi[v2 ? i2 : 0];
+                                    const int64_t af2 = v2 ? m_af[i2] : 0;
+                                    const uint64_t tot2 = w_tot[(g0 >> 6) + 1], sim2 = w_sim[(g0 >> 6) + 1];
+                                    const uint64_t d2 = (uint64_t)readlane64(S, 63) + (uint64_t)readlane64(af, 63) - base +
+                                                        ((uint64_t)wave_incl_sum(af2) - (uint64_t)af2);
+                                    const bool cand2 = v2 && (((tot2 >> l) & 1) ||
+                                                              !((int64_t)(A - d2) >= lo2 && (int64_t)(B - d2) <= hi2));
+                                    const uint64_t cm2 = ballot(cand2);
+                                    if (cm2 && ((sim2 >> ctz64(cm2)) & 1)) p = g0 + 64 + ctz64(cm2);
+                                }
+                            }
+                            // pf is defined once per stop (the compiler would
+                            // otherwise copy it between registers, and a copy
+                            // waits for the loads in flight): a miss loads
+                            // into a temporary, and the next prefetch is
+                            // always issued (of this segment again when there
+                            // is no prediction)
+                            const int c = g0 + stop;
+                            if (pf_lane == c) {
+#pragma unroll
+                                for (int w = 0; w < NW; ++w) ring[0][w * 64 + l] = pf[w];
+                            } else {
+                                int64_t tmp[NW];
+                                load_kept(D, k * TILE + c, tmp);
+#pragma unroll
+                                for (int w = 0; w < NW; ++w) ring[0][w * 64 + l] = tmp[w];
+                            }
+                            pf_lane = p;
+                            load_kept(D, k * TILE + (p >= 0 ? p : c), pf);
+                            r = walk_prefixes(ring[0], T, xs);
+                            ++q;
+                        } else if ((sim >> stop) & 1) {
                             const int slot = q % RING;
-                            if (sparse || (kept && __hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE,
-                                                                     __HIP_MEMORY_SCOPE_WORKGROUP) != q)) {
+                            if (kept && __hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE,
+                                                          __HIP_MEMORY_SCOPE_WORKGROUP) != q) {
                                 // its producer is behind: read the kept prefixes instead of waiting
                                 r = walk_kept(D, k * TILE + g0 + stop, T, xs);
                             } else {
