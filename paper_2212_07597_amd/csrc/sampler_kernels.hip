@@ -994,6 +994,23 @@ __device__ __forceinline__ int64_t walk_regs(const int64_t (&f)[NW], int64_t T, 
     return cr.ref - readlane64(f[NW - 1], 63);
 }
 
+// Exit offset from entry offset x of a segment that moves less than T (its
+// prefixes f in registers) when x lies outside its no-sample interval: the
+// chain samples once, at the first node at least T above x (x below the
+// interval) or at least T below it (above), and never again in the segment.
+// The eight windows are tested at once, not one after another.
+__device__ __forceinline__ int64_t exit_one_sample(const int64_t (&f)[NW], int64_t T, int64_t x, bool up) {
+    const int64_t thr = up ? x + T : x - T;
+    uint64_t m[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) m[w] = ballot(up ? f[w] >= thr : f[w] <= thr);
+    int64_t fu = x;  // (unreachable for a stop: some node crosses)
+#pragma unroll
+    for (int w = NW - 1; w >= 0; --w)
+        if (m[w]) fu = readlane64(f[w], ctz64(m[w]));
+    return fu - readlane64(f[NW - 1], 63);
+}
+
 // The same from the kept prefixes in HBM (all windows loaded at once).
 __device__ __forceinline__ int64_t walk_kept(const Desc& D, int64_t j, int64_t T, int64_t x) {
     int64_t f[NW];
@@ -1223,19 +1240,33 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                             // into a temporary, and the next prefetch is
                             // always issued (of this segment again when there
                             // is no prediction)
+                            // A segment that moves less than T samples once
+                            // (hi - lo >= T - 1 implies max - min < T): its
+                            // exit comes straight from the registers.  Others
+                            // are walked from ring slot 0.
                             const int c = g0 + stop;
+                            const bool one = (uint64_t)hi_c - (uint64_t)lo_c >= (uint64_t)(T - 1) && hi_c >= lo_c;
+                            const bool up = xs < lo_c;
                             if (pf_lane == c) {
+                                if (one) {
+                                    r = exit_one_sample(pf, T, xs, up);
+                                } else {
 #pragma unroll
-                                for (int w = 0; w < NW; ++w) ring[0][w * 64 + l] = pf[w];
+                                    for (int w = 0; w < NW; ++w) ring[0][w * 64 + l] = pf[w];
+                                }
                             } else {
                                 int64_t tmp[NW];
                                 load_kept(D, k * TILE + c, tmp);
+                                if (one) {
+                                    r = exit_one_sample(tmp, T, xs, up);
+                                } else {
 #pragma unroll
-                                for (int w = 0; w < NW; ++w) ring[0][w * 64 + l] = tmp[w];
+                                    for (int w = 0; w < NW; ++w) ring[0][w * 64 + l] = tmp[w];
+                                }
                             }
                             pf_lane = p;
                             load_kept(D, k * TILE + (p >= 0 ? p : c), pf);
-                            r = walk_prefixes(ring[0], T, xs);
+                            if (!one) r = walk_prefixes(ring[0], T, xs);
                             ++q;
                         } else if ((sim >> stop) & 1) {
                             const int slot = q % RING;
