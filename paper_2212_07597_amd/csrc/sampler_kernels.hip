@@ -1000,10 +1000,16 @@ __device__ __forceinline__ int64_t walk_regs(const int64_t (&f)[NW], int64_t T, 
 // interval) or at least T below it (above), and never again in the segment.
 // The eight windows are tested at once, not one after another.
 __device__ __forceinline__ int64_t exit_one_sample(const int64_t (&f)[NW], int64_t T, int64_t x, bool up) {
-    const int64_t thr = up ? x + T : x - T;
     uint64_t m[NW];
+    if (up) {  // (wave-uniform: one set of compares, not both and a select)
+        const int64_t thr = x + T;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) m[w] = ballot(up ? f[w] >= thr : f[w] <= thr);
+        for (int w = 0; w < NW; ++w) m[w] = ballot(f[w] >= thr);
+    } else {
+        const int64_t thr = x - T;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) m[w] = ballot(f[w] <= thr);
+    }
     int64_t fu = x;  // (unreachable for a stop: some node crosses)
 #pragma unroll
     for (int w = NW - 1; w >= 0; --w)
