@@ -230,6 +230,61 @@ __device__ __forceinline__ int64_t wave_incl_sum(int64_t x) {
         : "vcc");
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
+// Two (three) inclusive 64-bit sums at once, their DPP steps interleaved: the
+// other scans' instructions between two steps of one scan give the DPP read
+// its wait states, so only the first step needs an s_nop.
+__device__ __forceinline__ void wave_incl_sum2(int64_t& a, int64_t& b) {
+    uint32_t alo = (uint32_t)(uint64_t)a, ahi = (uint32_t)((uint64_t)a >> 32);
+    uint32_t blo = (uint32_t)(uint64_t)b, bhi = (uint32_t)((uint64_t)b >> 32);
+#define SMP_SUM2_STEP(CTRL)                                                    \
+    "v_add_co_u32_dpp %0, vcc, %0, %0 " CTRL "\n\t"                              \
+    "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc " CTRL "\n\t"                        \
+    "v_add_co_u32_dpp %2, vcc, %2, %2 " CTRL "\n\t"                              \
+    "v_addc_co_u32_dpp %3, vcc, %3, %3, vcc " CTRL "\n\t"
+    asm volatile(
+        "s_nop 1\n\t"
+        SMP_SUM2_STEP("row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:0")
+        SMP_SUM2_STEP("row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:0")
+        SMP_SUM2_STEP("row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:0")
+        SMP_SUM2_STEP("row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:0")
+        SMP_SUM2_STEP("row_bcast:15 row_mask:0xa bank_mask:0xf")
+        SMP_SUM2_STEP("row_bcast:31 row_mask:0xc bank_mask:0xf")
+        "s_nop 1\n\t"
+        : "+v"(alo), "+v"(ahi), "+v"(blo), "+v"(bhi)
+        :
+        : "vcc");
+#undef SMP_SUM2_STEP
+    a = (int64_t)(((uint64_t)ahi << 32) | alo);
+    b = (int64_t)(((uint64_t)bhi << 32) | blo);
+}
+__device__ __forceinline__ void wave_incl_sum3(int64_t& a, int64_t& b, int64_t& c) {
+    uint32_t alo = (uint32_t)(uint64_t)a, ahi = (uint32_t)((uint64_t)a >> 32);
+    uint32_t blo = (uint32_t)(uint64_t)b, bhi = (uint32_t)((uint64_t)b >> 32);
+    uint32_t clo = (uint32_t)(uint64_t)c, chi = (uint32_t)((uint64_t)c >> 32);
+#define SMP_SUM3_STEP(CTRL)                                                    \
+    "v_add_co_u32_dpp %0, vcc, %0, %0 " CTRL "\n\t"                              \
+    "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc " CTRL "\n\t"                        \
+    "v_add_co_u32_dpp %2, vcc, %2, %2 " CTRL "\n\t"                              \
+    "v_addc_co_u32_dpp %3, vcc, %3, %3, vcc " CTRL "\n\t"                        \
+    "v_add_co_u32_dpp %4, vcc, %4, %4 " CTRL "\n\t"                              \
+    "v_addc_co_u32_dpp %5, vcc, %5, %5, vcc " CTRL "\n\t"
+    asm volatile(
+        "s_nop 1\n\t"
+        SMP_SUM3_STEP("row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:0")
+        SMP_SUM3_STEP("row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:0")
+        SMP_SUM3_STEP("row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:0")
+        SMP_SUM3_STEP("row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:0")
+        SMP_SUM3_STEP("row_bcast:15 row_mask:0xa bank_mask:0xf")
+        SMP_SUM3_STEP("row_bcast:31 row_mask:0xc bank_mask:0xf")
+        "s_nop 1\n\t"
+        : "+v"(alo), "+v"(ahi), "+v"(blo), "+v"(bhi), "+v"(clo), "+v"(chi)
+        :
+        : "vcc");
+#undef SMP_SUM3_STEP
+    a = (int64_t)(((uint64_t)ahi << 32) | alo);
+    b = (int64_t)(((uint64_t)bhi << 32) | blo);
+    c = (int64_t)(((uint64_t)chi << 32) | clo);
+}
 __device__ __forceinline__ int64_t wave_incl_max(int64_t x) { return wave_scan<OpMax>(x); }
 __device__ __forceinline__ int64_t wave_incl_min(int64_t x) { return wave_scan<OpMin>(x); }
 

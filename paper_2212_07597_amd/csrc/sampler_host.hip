@@ -35,7 +35,7 @@ namespace {
 constexpr uint64_t ALIGN = 256;
 constexpr int RUN_SLOTS = 8;
 constexpr int MAX_TRACES_PER_RUN = 4096;
-constexpr uint64_t CBLK_WORDS = 1024;
+constexpr uint64_t CBLK_WORDS = 256;
 constexpr int NPASS = 5;  // summarize, resolve, chain, scan, emit
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }

@@ -566,7 +566,8 @@ __device__ bool scan_sums(const StatusView& sv, int64_t g, int64_t& oF, int64_t&
         const int64_t vP = (need || at) ? unpack(x1) : 0;
         const int64_t vC = (need || at) ? unpack(x2) : 0;
         // suffix sums toward older tiles: S_l = sum over lanes >= l
-        const int64_t xF = wave_incl_sum(vF), xP = wave_incl_sum(vP), xC = wave_incl_sum(vC);
+        int64_t xF = vF, xP = vP, xC = vC;
+        wave_incl_sum3(xF, xP, xC);
         const int64_t tF = readlane64(xF, 63), tP = readlane64(xP, 63), tC = readlane64(xC, 63);
         if (first && im && need) {
             st_status(sv.at(W_IF, js), pack(tF - xF + vF, 1));
@@ -801,8 +802,10 @@ __device__ __forceinline__ void summarize_segment(const Desc& D, uint64_t g, int
         }
         // forced: |dm| >= 2T - 1, as one unsigned compare (as in crossing)
         const uint64_t fm = ballot((uint64_t)e.dm + (uint64_t)(two_t - 1) >= (uint64_t)(2 * two_t - 1));
-        const int64_t f = wave_incl_sum(e.dm) + cF;
-        const int64_t p = wave_incl_sum(e.dp) + cP;
+        int64_t f = e.dm, p = e.dp;
+        wave_incl_sum2(f, p);
+        f += cF;
+        p += cP;
         cF = readlane64(f, 63);
         cP = readlane64(p, 63);
         lF_[k] = f;
@@ -1103,7 +1106,8 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     m_ex[tid] = kf;  // final for total maps; the walker overwrites the others
     const uint64_t tot = ballot(valid && kind == MAP_TOTAL), sim = ballot(valid && kind == MAP_SIM);
     // sums inside the wave
-    const int64_t iF = wave_incl_sum(af), iP = wave_incl_sum(ap), iC = wave_incl_sum(ac);
+    int64_t iF = af, iP = ap, iC = ac;
+    wave_incl_sum3(iF, iP, iC);
     if (l == 63) {
         w_sum[0][wv] = iF;
         w_sum[1][wv] = iP;
@@ -1628,8 +1632,10 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
                 const uint64_t rdw = w < HEAD_W ? cur.d[w] : rd[w - HEAD_W];
                 const int64_t dm = (k < nlim && (fl & 6u) == 0) ? (int64_t)rdw : 0;
                 const int64_t dp = (fl & 1u) ? 0 : dm;
-                const int64_t f = wave_incl_sum(dm) + cF;
-                const int64_t p = wave_incl_sum(dp) + cP;
+                int64_t f = dm, p = dp;
+                wave_incl_sum2(f, p);
+                f += cF;
+                p += cP;
                 cF = readlane64(f, 63);
                 cP = readlane64(p, 63);
                 chain_window<true>(f, p, T, cr, lsp, w, -1);
@@ -1982,8 +1988,10 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, cons
         const uint32_t fl = in.fw[w];
         const int64_t dm = (k < nv && (fl & 6u) == 0) ? (int64_t)(((uint64_t)in.q[w].y << 32) | in.q[w].x) : 0;
         const int64_t dp = (fl & 1u) ? 0 : dm;
-        const int64_t f = wave_incl_sum(dm) + cF;
-        const int64_t p = wave_incl_sum(dp) + cP;
+        int64_t f = dm, p = dp;
+        wave_incl_sum2(f, p);
+        f += cF;
+        p += cP;
         cF = readlane64(f, 63);
         cP = readlane64(p, 63);
         const uint64_t fm = ballot(dm < 0);
@@ -2152,7 +2160,8 @@ __global__ void k_clear(const Desc* __restrict__ desc, int ntraces, uint64_t tot
 
 // ------------------------------------------------ tracked-list compaction
 
-constexpr int CBLK_WORDS = 1024;   // bitmap words per compaction block
+constexpr int CBLK_WORDS = 256;    // bitmap words per compaction block (one per thread)
+constexpr int TRACK_UNROLL = 4;    // tracked entries per thread and trip of the fill
 
 __device__ __forceinline__ int find_trace_blk(const Desc* desc, int ntraces, uint64_t x) {
     int lo = 0, hi = ntraces - 1;
@@ -2275,18 +2284,41 @@ __global__ __launch_bounds__(256) void k_track(const Desc* __restrict__ desc, in
             }
         }
         __syncthreads();
-        for (uint64_t hh = h0 + tid; hh < h1; hh += 256) {
-            const uint32_t r = tq[4 * hh];
-            if (r >= K) continue;
-            const Sample smp_ = load_sample(D.samples + r);
-            const uint32_t freed = smp_.event_idx < D.n
-                                       ? (uint32_t)((gp(D.freed_bits)[smp_.event_idx >> 6] >> (smp_.event_idx & 63)) & 1)
-                                       : 0u;
-            tq[4 * hh] = smp_.event_idx;
-            tq[4 * hh + 1] = smp_.line;
-            tq[4 * hh + 2] = gp(D.sample_ptr)[r];
-            tq[4 * hh + 3] = freed;
-            if (smp_.line < D.L) hist_add(hc, D, t, smp_.line, C_LM, 1, C_LF, (int64_t)freed, -1, 0, -1, 0);
+        // TRACK_UNROLL entries per thread and trip, each step's loads issued
+        // for all of them before the first is used: a block may hold many
+        // thousands of entries, and one at a time its three dependent loads
+        // (rank, sample, freed bit) would each cost a full round trip.
+        for (uint64_t hb = h0 + tid; hb < h1; hb += 256 * TRACK_UNROLL) {
+            uint32_t r[TRACK_UNROLL], ptr[TRACK_UNROLL];
+            uint64_t sw[TRACK_UNROLL], fw[TRACK_UNROLL];
+#pragma unroll
+            for (int u = 0; u < TRACK_UNROLL; ++u) {
+                const uint64_t hh = hb + 256 * (uint64_t)u;
+                r[u] = hh < h1 ? tq[4 * hh] : 0xFFFFFFFFu;
+            }
+#pragma unroll
+            for (int u = 0; u < TRACK_UNROLL; ++u) {
+                const uint32_t rr = r[u] < K ? r[u] : 0u;
+                sw[u] = *(const SMP_GLOBAL uint64_t*)(D.samples + rr);  // event index, line
+                ptr[u] = gp(D.sample_ptr)[rr];
+            }
+#pragma unroll
+            for (int u = 0; u < TRACK_UNROLL; ++u) {
+                const uint32_t ev = (uint32_t)sw[u];
+                fw[u] = r[u] < K && ev < D.n ? gp(D.freed_bits)[ev >> 6] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < TRACK_UNROLL; ++u) {
+                if (r[u] >= K) continue;  // (past the block's entries, or after an internal fault)
+                const uint64_t hh = hb + 256 * (uint64_t)u;
+                const uint32_t ev = (uint32_t)sw[u], line = (uint32_t)(sw[u] >> 32);
+                const uint32_t freed = (uint32_t)((fw[u] >> (ev & 63)) & 1);
+                tq[4 * hh] = ev;
+                tq[4 * hh + 1] = line;
+                tq[4 * hh + 2] = ptr[u];
+                tq[4 * hh + 3] = freed;
+                if (line < D.L) hist_add(hc, D, t, line, C_LM, 1, C_LF, (int64_t)freed, -1, 0, -1, 0);
+            }
         }
         __syncthreads();  // w_cnt and s_excl are reused by the next block
     }
