@@ -170,8 +170,10 @@ struct RunSlot {
     Desc* dev_desc = nullptr;
     Desc* last_desc = nullptr;   // what dev_desc holds (host copy), to skip an unchanged upload
     size_t last_cnt = 0;
-    Scalars* dev_scal = nullptr;   // every trace's scalars, gathered after the launch
-    Scalars* host_scal = nullptr;  // pinned copy of dev_scal
+    // every trace's scalars, gathered by the last kernel of the launch straight
+    // into pinned, coherent host memory (no copy in the launch sequence)
+    Scalars* host_scal = nullptr;
+    Scalars* host_scal_dev = nullptr;  // its device address
     std::vector<uint64_t> ids;     // the launch's traces, in descriptor order
     unsigned long long* dev_ticket = nullptr;
     hipStream_t stream = nullptr;  // launches of this slot; ordered after the caller's stream
@@ -217,10 +219,7 @@ struct smp_sampler {
 namespace {
 
 // Per run slot: descriptors, 32 control words, gathered scalars.
-uint64_t slot_bytes() {
-    return align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN) + ALIGN +
-           align_up(sizeof(Scalars) * MAX_TRACES_PER_RUN, ALIGN);
-}
+uint64_t slot_bytes() { return align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN) + ALIGN; }
 
 uint64_t fixed_bytes() { return align_up((uint64_t)RUN_SLOTS * slot_bytes(), ALIGN); }
 
@@ -346,9 +345,10 @@ int sampler_create(int device, void* hip_stream, uint64_t mem_budget, void* work
         uint8_t* base = s->ws + i * slot_bytes();
         r.dev_desc = (Desc*)base;
         r.dev_ticket = (unsigned long long*)(base + align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN));
-        r.dev_scal = (Scalars*)(base + align_up(sizeof(Desc) * MAX_TRACES_PER_RUN, ALIGN) + ALIGN);
         if (hipHostMalloc((void**)&r.host_desc, sizeof(Desc) * MAX_TRACES_PER_RUN, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&r.host_scal, sizeof(Scalars) * MAX_TRACES_PER_RUN, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&r.host_scal, sizeof(Scalars) * MAX_TRACES_PER_RUN, hipHostMallocCoherent) !=
+                hipSuccess ||
+            hipHostGetDevicePointer((void**)&r.host_scal_dev, r.host_scal, 0) != hipSuccess ||
             hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&r.e_ready, hipEventDisableTiming) != hipSuccess ||
             hipEventCreate(&r.e_start) != hipSuccess || hipEventCreate(&r.e_end) != hipSuccess ||
@@ -459,9 +459,7 @@ static hipError_t issue_launch(RunSlot& r, const LaunchKey& k) {
         if (!ok(launch_pass(p, r.dev_desc, cnt, k.seg, k.tile, r.dev_ticket, lim, r.stream))) return e;
     }
     if ((k.ev_mask >> NPASS) & 1u && !ok(record(r.e_pass[NPASS]))) return e;
-    if (!ok(launch_finish(r.dev_desc, cnt, k.blk, k.lines, r.dev_ticket, (int)k.track_grid, r.dev_scal, r.stream)))
-        return e;
-    ok(hipMemcpyAsync(r.host_scal, r.dev_scal, sizeof(Scalars) * k.cnt, hipMemcpyDeviceToHost, r.stream));
+    ok(launch_finish(r.dev_desc, cnt, k.blk, k.lines, r.dev_ticket, (int)k.track_grid, r.host_scal_dev, r.stream));
     return e;
 }
 

@@ -2344,7 +2344,8 @@ __device__ int64_t gcd64(int64_t x, int64_t y) {
 // 0.95.  The last tracked object of a trace stays unresolved (its free does
 // not count) unless RESOLVE_AT_END, so the thread of its line takes it back
 // out of that line's frees.  Threads below 8 x ntraces also gather every
-// trace's scalars (final from here on) into one array for a single copy out.
+// trace's scalars (final from here on) into one array, which may live in
+// pinned host memory (the host reads it once the launch has completed).
 __global__ void k_finish(const Desc* __restrict__ desc, int ntraces, uint64_t total_lines, Scalars* gather) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < (uint64_t)ntraces * 8) {
