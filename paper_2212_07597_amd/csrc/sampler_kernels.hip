@@ -2040,7 +2040,9 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, cons
                 refF = readlane64(f, ls);
                 refP = readlane64(p, ls);
             }
-            if (fm && (cur_has || tmask)) {
+            if (fm && tmask) {
+                // a new tracked object in this window: each free compares
+                // with the last one tracked before it
                 const uint64_t tb = tmask & lanemask_lt();
                 const int al = tb ? top64(tb) : l;
                 const uint32_t spt = (uint32_t)shfl32((int)pt, al);
@@ -2049,6 +2051,10 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, cons
                 const bool ahas = tb != 0 || cur_has;
                 if (((fm >> l) & 1) && ahas && pt == aptr && aidx < D.n)
                     g_or(&D.freed_bits[aidx >> 6], 1ull << (aidx & 63));
+            } else if (fm && cur_has) {
+                // (the usual case) every free compares with the active object
+                if (((fm >> l) & 1) && pt == cur_ptr && cur_idx < D.n)
+                    g_or(&D.freed_bits[cur_idx >> 6], 1ull << (cur_idx & 63));
             }
             if (tmask) {
                 const int tl = top64(tmask);
