@@ -1063,6 +1063,7 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     __shared__ int64_t w_peak[TWAVES], w_peakS[TWAVES];
     __shared__ int w_left[TWAVES];
     __shared__ int64_t m_lo[TILE], m_hi[TILE], m_af[TILE], m_kf[TILE], m_ex[TILE];
+    __shared__ int64_t m_R[TILE];  // sparse tiles: the footprint change before each segment
     __shared__ uint64_t w_tot[TWAVES], w_sim[TWAVES];  // valid lanes with TOTAL / SIM maps
     __shared__ int64_t ring[RING][SEG];
     __shared__ int r_ready[RING];  // walk-order SIM index held by each slot
@@ -1157,6 +1158,12 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
     // of the walker's own (each stop of the walker waits for one): here the
     // other waves stay idle and the walker reads the kept prefixes itself.
     const bool sparse = kept && nsim > 0 && 4 * nwide >= 3 * nsim;
+    if (sparse) {
+        // the walker reads footprint offsets inside the tile from LDS instead
+        // of scanning each group of 64 segments it enters
+        m_R[tid] = rF;
+        __syncthreads();
+    }
     if (wv == 0) {
         // ---- the walker ----
         int q = 0;  // SIM segments passed, in walk order
@@ -1174,7 +1181,8 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                 const int64_t lo = m_lo[i], hi = m_hi[i], af = m_af[i], kf = m_kf[i];
                 const uint64_t sim = w_sim[g0 >> 6], tot = w_tot[g0 >> 6];
                 const bool is_tot = (tot >> l) & 1;
-                const int64_t S = (int64_t)((uint64_t)wave_incl_sum(af) - (uint64_t)af);
+                const int64_t S = sparse ? (int64_t)((uint64_t)m_R[i] - (uint64_t)m_R[g0])
+                                         : (int64_t)((uint64_t)wave_incl_sum(af) - (uint64_t)af);
                 // the last total-map lane before this one, and the entry it gives
                 const uint64_t tb = tot & lanemask_lt();
                 const int jl = tb ? top64(tb) : -1;
@@ -1188,7 +1196,7 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                     const int stop = fire ? ctz64(fire) : ge;
                     const int64_t xo = is_tot ? kf : (int64_t)((uint64_t)xi - (uint64_t)af);
                     if (l >= i0 && l < stop && !is_tot) m_ex[i] = xo;
-                    q += __popcll(sim & range_mask(0, i0, stop));
+                    if (!sparse) q += __popcll(sim & range_mask(0, i0, stop));
                     // release the slots passed over before any wait below (a
                     // producer may be waiting for them); every lane stores the
                     // same value (no lane-0-only region inside the loop).  A
@@ -1234,10 +1242,8 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                                     const int i2 = g0 + 64 + l;
                                     const bool v2 = i2 < e;
                                     const int64_t lo2 = m_lo[v2 ? i2 : 0], hi2 = m_hi[v2 ? i2 : 0];
-                                    const int64_t af2 = v2 ? m_af[i2] : 0;
                                     const uint64_t tot2 = w_tot[(g0 >> 6) + 1], sim2 = w_sim[(g0 >> 6) + 1];
-                                    const uint64_t d2 = (uint64_t)readlane64(S, 63) + (uint64_t)readlane64(af, 63) - base +
-                                                        ((uint64_t)wave_incl_sum(af2) - (uint64_t)af2);
+                                    const uint64_t d2 = (uint64_t)m_R[v2 ? i2 : 0] - (uint64_t)m_R[g0] - base;
                                     const bool cand2 = v2 && (((tot2 >> l) & 1) ||
                                                               !((int64_t)(A - d2) >= lo2 && (int64_t)(B - d2) <= hi2));
                                     const uint64_t cm2 = ballot(cand2);
@@ -1277,7 +1283,6 @@ __global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc,
                             pf_lane = p;
                             load_kept(D, k * TILE + (p >= 0 ? p : c), pf);
                             if (!one) r = walk_prefixes(ring[0], T, xs);
-                            ++q;
                         } else if ((sim >> stop) & 1) {
                             const int slot = q % RING;
                             if (kept && __hip_atomic_load(&r_ready[slot], __ATOMIC_ACQUIRE,
