@@ -15,7 +15,7 @@ constexpr int NW = 8;
 constexpr int SEG = 64 * NW;
 constexpr int WAVES = 4;                 // wavefronts per workgroup of the per-segment passes
 constexpr int BLOCK = 64 * WAVES;
-constexpr int TILE = 1024;               // segments per tile
+constexpr int TILE = 512;                // segments per tile
 constexpr int TWAVES = TILE / 64;
 constexpr int EMIT_SLOTS = 128;          // emit pass (samples)
 constexpr int TRACK_SLOTS = 64;          // and tracked-list pass (mallocs, frees)

@@ -916,7 +916,7 @@ __global__ __launch_bounds__(BLOCK) void k_summarize(const Desc* __restrict__ de
 
 // ------------------------------------------------------------ resolve pass
 
-constexpr int RING = 14;  // SIM segments pre-scanned ahead of the walker (one per producer wave)
+constexpr int RING = 12;  // SIM segments pre-scanned ahead of the walker
 
 // Relative footprint prefixes of segment j into F (one wave; lanes past the
 // segment end hold its last prefix).
@@ -1055,7 +1055,7 @@ __device__ __forceinline__ uint64_t range_mask(int w, int lo, int hi) {
 // the other waves scan the SIM segments' footprint prefixes into an LDS ring
 // ahead of the walker (skipping those it has already passed), so each one
 // costs the walker only a pass over LDS.
-__global__ __launch_bounds__(TILE) void k_resolve(const Desc* __restrict__ desc, int ntraces, uint64_t ntile_total,
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void k_resolve(const Desc* __restrict__ desc, int ntraces, uint64_t ntile_total,
                                                   unsigned long long* ctl) {
     __shared__ unsigned long long s_tk;
     __shared__ int64_t w_sum[3][TWAVES];

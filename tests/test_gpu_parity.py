@@ -178,7 +178,7 @@ def test_adversarial(sampler):
 
 
 def multi_tile_cases():
-    """Traces longer than one tile of 1024 segments (524,288 events) whose
+    """Traces spanning several tiles of 512 segments (262,144 events each) whose
     segment maps are rarely or never total, so that chain states travel
     serially across waves and tiles, and segments whose chains do not all
     coincide have to be followed from their actual entry."""
