@@ -494,6 +494,7 @@ def bench_batched(smp, tg, torch, np, steps=3, cpu=True, tune=None, plain_compar
     total = sum(len(ev) for ev, _ in traces)
     devs = [torch.from_numpy(ev.view(np.uint8)).to("cuda") for ev, _ in traces]
     params = [smp.make_params(kw["threshold"], kw["num_lines"]) for _, kw in traces]
+    params_arr = (smp.Params * len(params))(*params)  # built once: the batch is submitted every step
     need = sum(smp.workspace_bytes(len(ev), p) for (ev, _), p in zip(traces, params))
     s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + need + (64 << 20))
 
@@ -501,7 +502,7 @@ def bench_batched(smp, tg, torch, np, steps=3, cpu=True, tune=None, plain_compar
 
     def batched():
         t0 = time.perf_counter()
-        ids = s.submit_traces(devs, params)
+        ids = s.submit_traces(devs, params_arr)
         t1 = time.perf_counter()
         s.run(blocking=True)
         t2 = time.perf_counter()
@@ -512,7 +513,7 @@ def bench_batched(smp, tg, torch, np, steps=3, cpu=True, tune=None, plain_compar
         return km
 
     def one_batch():
-        ids = s.submit_traces(devs, params)
+        ids = s.submit_traces(devs, params_arr)
         s.run(blocking=True)
         s.release_traces(ids)
 

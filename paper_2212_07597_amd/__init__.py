@@ -416,33 +416,33 @@ class Sampler:
 
     def submit_traces(self, events_list, params_list):
         """Admit several traces with one call (all CUDA tensors, borrowed until
-        fetch, or all numpy arrays, copied).  Returns their ids.  If one is
-        refused, raises SamplerError whose .ids holds the admitted ones."""
+        fetch, or all numpy arrays, copied).  params_list is a list of Params,
+        or a ctypes array of Params built once for a batch that is submitted
+        again and again.  Returns their ids.  If one is refused, raises
+        SamplerError whose .ids holds the admitted ones."""
         k = len(events_list)
         if len(params_list) != k:
             raise ValueError("one Params per trace")
         if k == 0:
             return []
-        on_dev = all(hasattr(e, "data_ptr") and e.is_cuda for e in events_list)
+        on_dev = all(getattr(e, "is_cuda", False) for e in events_list)
         if not on_dev and any(hasattr(e, "data_ptr") for e in events_list):
             raise ValueError("pass all CUDA tensors or all numpy arrays")
         arrs = events_list if on_dev else [np.ascontiguousarray(e) for e in events_list]
         if on_dev:
-            ptrs = [e.data_ptr() for e in arrs]
-            ns = [e.numel() * e.element_size() // 24 for e in arrs]
+            ptrs = np.fromiter((e.data_ptr() for e in arrs), dtype=np.uint64, count=k)
         else:
-            ptrs = [a.ctypes.data if a.nbytes else 0 for a in arrs]
-            ns = [a.nbytes // 24 for a in arrs]
-        ev_a = (ctypes.c_void_p * k)(*ptrs)
-        n_a = (ctypes.c_uint64 * k)(*ns)
-        p_a = (Params * k)(*params_list)
-        ids = (ctypes.c_uint64 * k)()
+            ptrs = np.fromiter((a.ctypes.data if a.nbytes else 0 for a in arrs), dtype=np.uint64, count=k)
+        ns = np.fromiter((e.nbytes for e in arrs), dtype=np.uint64, count=k) // np.uint64(24)
+        p_a = params_list if isinstance(params_list, ctypes.Array) else (Params * k)(*params_list)
+        ids = np.zeros(k, dtype=np.uint64)
         done = ctypes.c_uint32()
-        rc = lib().submit_traces(self.h, k, ev_a, n_a, p_a, 1 if on_dev else 0, ids, ctypes.byref(done))
-        out = [int(ids[i]) for i in range(done.value)]
+        rc = lib().submit_traces(self.h, k, ptrs.ctypes.data_as(ctypes.POINTER(ctypes.c_void_p)),
+                                 ns.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), p_a, 1 if on_dev else 0,
+                                 ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), ctypes.byref(done))
+        out = ids[:done.value].tolist()
         if on_dev:
-            for i, tid in enumerate(out):
-                self._keep[tid] = arrs[i]
+            self._keep.update(zip(out, arrs))
         if rc != SMP_OK:
             err = SamplerError("submit_traces", rc)
             err.ids = out
@@ -454,15 +454,18 @@ class Sampler:
         k = len(trace_ids)
         if k == 0:
             return []
-        ids = (ctypes.c_uint64 * k)(*[int(t) for t in trace_ids])
-        ns = (ctypes.c_uint64 * k)()
-        st = (ctypes.c_int32 * k)()
+        ids = np.asarray(trace_ids, dtype=np.uint64)
+        ns = np.zeros(k, dtype=np.uint64)
+        st = np.zeros(k, dtype=np.int32)
         done = ctypes.c_uint32()
-        rc = lib().release_traces(self.h, k, ids, ns, st, ctypes.byref(done))
-        for i in range(done.value):
-            self._keep.pop(int(trace_ids[i]), None)
+        rc = lib().release_traces(self.h, k, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                  ns.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                  st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(done))
+        keep = self._keep
+        for t in ids[:done.value].tolist():
+            keep.pop(t, None)
         _check("release_traces", rc)
-        return [(int(ns[i]), int(st[i])) for i in range(k)]
+        return list(zip(ns.tolist(), st.tolist()))
 
     def release(self, trace_id):
         """Wait for a trace and free its workspace without copying results out.
