@@ -292,6 +292,11 @@ def test_batch_submit_and_release(sampler):
     assert got == [(o["K"], smp.SMP_OK) for o in want]
     with pytest.raises(smp.SamplerError):
         sampler.release_traces(ids)  # already released
+    # the same batch with its parameters as a prebuilt ctypes array
+    params_arr = (smp.Params * len(params))(*params)
+    ids = sampler.submit_traces(devs, params_arr)
+    sampler.run(blocking=True)
+    assert sampler.release_traces(ids) == [(o["K"], smp.SMP_OK) for o in want]
 
 
 def test_run_splits_over_4096_traces(sampler):
