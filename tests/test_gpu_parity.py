@@ -117,6 +117,29 @@ def test_segment_boundaries(sampler, n):
     check_batch(sampler, cases)
 
 
+def random_trace(rng, n):
+    """tiny_trace's distribution, drawn with numpy (for long traces)."""
+    ev = np.zeros(n, dtype=tg.EVENT_DTYPE)
+    kind = np.where(rng.random(n) < 0.15, rng.integers(1, 3, n), 0)
+    ev["delta"] = np.where(kind == 0, rng.integers(-40, 41, n), rng.integers(0, 30, n))
+    ev["ptr"] = rng.integers(1, 12, n)
+    ev["line"] = rng.integers(0, 5, n)
+    ev["flags"] = rng.integers(0, 2, n) | (kind << 1)
+    return ev
+
+
+@pytest.mark.parametrize("n", [512 * 512 - 1, 512 * 512, 512 * 512 + 1, 2 * 512 * 512 + 3])
+def test_tile_boundaries(sampler, n):
+    """Traces ending just before, at and just after a tile boundary (512
+    segments of 512 events), with thresholds that leave the tiles dense
+    (many stops) and sparse (T far above what a segment moves, with a few
+    samples per tile or none)."""
+    say(f"tile boundary n={n}")
+    ev = random_trace(np.random.default_rng(n), n)
+    cases = [(f"t{n}T{T}", ev, dict(threshold=T, num_lines=5)) for T in (30, 1000, 3000, 200_000)]
+    check_batch(sampler, cases)
+
+
 def test_config1_mix(sampler):
     say("config-1 mix: seeds x thresholds")
     cases = []
