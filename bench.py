@@ -4,19 +4,24 @@ Workload (single GPU): config 2 - one trace of 1e8 events (lifetime mix: 95 %
 small Python objects, 5 % native arrays of 1-256 MiB, exponential lifetimes,
 10,000 lines, T = 10 MiB).  The trace is generated on the host (seeded),
 copied to HBM once, and every step runs submit_trace (device-resident
-events) + run + release on the sampler's stream.  Inputs are resident in HBM
-when the timed region starts.
+events) + run + release.  Inputs are resident in HBM when the timed region
+starts.  The headline steps are issued back to back, two in flight on two
+run slots: a step's launch is queued while the previous step runs, and the
+previous step is released once the next has been launched (every step still
+runs the whole launch sequence).  The same steps one after another, each
+waited for, are reported beside it (config.serialized).
 
 Prints one JSON line with events/s, the roofline figures of the dominant
 kernel (the slowest of the five sampling passes; its algorithmic bytes are
 the 24-byte record of every event, over that kernel's own HIP-event duration
-in the timed steps), the whole launch against the same bytes, and the CPU
-oracle timed on one pinned host core as a baseline.  The per-pass breakdown
-(pass_ms, kernel_ms) comes from untimed steps that record events around
-every pass; the timed steps record only the two around the dominant pass,
-because each event between two kernels idles the GPU for a few
-microseconds.  An end-to-end figure (pinned host events -> HBM, the launch,
-and the full profile copied back) is reported beside it, never as `value`.
+in the serialized steps), the whole launch against the same bytes, and the
+CPU oracle timed on one pinned host core as a baseline.  The per-pass
+breakdown (pass_ms, kernel_ms) comes from untimed steps that record events
+around every pass; the serialized steps record only the two around the
+dominant pass, because each event between two kernels idles the GPU for a
+few microseconds.  An end-to-end figure (pinned host events -> HBM, the
+launch, and the full profile copied back) is reported beside it, never as
+`value`.
 
 ``--only config5|batched|served`` runs one extra measurement alone and
 prints its JSON (for profiling one workload at a time).
@@ -199,8 +204,10 @@ def main():
     dev = torch.from_numpy(ev.view(np.uint8)).to("cuda")
     params = smp.make_params(kw["threshold"], kw["num_lines"])
     want = set() if args.no_extras else {x for x in args.extras.split(",") if x}
-    # room for a device copy of the events too (the end-to-end steps)
-    need = smp.workspace_bytes(n, params, ev_on_device="e2e" not in want)
+    # room for two traces in flight (the back-to-back steps) and for one with
+    # a device copy of its events (the end-to-end steps)
+    need = max(2 * smp.workspace_bytes(n, params, ev_on_device=True),
+               smp.workspace_bytes(n, params, ev_on_device="e2e" not in want))
     s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + need + (1 << 20))
 
     def step():
@@ -239,31 +246,42 @@ def main():
     di = smp.PASS_NAMES.index(dominant)
     s.set_pass_events((1 << di) | (1 << (di + 1)))
 
+    # One step after another, each waited for: the dominant pass's own time
+    # and the serialized step (host launch latency and completion wake-up
+    # included in every step).
     dom_ms = []
-    log(f"timing {args.steps} steps")
+    log(f"timing {args.steps} serialized steps")
     torch.cuda.synchronize()
-    t_start = time.perf_counter()
+    t_ser = time.perf_counter()
     for _ in range(args.steps):
         tid = step()
         dom_ms.append(s.last_pass_timing()[dominant])
         release(tid)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    # The same steps with only the start event: the launch sequence replays
-    # as a HIP graph (reported beside the headline, whose loop records the
-    # events around the dominant pass and so launches plainly).
+    elapsed_ser = time.perf_counter() - t_ser
+    # The headline: the same steps issued back to back, two in flight on two
+    # run slots (a step's launch is queued while the previous step runs, and
+    # the previous step is released once the next has been launched), with
+    # only the start event, so each launch sequence replays as a HIP graph.
     s.set_pass_events(0x40)
-    for _ in range(3):
-        release(step())
+
+    def back_to_back(steps):
+        prev = None
+        for _ in range(steps):
+            tid = s.submit_trace(dev, params)
+            s.run(blocking=False)
+            if prev is not None:
+                release(prev)
+            prev = tid
+        release(prev)
+
+    back_to_back(6)
     torch.cuda.synchronize()
-    graph_launch = []
-    t_g = time.perf_counter()
-    for _ in range(args.steps):
-        tid = step()
-        graph_launch.append(s.last_timing()[1])
-        release(tid)
+    log(f"timing {args.steps} back-to-back steps")
+    t_start = time.perf_counter()
+    back_to_back(args.steps)
     torch.cuda.synchronize()
-    elapsed_g = time.perf_counter() - t_g
+    elapsed = time.perf_counter() - t_start
     s.set_pass_events(0x7F)
     K = last["K"]
     s_stats = s.launch_stats()
@@ -324,13 +342,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "config2: one trace, 1e8 events, lifetime mix (95% Python 16-512 B, 5% native "
                                "1-256 MiB, exp lifetimes mean 1e4), 10000 lines Zipf 1.2, T=10 MiB",
-                   "events": n, "samples": K, "seed": args.seed, "path": "plain one-trace-per-launch",
+                   "events": n, "samples": K, "seed": args.seed,
+                   "path": "one trace per launch, launches replayed as HIP graphs, two steps in flight",
                    "kernel_ms": round(main_ms, 4), "launch_sequence_ms": round(launch_ms, 4),
                    "pass_ms": {k: round(v, 4) for k, v in passes.items()},
                    "dominant_pass_ms_timed": round(dom_timed, 4), "tuning": tuned,
-                   "graph_replay": {"ms_per_step": round(elapsed_g * 1e3 / args.steps, 4),
-                                    "events_per_s": round(n * args.steps / elapsed_g, 1),
-                                    "launch_sequence_ms": round(statistics.median(graph_launch), 4)},
+                   "steps_in_flight": 2,
+                   "serialized": {"ms_per_step": round(elapsed_ser * 1e3 / args.steps, 4),
+                                  "events_per_s": round(n * args.steps / elapsed_ser, 1)},
                    "launches": s_stats},
         "roofline": roof,
         "cpu_baseline": cpu_base,
