@@ -515,7 +515,8 @@ def bench_batched(smp, tg, torch, np, steps=3, cpu=True, tune=None, plain_compar
     params = [smp.make_params(kw["threshold"], kw["num_lines"]) for _, kw in traces]
     params_arr = (smp.Params * len(params))(*params)  # built once: the batch is submitted every step
     need = sum(smp.workspace_bytes(len(ev), p) for (ev, _), p in zip(traces, params))
-    s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + need + (64 << 20))
+    # room for two batches in flight (the back-to-back batches)
+    s = smp.Sampler(workspace=smp.sampler_fixed_bytes() + 2 * need + (64 << 20))
 
     phases = []
 
@@ -560,6 +561,25 @@ def bench_batched(smp, tg, torch, np, steps=3, cpu=True, tune=None, plain_compar
     for _ in range(steps):
         batched()
     tb = (time.perf_counter() - t0) / steps
+    # the same batches back to back, two in flight on two run slots (a
+    # batch is released once the next one has been launched)
+
+    def back_to_back(n_batches):
+        prev = None
+        for _ in range(n_batches):
+            ids = s.submit_traces(devs, params_arr)
+            s.run(blocking=False)
+            if prev is not None:
+                s.release_traces(prev)
+            prev = ids
+        s.release_traces(prev)
+
+    back_to_back(3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    back_to_back(steps)
+    torch.cuda.synchronize()
+    tb2 = (time.perf_counter() - t0) / steps
     s.set_pass_events(0x7F)
     s_stats = s.launch_stats()
     tp = None
@@ -615,6 +635,8 @@ def bench_batched(smp, tg, torch, np, steps=3, cpu=True, tune=None, plain_compar
             "cpu_baseline_one_core": cpu_one, "cpu_baseline_all_cores": cpu_all,
             "events": total, "batched_events_per_s": round(total / tb, 1), "batched_ms": round(tb * 1e3, 3),
             "batched_kernel_ms": round(kms_avg, 3),
+            "back_to_back": {"ms_per_batch": round(tb2 * 1e3, 3), "events_per_s": round(total / tb2, 1),
+                             "batches_in_flight": 2},
             "batched_phase_ms": {k: round(statistics.median(p[i] for p in phases) * (1 if i == 3 else 1e3), 3)
                                  for i, k in enumerate(("submit_traces", "run_blocking", "release_traces",
                                                         "launch_sequence_gpu"))},
