@@ -255,7 +255,13 @@ SMP_API int sampler_last_pass_timing(smp_sampler_t *s, float *pass_ms);
 /* Diagnostics: the 32 control words of the last launch (word 1: abort flag,
  * words 2 and 3: tiles taken by the resolve and scan passes, word 4:
  * segments the chain pass followed through their records (the resolve pass
- * finishes the others); the other words are 0). */
+ * finishes the others), word 5: tiles given a tile map, word 6: tiles whose
+ * exit was chained through tile maps before the resolve pass, words 7-10:
+ * tiles of traces with tile maps that got none because a segment moves T or
+ * more (or is not followed by chains), or because the tile needs more source
+ * intervals, live chains or runs than a map holds, word 12: segments the
+ * chain pass visits only to count their copy and timer events; the other
+ * words are 0). */
 SMP_API int sampler_last_counters(smp_sampler_t *s, uint64_t *out32);
 
 /* Launch parameters of later runs.  None changes any result (every
@@ -272,6 +278,13 @@ SMP_API int sampler_last_counters(smp_sampler_t *s, uint64_t *out32);
  *                captured on the second launch of that shape; launches that
  *                record timing events between passes (sampler_set_pass_events
  *                bits 0-5) are always plain; 0 = plain launches only
+ *   tile_map_tiles : traces of at least this many tiles (of 512 segments of
+ *                512 events) get tile maps: for every tile whose segments
+ *                each move the footprint by less than T, its chain map over
+ *                all entries (section 3.2), built for all tiles at once
+ *                before the resolve pass, so that tile entries follow by one
+ *                lookup per tile instead of a walk per tile (0 = the default,
+ *                64; 0xFFFFFFFF = never)
  * sampler_set_tuning returns SMP_EINVAL for values out of range;
  * sampler_get_tuning reports the current ones with the defaults resolved. */
 typedef struct {
@@ -279,6 +292,7 @@ typedef struct {
     uint32_t chain_grid;
     uint32_t emit_grid;
     uint32_t graphs;
+    uint32_t tile_map_tiles;
 } smp_tuning_t;
 SMP_API int sampler_set_tuning(smp_sampler_t *s, const smp_tuning_t *t);
 SMP_API int sampler_get_tuning(smp_sampler_t *s, smp_tuning_t *t);

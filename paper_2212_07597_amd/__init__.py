@@ -82,6 +82,7 @@ class Tuning(ctypes.Structure):
         ("chain_grid", ctypes.c_uint32),
         ("emit_grid", ctypes.c_uint32),
         ("graphs", ctypes.c_uint32),
+        ("tile_map_tiles", ctypes.c_uint32),
     ]
 
 
@@ -494,15 +495,16 @@ class Sampler:
         _check("sampler_last_pass_timing", lib().sampler_last_pass_timing(self.h, buf))
         return dict(zip(PASS_NAMES, (float(x) for x in buf)))
 
-    def set_tuning(self, chain_cap=16, chain_grid=0, emit_grid=0, graphs=1):
+    def set_tuning(self, chain_cap=16, chain_grid=0, emit_grid=0, graphs=1, tile_map_tiles=0):
         """Launch parameters of later runs (no effect on results)."""
         _check("sampler_set_tuning", lib().sampler_set_tuning(self.h, ctypes.byref(
-            Tuning(int(chain_cap), int(chain_grid), int(emit_grid), int(graphs)))))
+            Tuning(int(chain_cap), int(chain_grid), int(emit_grid), int(graphs), int(tile_map_tiles)))))
 
     def get_tuning(self):
         t = Tuning()
         _check("sampler_get_tuning", lib().sampler_get_tuning(self.h, ctypes.byref(t)))
-        return {"chain_cap": t.chain_cap, "chain_grid": t.chain_grid, "emit_grid": t.emit_grid, "graphs": t.graphs}
+        return {"chain_cap": t.chain_cap, "chain_grid": t.chain_grid, "emit_grid": t.emit_grid, "graphs": t.graphs,
+                "tile_map_tiles": t.tile_map_tiles}
 
     def launch_stats(self):
         """(plain launch sequences, graphs captured, graph replays) so far."""

@@ -21,6 +21,7 @@ constexpr int EMIT_SLOTS = 128;          // emit pass (samples)
 constexpr int TRACK_SLOTS = 64;          // and tracked-list pass (mallocs, frees)
 constexpr int NCNT = 12;                 // counters cached per slot
 constexpr int CHAIN_CAP_MAX = 64;        // chains the all-entry analysis can follow (one per lane)
+constexpr uint64_t TILE_MAP_BYTES = 32768;  // map area per tile (in the tracked-list area)
 
 constexpr int64_t MAX_ABS_DELTA = (int64_t)1 << 52;
 constexpr int64_t MAX_ABS_F = (int64_t)1 << 61;
@@ -56,6 +57,7 @@ enum {
     NSPLANE
 };
 constexpr int64_t BFL_CHAIN = 8;
+constexpr int64_t BFL_AUX = 16;  // (with the resolve pass's results) copy and timer events left to the chain pass
 
 // Look-back status words of one tile (each: 2-bit state | 62-bit payload,
 // written once per run; stored plane by plane like the segment values).
@@ -130,6 +132,8 @@ struct Desc {
     uint64_t zero_bytes;
     uint64_t zero_begin;     // offset of that range in the launch's flattened clear space
     uint64_t line_begin;     // offset of this trace's lines in the flattened line space
+    uint32_t tmap;           // 1: tiles that qualify get a tile map before the resolve pass
+    uint32_t pad_;
 };
 
 // ---- wave64 helpers -------------------------------------------------------

@@ -21,6 +21,7 @@ hipError_t launch_pass(int pass, const Desc* desc, int ntraces, uint64_t nseg_to
                        unsigned long long* ctl, int grid_limit, hipStream_t s);
 hipError_t launch_finish(const Desc* desc, int ntraces, uint64_t nblk_total, uint64_t total_lines,
                          unsigned long long* ctl, int track_grid, Scalars* gather, hipStream_t s);
+hipError_t launch_tmap(const Desc* desc, int ntraces, uint64_t ntile_total, unsigned long long* ctl, hipStream_t s);
 }  // namespace smp
 
 using namespace smp;
@@ -37,6 +38,7 @@ constexpr int RUN_SLOTS = 8;
 constexpr int MAX_TRACES_PER_RUN = 4096;
 constexpr uint64_t CBLK_WORDS = 256;
 constexpr int NPASS = 5;  // summarize, resolve, chain, scan, emit
+constexpr uint32_t TILE_MAP_TILES_DEFAULT = 64;  // traces of at least this many tiles get tile maps
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -161,7 +163,7 @@ constexpr uint32_t PASS_EVENT_BITS = (1u << (NPASS + 1)) - 1;  // the events bet
 // Shape of one launch sequence: everything its kernel arguments and grids
 // depend on besides the slot's own buffers.
 struct LaunchKey {
-    uint64_t cnt, seg, tile, blk, zero, lines, ev_mask, chain_grid, emit_grid, track_grid;
+    uint64_t cnt, seg, tile, blk, zero, lines, ev_mask, chain_grid, emit_grid, track_grid, tmap;
     bool operator==(const LaunchKey& o) const { return memcmp(this, &o, sizeof(LaunchKey)) == 0; }
 };
 
@@ -210,7 +212,7 @@ struct smp_sampler {
     float last_main_ms = 0, last_total_ms = 0;
     float last_pass_ms[NPASS] = {};
     uint32_t pass_events = PASS_EVENTS_ALL;  // timing events to record (all by default)
-    smp_tuning_t tuning{16, 0, 0, 1};
+    smp_tuning_t tuning{16, 0, 0, 1, 0};
     bool graphs_ok = true;                   // off after a failed capture
     uint64_t n_plain = 0, n_captured = 0, n_replayed = 0;
     uint64_t last_seq = 0;
@@ -256,6 +258,15 @@ void arena_free(smp_sampler* s, uint64_t off, uint64_t bytes) {
 int fail(smp_sampler* s) {
     s->failed = true;
     return SMP_EDEVICE;
+}
+
+// Whether a trace gets tile maps: long enough (the maps are built for all
+// tiles at once, in about the time a few tiles take to walk one after
+// another) and with room for them in its tracked-list area.
+bool wants_tile_maps(const smp_sampler* s, const TraceRec& t) {
+    const uint64_t min_tiles = s->tuning.tile_map_tiles ? s->tuning.tile_map_tiles : TILE_MAP_TILES_DEFAULT;
+    return t.lay.ntile >= min_tiles && t.lay.ntile > 1 &&
+           sizeof(Tracked) * (t.n + 1) >= t.lay.ntile * TILE_MAP_BYTES;
 }
 
 #define HIPCHK(expr)                          \
@@ -456,6 +467,7 @@ static hipError_t issue_launch(RunSlot& r, const LaunchKey& k) {
     for (int p = 0; p < NPASS; ++p) {
         if ((k.ev_mask >> p) & 1u && !ok(record(r.e_pass[p]))) return e;
         const int lim = p == 2 ? (int)k.chain_grid : (int)k.emit_grid;
+        if (p == 1 && k.tmap && !ok(launch_tmap(r.dev_desc, cnt, k.tile, r.dev_ticket, r.stream))) return e;
         if (!ok(launch_pass(p, r.dev_desc, cnt, k.seg, k.tile, r.dev_ticket, lim, r.stream))) return e;
     }
     if ((k.ev_mask >> NPASS) & 1u && !ok(record(r.e_pass[NPASS]))) return e;
@@ -522,6 +534,7 @@ int run(smp_sampler_t* s, int blocking) {
             key.blk += t.lay.nblk;
             key.zero += t.lay.zero_end - t.lay.zero;
             key.lines += t.params.num_lines;
+            key.tmap += wants_tile_maps(s, t) ? 1 : 0;
         }
         key.ev_mask = s->pass_events;
         key.chain_grid = s->tuning.chain_grid ? s->tuning.chain_grid : (uint64_t)s->grid_chain;
@@ -588,6 +601,7 @@ int run(smp_sampler_t* s, int blocking) {
             D.zero_bytes = t.lay.zero_end - t.lay.zero;
             D.zero_begin = zero;
             D.line_begin = lines;
+            D.tmap = wants_tile_maps(s, t) ? 1u : 0u;
             seg += D.nseg;
             tile += D.ntile;
             blk += D.nblk;

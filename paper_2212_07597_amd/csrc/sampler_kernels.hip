@@ -1041,6 +1041,536 @@ __device__ __forceinline__ uint64_t range_mask(int w, int lo, int hi) {
     return ma & mb;
 }
 
+// ------------------------------------------------------------ tile maps
+//
+// A tile whose segments each move less than T (every SIM map holds at least
+// T - 1 + 1 entries in its no-sample interval) lets an entry sample at most
+// once per segment.  For such a tile the chain map over all entry offsets of
+// the whole tile is computed by one wave, segment by segment, before the
+// resolve pass (section 3.2's rule, restated over entries as in the segment
+// analysis):
+//  * entries that have not sampled yet form one interval U, which shrinks as
+//    the tile's running maximum and minimum footprint grow apart;
+//  * at each new running maximum (minimum) node while U is not empty, the
+//    entries of U at least T below (above) that node sample there: they form
+//    one source interval and start a chain whose reference is that node's
+//    footprint;
+//  * a chain outside a segment's no-sample interval samples once in it, at
+//    the first node at least T above (below) its reference;
+//  * chains that sample at the same node coincide from there on and are
+//    merged (their sources are joined in a union-find forest).
+// Source intervals started at maxima lie below U and grow upward in start
+// order; those started at minima lie above it and grow downward.  Runs of
+// consecutive sources that end at the same reference are written as (bound,
+// exit) pairs, so that the tile's exit for any entry is one search.  One
+// workgroup then chains each trace's tile entries through the maps in tile
+// order and publishes every tile's exit, so that the resolve pass no longer
+// waits for the previous tile's walk.  A tile that does not qualify, or whose
+// chains or runs exceed the capacities below, gets no map; the tiles from it
+// on are chained by the resolve pass's walks as before.
+
+constexpr int TM_CAP = 1024;   // chains followed at once
+constexpr int TM_SRC = 2048;   // source intervals per tile
+constexpr int TM_SIDE = 128;   // runs per side (below and above U)
+constexpr int64_t TM_WORDS = (int64_t)(TILE_MAP_BYTES / 8);
+// Run r of side s (0: below U, 1: above) has its bound at run_word(s, 0, r)
+// and its exit at run_word(s, 1, r): the first 64 runs of both sides and the
+// header (state, runs below, runs above, tile change) lie in words 0-259, the
+// words the map chain copies; runs 64-127 follow at word 512.
+constexpr int TM_HDR = 256;
+constexpr int TM_RUN_HI = 512;
+__device__ __forceinline__ int run_word(int side, int which, int r) {
+    return (r < 64 ? 0 : TM_RUN_HI) + side * 128 + which * 64 + (r & 63);
+}
+constexpr int TM_SB = 1024;    // source bounds (scratch while the map is built)
+constexpr int TM_SD = 3072;    // source sides, one byte each: 1 = below U (scratch)
+enum { TM_MAPPED = 1, TM_NONE = 2 };
+// causes of a tile without a map (control words 7-10 count them)
+enum { TMF_QUALIFY = 1, TMF_SOURCES, TMF_CHAINS, TMF_RUNS };
+
+// The map area of tile k: the tracked-list area, unused until the tracked
+// list is built at the end of the launch (16 bytes per event against 4 bytes
+// per event needed here).
+__device__ __forceinline__ SMP_GLOBAL int64_t* tile_map(const Desc& D, int64_t k) {
+    return gp((int64_t*)D.tracked) + k * TM_WORDS;
+}
+
+// First node of a segment (relative prefixes f) whose prefix is >= thr (GE)
+// or <= thr (LE); SEG if none.  Branch-free: one compare per window, then a
+// select per window from the last one down.
+template <bool GE>
+__device__ __forceinline__ int first_node(const int64_t (&f)[NW], int64_t thr) {
+    uint64_t m[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) m[w] = ballot(GE ? f[w] >= thr : f[w] <= thr);
+    int k = SEG;
+#pragma unroll
+    for (int w = NW - 1; w >= 0; --w) k = m[w] ? w * 64 + ctz64(m[w]) : k;
+    return k;
+}
+// The same for two thresholds at once (independent, so their instructions interleave).
+template <bool GE>
+__device__ __forceinline__ void first_node2(const int64_t (&f)[NW], int64_t t1, int64_t t2, int& k1, int& k2) {
+    uint64_t m1[NW], m2[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        m1[w] = ballot(GE ? f[w] >= t1 : f[w] <= t1);
+        m2[w] = ballot(GE ? f[w] >= t2 : f[w] <= t2);
+    }
+    k1 = SEG;
+    k2 = SEG;
+#pragma unroll
+    for (int w = NW - 1; w >= 0; --w) {
+        k1 = m1[w] ? w * 64 + ctz64(m1[w]) : k1;
+        k2 = m2[w] ? w * 64 + ctz64(m2[w]) : k2;
+    }
+}
+
+// One wave per tile (grid: every tile of the launch; tiles of traces without
+// maps return at once).
+__global__ __launch_bounds__(64) void k_tmap(const Desc* __restrict__ desc, int ntraces, unsigned long long* ctl) {
+    __shared__ int64_t cx[TM_CAP];       // live chains: reference (tile coordinates)
+    __shared__ uint16_t cr[TM_CAP];      // and the root source of their set
+    __shared__ uint16_t par[TM_SRC];     // union-find parent of each source
+    // per segment: its prefixes, and per node the chain that sampled there
+    // first (see claim below); at the end: the live chain of each root
+    __shared__ int64_t lds_u[(SEG * 8 + SEG * 4 > TM_SRC * 2 ? SEG * 8 + SEG * 4 : TM_SRC * 2) / 8];
+    int64_t* fl = lds_u;
+    uint32_t* claim = (uint32_t*)(lds_u + SEG);
+    uint16_t* cidx = (uint16_t*)lds_u;
+    const int l = lane_id();
+    const uint64_t tk = blockIdx.x;
+    const Desc& D = desc[find_trace_tile(desc, ntraces, tk)];
+    if (!D.tmap) return;
+    const int64_t k = (int64_t)(tk - D.tile_begin);
+    const int64_t ns = (int64_t)D.nseg;
+    const int nval = (int)((ns - k * TILE) < TILE ? (ns - k * TILE) : TILE);
+    const int64_t T = D.T;
+    SMP_GLOBAL int64_t* map = tile_map(D, k);
+    SMP_GLOBAL uint8_t* sside = (SMP_GLOBAL uint8_t*)(map + TM_SD);
+    const SMP_GLOBAL int64_t* sp = gp(D.seg) + k * TILE;
+    // every segment SIM, with a no-sample interval of at least T entries
+    // (then max - min < T over its prefixes and the entry)
+    bool ok = prefixes_kept(D);
+    for (int g = 0; g < nval && ok; g += 64) {
+        const int s = g + l;
+        const bool v = s < nval;
+        const int64_t lo = v ? sp[SP_LO * ns + s] : 0, hi = v ? sp[SP_HI * ns + s] : 0;
+        const int64_t fl_ = v ? sp[SP_FLG * ns + s] : 0;
+        if (ballot(v && ((fl_ & 3) != MAP_SIM || hi < lo || hi - lo < T - 1))) ok = false;
+    }
+    if (!ok) {
+        if (l == 0) {
+            map[TM_HDR] = TM_NONE;
+            g_add((uint64_t*)&ctl[6 + TMF_QUALIFY], 1ull);
+        }
+        return;
+    }
+    for (int i = l; i < SEG; i += 64) claim[i] = 0;
+    int nch = 0, nsrc = 0;
+    int fail = 0;  // cause, 0 while the map holds
+    int64_t Umax = 0, Umin = 0, carry = 0;  // running extremes (from the tile start), footprint change so far
+    // segments g..g+63, one per lane: offset, no-sample bounds and extremes in tile coordinates
+    int64_t gR = 0, gL = 0, gH = 0, gX = 0, gN = 0;
+    auto step = [&](int s, const int64_t (&f)[NW]) {
+        if ((s & 63) == 0) {
+            const int j = s + l;
+            const bool v = j < nval;
+            const int64_t af = v ? sp[SP_AF * ns + j] : 0;
+            const int64_t lo = v ? sp[SP_LO * ns + j] : 0, hi = v ? sp[SP_HI * ns + j] : 0;
+            const int64_t mx = v ? sp[SP_MXF * ns + j] : 0, mn = v ? sp[SP_MNF * ns + j] : 0;
+            const int64_t inc = wave_incl_sum(af);
+            gR = carry + inc - af;
+            carry += readlane64(inc, 63);
+            gL = gR + lo;
+            gH = gR + hi;
+            gX = gR + mx;
+            gN = gR + mn;
+        }
+        const int i = s & 63;
+        const int64_t R = readlane64(gR, i), Ls = readlane64(gL, i), Hs = readlane64(gH, i);
+        const int64_t Sx = readlane64(gX, i), Sn = readlane64(gN, i);
+        // the prefixes in LDS: the value at a sampled node is read from there
+#pragma unroll
+        for (int w = 0; w < NW; ++w) fl[w * 64 + l] = f[w];
+        // Chains that sample at one node merge into the first of them.
+        // claim[node] (step numbers from 1): step << 16 | 0x7FFF - chain
+        // while chains compete for it (the largest wins: the earliest
+        // chain), then step << 16 | 0x8000 | root of the winner's set.
+        const uint32_t stag = (uint32_t)(s + 1) << 16;
+        // live chains: those outside the no-sample interval sample once here
+        // (each group's words load while the one before it is processed:
+        // the compaction below never writes past the group it processes)
+        int out = 0;
+        int64_t Xn = l < nch ? cx[l] : 0;
+        int rtn = l < nch ? (int)cr[l] : 0;
+        for (int c0 = 0; c0 < nch; c0 += 64) {
+            const int c = c0 + l;
+            const bool v = c < nch;
+            int64_t X = Xn;
+            const int rt = rtn;
+            if (c0 + 64 < nch) {
+                const int cn = c + 64;
+                Xn = cn < nch ? cx[cn] : 0;
+                rtn = cn < nch ? (int)cr[cn] : 0;
+            }
+            const uint64_t vm = ballot(v);
+            uint64_t alive = vm;
+            bool moved = false;  // sampled here and keeps its chain
+            const bool up = v && X < Ls;
+            const uint64_t sm0 = ballot(up || (v && X > Hs));
+            if (sm0) {
+                // each sampling chain's node: two chains of one direction at a time
+                const uint64_t um = ballot(up), dm = sm0 & ~um;
+                const int64_t thr = up ? X - R + T : X - R - T;
+                int xnode = SEG;
+#define SMP_TM_SEARCH(MASK, GE)                                                 \
+    for (uint64_t m_ = (MASK); m_;) {                                           \
+        const int q1 = ctz64(m_);                                               \
+        m_ &= m_ - 1;                                                           \
+        const int64_t th1 = readlane64(thr, q1);                                \
+        if (m_) {                                                               \
+            const int q2 = ctz64(m_);                                           \
+            m_ &= m_ - 1;                                                       \
+            int n1, n2;                                                         \
+            first_node2<GE>(f, th1, readlane64(thr, q2), n1, n2);               \
+            xnode = l == q1 ? n1 : (l == q2 ? n2 : xnode);                      \
+        } else {                                                                \
+            const int n1 = first_node<GE>(f, th1);                              \
+            xnode = l == q1 ? n1 : xnode;                                       \
+        }                                                                       \
+    }
+                SMP_TM_SEARCH(um, true)
+                SMP_TM_SEARCH(dm, false)
+#undef SMP_TM_SEARCH
+                const bool mine = (sm0 >> l) & 1;
+                if (ballot(mine && xnode >= SEG)) {  // (unreachable: a chain outside the interval crosses)
+                    fail = TMF_QUALIFY;
+                    break;
+                }
+                // merges, for the whole group at once
+                const uint32_t key = stag | (uint32_t)(0x7FFF - c);
+                if (mine) __hip_atomic_fetch_max(&claim[xnode], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const uint32_t got =
+                    mine ? __hip_atomic_load(&claim[xnode], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
+                const bool win = mine && got == key;
+                if (win)
+                    __hip_atomic_store(&claim[xnode], stag | 0x8000u | (uint32_t)rt, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                const bool lose = mine && !win;
+                // the winner's root: in the claim once resolved (an earlier
+                // group), else held by the winner's lane in this group
+                const int wl = (int)(0x7FFFu - (got & 0x7FFFu)) - c0;
+                const int wr = shfl32(rt, (got & 0x8000u) ? l : (wl & 63));
+                if (lose) par[rt] = (uint16_t)((got & 0x8000u) ? (got & 0x7FFFu) : (uint32_t)wr);
+                alive &= ~ballot(lose);
+                if (win) X = R + fl[xnode];
+                moved = win;
+            }
+            // compact in place (survivors never move up); while no chain of
+            // this step has merged, only the sampled references change
+            if (out == c0 && alive == vm) {
+                if (moved) cx[c] = X;
+            } else if ((alive >> l) & 1) {
+                const int o = out + __popcll(alive & lanemask_lt());
+                cx[o] = X;
+                cr[o] = (uint16_t)rt;
+            }
+            out += __popcll(alive);
+        }
+        nch = out;
+        // New running extremes while U is not empty start chains.  A window
+        // with no node beyond the extremes so far leaves them unchanged; in
+        // the others, the extremes before each node come from a scan.
+        if (!fail && Umax - Umin <= 2 * T - 2 && (Sx > Umax || Sn < Umin)) {
+            int64_t cm = Umax, cn = Umin;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                if (cm - cn > 2 * T - 2 || fail) break;
+                const int64_t gv = R + f[w];
+                if (!ballot(gv > cm || gv < cn)) continue;
+                int64_t im = wave_incl_max(gv), in = wave_incl_min(gv);
+                im = im > cm ? im : cm;
+                in = in < cn ? in : cn;
+                const int64_t pm = wave_shr1(im, cm), pn = wave_shr1(in, cn);  // before the node
+                const bool open = pm - pn <= 2 * T - 2;
+                const bool up = open && gv > pm, dn = open && gv < pn;
+                const uint64_t spm = ballot(up || dn);
+                cm = readlane64(im, 63);
+                cn = readlane64(in, 63);
+                if (!spm) continue;
+                const int cnt = __popcll(spm);
+                if (nsrc + cnt > TM_SRC) {
+                    fail = TMF_SOURCES;
+                    break;
+                }
+                // sources in node order; the entries of U = [pm - T + 1,
+                // pn + T - 1] that sample at this node
+                const bool sp_ = (spm >> l) & 1;
+                const int src = nsrc + __popcll(spm & lanemask_lt());
+                const int64_t bound = up ? ((pn + T - 1) < (gv - T) ? (pn + T - 1) : (gv - T))
+                                         : ((pm - T + 1) > (gv + T) ? (pm - T + 1) : (gv + T));
+                // a chain that sampled at the same node takes the source into its set
+                const uint32_t cl =
+                    sp_ ? __hip_atomic_load(&claim[w * 64 + l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
+                const bool hit = sp_ && (cl >> 16) == (stag >> 16);
+                const uint64_t nm = spm & ~ballot(hit);  // new chains
+                if (nch + __popcll(nm) > TM_CAP) {
+                    fail = TMF_CHAINS;
+                    break;
+                }
+                if (sp_) {
+                    map[TM_SB + src] = bound;
+                    sside[src] = up ? 1 : 0;
+                    par[src] = (uint16_t)(hit ? (cl & 0x7FFFu) : (uint32_t)src);
+                }
+                if ((nm >> l) & 1) {
+                    const int o = nch + __popcll(nm & lanemask_lt());
+                    cx[o] = gv;
+                    cr[o] = (uint16_t)src;
+                }
+                nsrc += cnt;
+                nch += __popcll(nm);
+            }
+        }
+        Umax = Sx > Umax ? Sx : Umax;
+        Umin = Sn < Umin ? Sn : Umin;
+    };
+    // the next segment's prefixes load while one is processed (into fn,
+    // copied out at the start of each step: the only loads then in flight
+    // are the ones the copy needs, issued a whole step earlier)
+    const int64_t j0 = k * TILE;
+    int64_t fn[NW];
+    load_kept(D, j0, fn);
+    for (int s = 0; s < nval && !fail; ++s) {
+        int64_t f[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) f[w] = fn[w];
+        load_kept(D, j0 + (s + 1 < nval ? s + 1 : s), fn);
+        step(s, f);
+    }
+    // runs: consecutive sources of one side that end at the same reference
+    int nup = 0, ndn = 0;
+    if (!fail) {
+        const int64_t tF = carry;
+        for (int i = l; i < nsrc; i += 64) cidx[i] = 0;
+        for (int c0 = 0; c0 < nch; c0 += 64)
+            if (c0 + l < nch) cidx[cr[c0 + l]] = (uint16_t)(c0 + l);
+        __threadfence();  // the source bounds and sides stored above, before they are read back
+        int64_t lastU = 0, lastD = 0;  // exit of the previous source of each side
+        for (int s0 = 0; s0 < nsrc; s0 += 64) {
+            const int s = s0 + l;
+            const bool v = s < nsrc;
+            int r = s;
+            for (int d = 0; v && d < TM_SRC && par[r] != r; ++d) r = par[r];
+            const int64_t ex = v ? cx[cidx[r]] - tF : 0;
+            const int64_t bnd = v ? map[TM_SB + s] : 0;
+            const bool isup = v && sside[s] != 0;
+            const bool isdn = v && !isup;
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const bool mine = side == 0 ? isup : isdn;
+                const uint64_t sm = ballot(mine);
+                if (!sm) continue;
+                int& cnt = side == 0 ? nup : ndn;
+                int64_t& last = side == 0 ? lastU : lastD;
+                // the previous source of this side: an earlier lane, else the carried one
+                const uint64_t before = sm & lanemask_lt();
+                const int64_t pe = shfl64(ex, before ? top64(before) : 0);
+                const bool has_prev = before != 0 || cnt > 0;
+                const int64_t prev = before ? pe : last;
+                const bool start = mine && (!has_prev || ex != prev);
+                const uint64_t stm = ballot(start);
+                const int run = cnt + __popcll(stm & (lanemask_lt() | (1ull << l))) - 1;
+                // a source whose next source of this side (in this group)
+                // starts a new run, or that is the group's last, writes its
+                // bound; a later group may still extend its run
+                const uint64_t after = sm & ~(lanemask_lt() | (1ull << l));
+                const bool ends = mine && (!after || ((stm >> ctz64(after)) & 1));
+                const int nr = cnt + __popcll(stm);
+                if (nr > TM_SIDE) {
+                    fail = TMF_RUNS;
+                    break;
+                }
+                if (start) map[run_word(side, 1, run)] = ex;
+                if (ends) map[run_word(side, 0, run)] = bnd;
+                cnt = nr;
+                last = readlane64(ex, top64(sm));
+            }
+            if (fail) break;
+        }
+        if (!fail && l == 0) {
+            map[TM_HDR + 1] = nup;
+            map[TM_HDR + 2] = ndn;
+            map[TM_HDR + 3] = tF;
+        }
+    }
+    if (l == 0) {
+        map[TM_HDR] = fail ? TM_NONE : TM_MAPPED;
+        g_add((uint64_t*)&ctl[fail ? 6 + fail : 5], 1ull);
+    }
+}
+
+// The exit of a tile from entry e, from its map's runs (two per lane and
+// side: runs l and 64 + l, bound and exit) and header values.
+static_assert(TM_SIDE == 128, "map_exit takes two runs per lane and side");
+__device__ __forceinline__ int64_t map_exit(int64_t e, int nup, int ndn, int64_t tF, int64_t ub0, int64_t ub1,
+                                            int64_t ue0, int64_t ue1, int64_t db0, int64_t db1, int64_t de0,
+                                            int64_t de1) {
+    const int l = lane_id();
+    // below U: the first run whose (upper) bound is >= e
+    const uint64_t u0 = ballot(l < nup && ub0 >= e), u1 = ballot(64 + l < nup && ub1 >= e);
+    if (u0) return readlane64(ue0, ctz64(u0));
+    if (u1) return readlane64(ue1, ctz64(u1));
+    // above U: the first run whose (lower) bound is <= e
+    const uint64_t d0 = ballot(l < ndn && db0 <= e), d1 = ballot(64 + l < ndn && db1 <= e);
+    if (d0) return readlane64(de0, ctz64(d0));
+    if (d1) return readlane64(de1, ctz64(d1));
+    return e - tF;  // in U: no sample in the tile
+}
+
+// The same for a map of at most 64 runs per side (one per lane; vu, vd:
+// the lanes that hold one), without branches: both searches, then selects.
+__device__ __forceinline__ int64_t map_exit64(int64_t e, uint64_t vu, uint64_t vd, int64_t tF, int64_t ub, int64_t ue,
+                                              int64_t db, int64_t de) {
+    const uint64_t u = vu & ballot(ub >= e), d = vd & ballot(db <= e);
+    const int64_t xu = readlane64(ue, u ? ctz64(u) : 0), xd = readlane64(de, d ? ctz64(d) : 0);
+    return u ? xu : (d ? xd : e - tF);
+}
+
+// One workgroup per trace with maps: wave 0 chains the entries through the
+// tile maps in tile order and publishes each tile's exit (the word the
+// resolve pass waits for); the other waves copy the maps' first words (the
+// first 64 runs of each side and the header) into an LDS ring ahead of it,
+// a few tiles per trip each.  It stops at the first tile without a map.
+constexpr int TC_RING = 64;  // (a power of two)
+constexpr int TC_WORDS = TM_HDR + 4;
+constexpr int TC_BLOCK = 1024;
+constexpr int TC_BATCH = 3;  // tiles per producer trip (15 producers: 45 tiles ahead at most)
+constexpr int TC_LOADS = (TC_WORDS + 63) / 64;
+constexpr int TC_CB = 8;     // tiles the chaining wave takes at a time
+static_assert((TC_BLOCK / 64 - 1) * TC_BATCH <= TC_RING && (TC_RING & (TC_RING - 1)) == 0 && TC_CB <= TC_RING,
+              "the ring holds every producer's batch");
+__global__ __launch_bounds__(TC_BLOCK) void k_tcompose(const Desc* __restrict__ desc, unsigned long long* ctl) {
+    __shared__ int64_t ring[TC_RING][TC_WORDS];
+    __shared__ int rdy[TC_RING];
+    __shared__ int s_cons, s_stop;
+    const Desc& D = desc[blockIdx.x];
+    if (!D.tmap) return;
+    const int tid = threadIdx.x, wv = tid >> 6, l = lane_id();
+    if (tid < TC_RING) rdy[tid] = -1;
+    if (tid == 0) {
+        s_cons = 0;
+        s_stop = 0;
+    }
+    __syncthreads();
+    const int nt = __builtin_amdgcn_readfirstlane((int)D.ntile);
+    const StatusView ts{D.tstat, (int64_t)nt};
+    if (wv == 0) {
+        // TC_CB tiles at a time: one read of their ready flags, then their
+        // words (lane b < TC_CB: tile b's header words; every lane: run l of
+        // each side, bound and exit), then their lookups one after another
+        int64_t e = 0;
+        int t = 0;
+        bool ok = true;
+        for (; ok && t < nt;) {
+            const int nb = (nt - t) < TC_CB ? (nt - t) : TC_CB;
+            LocalSpin sp_;
+            for (;;) {
+                const int rv = l < nb ? __hip_atomic_load(&rdy[(t + l) & (TC_RING - 1)], __ATOMIC_ACQUIRE,
+                                                          __HIP_MEMORY_SCOPE_WORKGROUP)
+                                      : t + l;
+                if (!ballot(rv != t + l)) break;
+                if (local_spin_abort(ctl, sp_)) {
+                    ok = false;
+                    break;
+                }
+            }
+            if (!ok) break;
+            int64_t h0 = 0, h1 = 0, h2 = 0, h3 = 0;  // lane b: tile t + b's header
+            if (l < nb) {
+                const int64_t* m = ring[(t + l) & (TC_RING - 1)];
+                h0 = m[TM_HDR];
+                h1 = m[TM_HDR + 1];
+                h2 = m[TM_HDR + 2];
+                h3 = m[TM_HDR + 3];
+            }
+            int64_t ub[TC_CB], ue[TC_CB], db[TC_CB], de[TC_CB];
+#pragma unroll
+            for (int b = 0; b < TC_CB; ++b) {
+                const int64_t* m = ring[(t + (b < nb ? b : 0)) & (TC_RING - 1)];
+                ub[b] = m[l];
+                ue[b] = m[64 + l];
+                db[b] = m[128 + l];
+                de[b] = m[192 + l];
+            }
+            int done = 0;
+#pragma unroll
+            for (int b = 0; b < TC_CB; ++b) {
+                if (b >= nb) break;
+                const int64_t st = readlane64(h0, b);
+                if (st != TM_MAPPED) break;
+                const int64_t nup = readlane64(h1, b), ndn = readlane64(h2, b), tF = readlane64(h3, b);
+                int64_t x;
+                if (nup <= 64 && ndn <= 64) {
+                    x = map_exit64(e, ballot(l < nup), ballot(l < ndn), tF, ub[b], ue[b], db[b], de[b]);
+                } else {  // more than 64 runs on a side: the rest from the map itself
+                    const SMP_GLOBAL int64_t* mp = tile_map(D, t + b);
+                    x = map_exit(e, (int)nup, (int)ndn, tF, ub[b], mp[TM_RUN_HI + l], ue[b], mp[TM_RUN_HI + 64 + l],
+                                 db[b], mp[TM_RUN_HI + 128 + l], de[b], mp[TM_RUN_HI + 192 + l]);
+                }
+                st_status(ts.at(W_XF, t + b), pack(x, 1));
+                e = x;
+                ++done;
+            }
+            t += done;
+            // relaxed: the slots' words are in registers, and a release here
+            // would also wait for the stores of the exits to reach memory
+            __hip_atomic_store(&s_cons, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (done < nb) break;  // a tile without a map
+        }
+        __hip_atomic_store(&s_stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (l == 0 && t > 0) g_add((uint64_t*)&ctl[6], (uint64_t)t);
+    } else {
+        const int np = TC_BLOCK / 64 - 1;
+        for (int t0 = (wv - 1) * TC_BATCH; t0 < nt; t0 += np * TC_BATCH) {
+            const int nb = (nt - t0) < TC_BATCH ? (nt - t0) : TC_BATCH;
+            // the batch's slots are free once their previous tiles have been consumed
+            LocalSpin sp_;
+            bool ok = true;
+            while (__hip_atomic_load(&s_cons, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= t0 + nb - 1 - TC_RING) {
+                if (__hip_atomic_load(&s_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ||
+                    local_spin_abort(ctl, sp_)) {
+                    ok = false;
+                    break;
+                }
+            }
+            if (!ok || __hip_atomic_load(&s_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+            int64_t v[TC_BATCH][TC_LOADS];
+#pragma unroll
+            for (int b = 0; b < TC_BATCH; ++b) {
+                const SMP_GLOBAL int64_t* src = tile_map(D, t0 + (b < nb ? b : 0));
+#pragma unroll
+                for (int w = 0; w < TC_LOADS; ++w) {
+                    const int i = w * 64 + l;
+                    v[b][w] = i < TC_WORDS ? src[i] : 0;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < TC_BATCH; ++b) {
+                if (b >= nb) break;
+                const int slot = (t0 + b) & (TC_RING - 1);
+#pragma unroll
+                for (int w = 0; w < TC_LOADS; ++w) {
+                    const int i = w * 64 + l;
+                    if (i < TC_WORDS) ring[slot][i] = v[b][w];
+                }
+                __hip_atomic_store(&rdy[slot], t0 + b, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+}
+
 // One workgroup per tile of TILE segments (tiles taken in ticket order, so a
 // tile's predecessors are always running or done): exclusive prefix sums and
 // the chain's entry and exit offset of every segment.
@@ -1061,7 +1591,7 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
     __shared__ int64_t w_sum[3][TWAVES];
     __shared__ int64_t s_pre[3];
     __shared__ int64_t w_peak[TWAVES], w_peakS[TWAVES];
-    __shared__ int w_left[TWAVES];
+    __shared__ int w_left[TWAVES], w_aux[TWAVES];
     __shared__ int64_t m_lo[TILE], m_hi[TILE], m_af[TILE], m_kf[TILE], m_ex[TILE];
     __shared__ int64_t m_R[TILE];  // sparse tiles: the footprint change before each segment
     __shared__ uint64_t w_tot[TWAVES], w_sim[TWAVES];  // valid lanes with TOTAL / SIM maps
@@ -1319,9 +1849,35 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
         }
         // the tile's entry, then [0, ft)
         int64_t e = 0;
+        // A tile with a map whose exit the map chain has not published (a
+        // tile before it has no map): the exit follows from the entry by one
+        // lookup and is published before the walk, so that the next tile
+        // need not wait for the walk.  The map loads while the entry is
+        // awaited.
+        const bool use_map = D.tmap && ft >= nval && k > 0;
+        int64_t mh = 0, mr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (use_map) {
+            const SMP_GLOBAL int64_t* mp = tile_map(D, k);
+            if (l < 4) mh = mp[TM_HDR + l];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                mr[w] = mp[w * 64 + l];
+                mr[4 + w] = mp[TM_RUN_HI + w * 64 + l];
+            }
+        }
         if (k > 0 && ok) ok = wait_word(ts.at(W_XF, k - 1), e, ctl);
+        if (use_map && ok && readlane64(mh, 0) == TM_MAPPED && !wstate(ld_status(ts.at(W_XF, k)))) {
+            const int64_t x = map_exit(e, (int)readlane64(mh, 1), (int)readlane64(mh, 2), readlane64(mh, 3), mr[0],
+                                       mr[4], mr[1], mr[5], mr[2], mr[6], mr[3], mr[7]);
+            st_status(ts.at(W_XF, k), pack(x, 1));
+        }
         const int64_t xb = ok ? walk(0, ft, e) : 0;
-        if (ft >= nval) st_status(ts.at(W_XF, k), pack(xb, 1));
+        if (ft >= nval) {
+            // a tile map may have published the exit already: it must agree
+            const uint64_t pw = ld_status(ts.at(W_XF, k));
+            if (wstate(pw) && unpack(pw) != xb && l == 0) g_or32(&D.scal->err, 4u);
+            st_status(ts.at(W_XF, k), pack(xb, 1));
+        }
         if (l == 0) {
             s_entry = e;
             if (!ok) {
@@ -1395,6 +1951,7 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
     uint32_t err = 0;
     int64_t pk = 0, pks = 0;
     bool left = false;  // left to the chain pass
+    bool auxonly = false;  // left to it for its copy and timer events only
     if (valid) {
         const int64_t af = sp[SP_AF * ns], ac = sp[SP_AC * ns];
         const int64_t mxf = sp[SP_MXF * ns], mnf = sp[SP_MNF * ns], mxp = sp[SP_MXP * ns], mnp = sp[SP_MNP * ns];
@@ -1409,14 +1966,16 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
             err = 2u;
         pk = F0 + mxf;
         if (j == ns - 1) *gp(&D.scal->final_F) = F0 + af;
-        // The chain pass's results, here, for a segment that holds no copy
-        // or timer events and whose entry takes no sample before its first
-        // forced event (the prefix's only sample is that event's, and from it
-        // on the chain is the summary pass's) or, without a forced event, no
-        // sample at all.  Every other segment is left to the chain pass.
+        // The chain pass's results, here, for a segment whose entry takes no
+        // sample before its first forced event (the prefix's only sample is
+        // that event's, and from it on the chain is the summary pass's) or,
+        // without a forced event, no sample at all.  Every other segment is
+        // left to the chain pass, and so are the copy and timer events of
+        // every segment (BFL_AUX: counted by the chain pass without a walk).
         const int fn = (int)sp[SP_FN * ns];
         const bool aux = (sp[SP_FLG * ns] & 4) != 0;
-        if (!aux && fn < 0 && ef >= lo && ef <= hi) {
+        const int64_t xaux = aux ? BFL_AUX : 0;
+        if (fn < 0 && ef >= lo && ef <= hi) {
             // no forced event and an entry inside the no-sample interval:
             // the segment takes no sample
             o[SP_BCNT * ns] = 0;
@@ -1424,11 +1983,11 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
             o[SP_BGI * ns] = 0;
             o[SP_BGP * ns] = 0;
             o[SP_LSV * ns] = 0;
-            o[SP_BFL * ns] = 0;
+            o[SP_BFL * ns] = xaux;
             SMP_GLOBAL uint64_t* mk = gp(D.mask) + j * NW;
 #pragma unroll
             for (int w = 0; w < NW; ++w) mk[w] = 0;
-        } else if (!aux && fn >= 0 && ef >= sp[SP_PLO * ns] && ef <= sp[SP_PHI * ns]) {
+        } else if (fn >= 0 && ef >= sp[SP_PLO * ns] && ef <= sp[SP_PHI * ns]) {
             const int64_t ffn = sp[SP_FFN * ns];
             int64_t gbest = 0, smax = ffn, lsrel;
             int gnode = -1;
@@ -1452,7 +2011,7 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
             o[SP_BGI * ns] = hg ? a + gnode : 0;
             o[SP_BGP * ns] = hg ? (int64_t)(uint32_t)record(D, a + gnode)[1] : 0;
             o[SP_LSV * ns] = P0 + lsrel;
-            o[SP_BFL * ns] = (hg ? 1 : 0) | 2;
+            o[SP_BFL * ns] = (hg ? 1 : 0) | 2 | xaux;
             // windows before the forced one hold no sample (as the summary
             // pass wrote); the forced window gains the forced sample
             gp(D.mask)[j * NW + (fn >> 6)] = (1ull << (fn & 63)) | (uint64_t)sp[SP_AMF * ns];
@@ -1460,28 +2019,33 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
             o[SP_BFL * ns] = BFL_CHAIN;
             left = true;
         }
+        auxonly = aux && !left;
     }
     if (ballot(err != 0) && l == 0) g_or32(&D.scal->err, 2u);
     const int nleft = __popcll(ballot(left));
+    const int naux = __popcll(ballot(auxonly));
     pk = wave_max(pk);
     pks = wave_max(pks);
     if (l == 0) {
         w_peak[wv] = pk;
         w_peakS[wv] = pks;
         w_left[wv] = nleft;
+        w_aux[wv] = naux;
     }
     __syncthreads();
     if (tid == 0) {
         int64_t p = 0, q = 0;
-        uint64_t c = 0;
+        uint64_t c = 0, ca = 0;
         for (int w = 0; w < TWAVES; ++w) {
             p = w_peak[w] > p ? w_peak[w] : p;
             q = w_peakS[w] > q ? w_peakS[w] : q;
             c += (uint64_t)w_left[w];
+            ca += (uint64_t)w_aux[w];
         }
         if (p > 0) g_max(&D.scal->peak_F, (int64_t)p);
         if (q > 0) g_max(&D.scal->peak_S, (int64_t)q);
         if (c) g_add((uint64_t*)&ctl[4], c);
+        if (ca) g_add((uint64_t*)&ctl[12], ca);
     }
 }
 
@@ -1526,41 +2090,51 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
     // take no sample before it, from the summary pass.  Each wave reads them
     // one segment ahead.
     const int pl_ = l < 5 ? SP_F0 + l : (l == 5 ? SP_FLG : (l < 18 ? SP_FN + (l - 6) : SP_F0));
+    // Segments the resolve pass left to this pass: BFL_CHAIN (follow the
+    // chain, and count the copy and timer events if any) or BFL_AUX (count
+    // those events only: the chain's results are the resolve pass's).
     // Only the segments the resolve pass left to this pass, grid-stride:
     // each wave reads the flags of its next 64 segments in one load (lane i:
     // the i-th) and visits the marked ones.
     const uint64_t stride = (uint64_t)gridDim.x * WAVES;
     uint64_t gb = (uint64_t)blockIdx.x * WAVES + wv, cur_gb = 0;
-    uint64_t pend = 0;  // marked segments among the last 64 read, not yet taken
-    int hint = 0;       // a trace at or before the wave's next segment
+    uint64_t pend = 0;   // marked segments among the last 64 read, not yet taken
+    uint64_t pwalk = 0;  // those of them whose chain is followed
+    int hint = 0;        // a trace at or before the wave's next segment
+    bool nwalk = false;  // (next_marked's segment is followed)
     auto next_marked = [&]() -> uint64_t {
         while (!pend) {
             if (gb >= nseg_total) return nseg_total;
             hint = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, hint, ntraces, gb));
             const uint64_t x = gb + (uint64_t)l * stride;
-            bool mk = false;
+            int64_t bf = 0;
             if (x < nseg_total) {
                 const Desc& Dx = desc[find_trace_seg(desc, hint, ntraces, x)];
-                mk = seg_val(Dx, SP_BFL, (int64_t)(x - Dx.seg_begin)) == BFL_CHAIN;
+                bf = seg_val(Dx, SP_BFL, (int64_t)(x - Dx.seg_begin));
             }
-            pend = ballot(mk);
+            pend = ballot((bf & (BFL_CHAIN | BFL_AUX)) != 0);
+            pwalk = ballot((bf & BFL_CHAIN) != 0);
             cur_gb = gb;
             gb += 64 * stride;
         }
         const int i = ctz64(pend);
         pend &= pend - 1;
+        nwalk = (pwalk >> i) & 1;
         return cur_gb + (uint64_t)i * stride;
     };
     uint64_t g = next_marked();
+    bool walk_next = nwalk;
     int64_t pv_next = 0;
-    ChainHead hd;  // the head of the wave's next segment
+    ChainHead hd;  // the head of the wave's next followed segment
     if (g < nseg_total) {
         const Desc& D0 = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g))];
         pv_next = seg_val(D0, pl_, (int64_t)(g - D0.seg_begin));
-        load_head(D0, (int64_t)(g - D0.seg_begin), hd);
+        if (walk_next) load_head(D0, (int64_t)(g - D0.seg_begin), hd);
     }
     for (uint64_t gn; g < nseg_total; g = gn) {
         gn = next_marked();
+        const bool walk = walk_next;
+        walk_next = nwalk;
         const int t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, cur_t, ntraces, g));
         if (t != cur_t && have_t && l == 0 && peakS > 0)
             g_max(&desc[cur_t].scal->peak_S, (int64_t)peakS);
@@ -1580,12 +2154,60 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
             const uint64_t gq = gn < nseg_total ? gn : g;
             const Desc& Dn = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, t, ntraces, gq))];
             pv_next = seg_val(Dn, pl_, (int64_t)(gq - Dn.seg_begin));
-            load_head(Dn, (int64_t)(gq - Dn.seg_begin), hd);
+            if (walk_next) load_head(Dn, (int64_t)(gq - Dn.seg_begin), hd);
         }
         const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), C0 = readlane64(pv, 2);
         const int64_t eF = readlane64(pv, 3), xF = readlane64(pv, 4);
         const int64_t flg = readlane64(pv, 5);
         const int fn = (int)readlane64(pv, 6);
+        // Copy volume (section 3.5: one Tc sample per multiple of Tc crossed by
+        // the cumulative copy bytes) and the timer split (section 2.1: Python
+        // time += quantum, native time += delay).  Only segments that hold such
+        // events re-read their records here.
+        if (flg & 4) {
+            // every window's words loaded before the first use
+            gu8_t* base = (gu8_t*)(D.ev + (size_t)a * 24);  // wave-uniform
+            uint64_t ad[NW];
+            uint32_t aln[NW], afw[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                gu8_t* p = record_addr(base, nv, w);
+                ad[w] = *(gu64_t*)p;
+                aln[w] = *(gu32_t*)(p + 12);
+                afw[w] = *(gu32_t*)(p + 16);
+            }
+            int64_t cc = C0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int k = w * 64 + l;
+                const int64_t delta = (int64_t)ad[w];
+                const uint32_t line = aln[w];
+                const uint32_t kind = (afw[w] >> 1) & 3;
+                const bool lok = k < nv && line < D.L;
+                const bool cp = lok && kind == 1 && delta >= 0 && delta < MAX_ABS_DELTA;
+                const bool tm = lok && kind == 2 && delta >= 0 && delta <= (int64_t)0xFFFFFFFFll;
+                const int64_t dc = cp ? delta : 0;
+                const int64_t sc_ = wave_incl_sum(dc) + cc;
+                cc = readlane64(sc_, 63);
+                if (cp || tm) {
+                    int64_t v0 = D.q, v1 = delta;
+                    if (cp) {
+                        const uint64_t cout = (uint64_t)sc_, cin = cout - (uint64_t)dc;
+                        uint64_t nsmp;
+                        if (D.tc_shift >= 0)
+                            nsmp = (cout >> D.tc_shift) - (cin >> D.tc_shift);
+                        else
+                            nsmp = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
+                        v0 = (int64_t)(nsmp * (uint64_t)D.Tc);
+                        v1 = dc;
+                    }
+                    aux_add(ac, D, (uint32_t)t, line, cp, v0, v1);
+                }
+            }
+        }
+
+        if (!walk) continue;  // (the chain's results are the resolve pass's)
+
         // The pointer of the summary pass's best growth sample after the forced
         // event, loaded now (it is the segment's best unless the walk below
         // finds a larger one before the forced event).
@@ -1644,52 +2266,6 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
                 cF = readlane64(f, 63);
                 cP = readlane64(p, 63);
                 chain_window<true>(f, p, T, cr, lsp, w, -1);
-            }
-        }
-
-        // Copy volume (section 3.5: one Tc sample per multiple of Tc crossed by
-        // the cumulative copy bytes) and the timer split (section 2.1: Python
-        // time += quantum, native time += delay).  Only segments that hold such
-        // events re-read their records here.
-        if (flg & 4) {
-            // every window's words loaded before the first use
-            gu8_t* base = (gu8_t*)(D.ev + (size_t)a * 24);  // wave-uniform
-            uint64_t ad[NW];
-            uint32_t aln[NW], afw[NW];
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                gu8_t* p = record_addr(base, nv, w);
-                ad[w] = *(gu64_t*)p;
-                aln[w] = *(gu32_t*)(p + 12);
-                afw[w] = *(gu32_t*)(p + 16);
-            }
-            int64_t cc = C0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const int k = w * 64 + l;
-                const int64_t delta = (int64_t)ad[w];
-                const uint32_t line = aln[w];
-                const uint32_t kind = (afw[w] >> 1) & 3;
-                const bool lok = k < nv && line < D.L;
-                const bool cp = lok && kind == 1 && delta >= 0 && delta < MAX_ABS_DELTA;
-                const bool tm = lok && kind == 2 && delta >= 0 && delta <= (int64_t)0xFFFFFFFFll;
-                const int64_t dc = cp ? delta : 0;
-                const int64_t sc_ = wave_incl_sum(dc) + cc;
-                cc = readlane64(sc_, 63);
-                if (cp || tm) {
-                    int64_t v0 = D.q, v1 = delta;
-                    if (cp) {
-                        const uint64_t cout = (uint64_t)sc_, cin = cout - (uint64_t)dc;
-                        uint64_t nsmp;
-                        if (D.tc_shift >= 0)
-                            nsmp = (cout >> D.tc_shift) - (cin >> D.tc_shift);
-                        else
-                            nsmp = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
-                        v0 = (int64_t)(nsmp * (uint64_t)D.Tc);
-                        v1 = dc;
-                    }
-                    aux_add(ac, D, (uint32_t)t, line, cp, v0, v1);
-                }
             }
         }
 
@@ -2428,6 +3004,13 @@ int track_grid_limit() { return occupancy_grid((const void*)k_track, 256); }
 hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, unsigned long long* ctl, hipStream_t s) {
     const uint64_t blocks = (total_bytes + (1ull << 16) - 1) >> 16;
     k_clear<<<dim3((unsigned)(blocks ? blocks : 1)), dim3(256), 0, s>>>(desc, ntraces, total_bytes, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_tmap(const Desc* desc, int ntraces, uint64_t ntile_total, unsigned long long* ctl, hipStream_t s) {
+    if (ntile_total == 0) return hipSuccess;
+    k_tmap<<<dim3((unsigned)ntile_total), dim3(64), 0, s>>>(desc, ntraces, ctl);
+    k_tcompose<<<dim3((unsigned)ntraces), dim3(TC_BLOCK), 0, s>>>(desc, ctl);
     return hipGetLastError();
 }
 

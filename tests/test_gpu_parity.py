@@ -235,6 +235,61 @@ def test_multi_tile_chains(sampler):
         check_batch(sampler, cases[i:i + 4])
 
 
+def tile_map_cases():
+    """Traces of several tiles (512 segments of 512 events) whose segments
+    move the footprint far less than T, so that tiles get tile maps: a
+    config-5 mix (a few samples per tile), the same at thresholds where only
+    some segments move less than T, the same with one allocation above 2T in
+    its third tile (a segment every entry samples in: that tile gets no map
+    and the tiles after it are chained by the resolve pass), a drift, and a
+    monotone trace whose every node is a new maximum (more chains than a map
+    follows: no map)."""
+    n = 5 * 512 * 512 + 1234
+    ev, kw = tg.config5(seed=51, n=n)
+    c5 = dict(copy_threshold=kw["copy_threshold"], num_lines=kw["num_lines"], quantum_us=kw["quantum_us"])
+    out = [(f"c5mix T{T >> 20}M", ev, dict(threshold=T, **c5)) for T in (64 * tg.MiB, 16 * tg.MiB, 4 * tg.MiB)]
+    big = ev.copy()
+    i = 2 * 512 * 512 + 4321
+    big["delta"][i] = 200 * tg.MiB
+    big["flags"][i] = 0
+    out.append(("c5mix forced", big, dict(threshold=64 * tg.MiB, **c5)))
+    rng = np.random.default_rng(23)
+    drift = np.zeros(3 * 512 * 512 + 77, dtype=tg.EVENT_DTYPE)
+    drift["delta"] = rng.integers(-100, 101, drift.shape[0])
+    drift["ptr"] = np.arange(1, drift.shape[0] + 1)
+    drift["line"] = rng.integers(0, 5, drift.shape[0])
+    for T in (3_000, 30_000):
+        out.append((f"drift T{T}", drift, dict(threshold=T, num_lines=5)))
+    mono = np.zeros(2 * 512 * 512 + 9, dtype=tg.EVENT_DTYPE)
+    mono["delta"] = 1
+    mono["ptr"] = np.arange(1, mono.shape[0] + 1)
+    out.append(("mono T1e6", mono, dict(threshold=10 ** 6, num_lines=1)))
+    return out
+
+
+def test_tile_maps(sampler):
+    """Tile maps forced on for every multi-tile trace: each trace alone (with
+    the map counters), then all of them in one launch."""
+    say("tile maps")
+    cases = tile_map_cases()
+    try:
+        sampler.set_tuning(tile_map_tiles=1)
+        mapped = {}
+        for case in cases:
+            check_batch(sampler, [case])
+            c = sampler.last_counters()
+            mapped[case[0]] = (c[5], c[6])
+            say(f"  {case[0]}: {c[5]} tiles mapped, {c[6]} chained through maps")
+        ntile = -(-cases[0][1].shape[0] // (512 * 512))
+        assert mapped["c5mix T64M"] == (ntile, ntile)
+        assert mapped["c5mix forced"][0] == ntile - 1 and mapped["c5mix forced"][1] == 2
+        # (its two full tiles get no map; the short last one may)
+        assert mapped["mono T1e6"][0] <= 1 and mapped["mono T1e6"][1] == 0
+        check_batch(sampler, cases)
+    finally:
+        sampler.set_tuning()
+
+
 def test_copy_and_timer_mix(sampler):
     say("copy + timer mix")
     ev = tg.mix(9, 300_000, num_lines=1000, zipf_s=1.05, copy_frac=0.10, timer_frac=0.01)
