@@ -1,10 +1,12 @@
 """Autotuner of the sampler's launch parameters (``Sampler.set_tuning``).
 
 The parameters trade work between the passes without changing any result:
-how many distinct chains the summary pass follows through a segment before
-it leaves the segment to be followed from its actual entry (``chain_cap``),
-and the grid sizes of the two grid-stride passes over the records
-(``chain_grid``, ``emit_grid``).  For one workload (a callable that submits
+whether long traces get tile maps before the resolve pass
+(``tile_map_tiles``: the library default, or never, for workloads whose tiles
+never qualify and would only pay for the check), how many distinct chains
+the summary pass follows through a segment before it leaves the segment to
+be followed from its actual entry (``chain_cap``), and the grid sizes of the
+two grid-stride passes over the records (``chain_grid``, ``emit_grid``).  For one workload (a callable that submits
 a batch to the sampler and runs it), the tuner times candidates on the GPU
 one parameter at a time, keeps the fastest, and caches the choice in a JSON
 file keyed by (GPU architecture, compute-unit count, size class), so a later
@@ -21,8 +23,9 @@ import math
 import os
 import statistics
 
-DEFAULT = {"chain_cap": 16, "chain_grid": 0, "emit_grid": 0, "graphs": 1}
+DEFAULT = {"chain_cap": 16, "chain_grid": 0, "emit_grid": 0, "graphs": 1, "tile_map_tiles": 0}
 CHAIN_CAPS = (4, 8, 16, 32, 64)
+TILE_MAPS_NEVER = 0xFFFFFFFF
 GRID_FACTORS = (0.5, 1, 2)
 
 
@@ -81,6 +84,8 @@ def candidates(param, defaults):
     default (as many workgroups as it holds at once)."""
     if param == "chain_cap":
         return list(CHAIN_CAPS)
+    if param == "tile_map_tiles":
+        return [0, TILE_MAPS_NEVER]
     base = defaults[param]
     return sorted({max(1, int(round(base * f))) for f in GRID_FACTORS})
 
@@ -104,15 +109,15 @@ def tune(sampler, workload, size, *, cache_path=None, reps=3, key=None, log=None
     tried = {}
 
     def name(t):
-        return ",".join(f"{k}={t[k]}" for k in ("chain_cap", "chain_grid", "emit_grid"))
+        return ",".join(f"{k}={t[k]}" for k in ("tile_map_tiles", "chain_cap", "chain_grid", "emit_grid"))
 
     best_ms = measure(sampler, workload, best, reps)
     tried[name(best)] = round(best_ms, 4)
-    for param in ("chain_cap", "emit_grid", "chain_grid"):
+    for param in ("tile_map_tiles", "chain_cap", "emit_grid", "chain_grid"):
         for v in candidates(param, resolved):
             cand = dict(best)
             cand[param] = v
-            if param != "chain_cap" and v == resolved[param]:
+            if param in ("chain_grid", "emit_grid") and v == resolved[param]:
                 cand[param] = 0  # the default itself
             if name(cand) in tried:
                 continue

@@ -95,7 +95,8 @@ struct Scalars {
     uint64_t H;
     uint32_t err;      // bit 0: malformed event, bit 1: overflow, bits 2-3: internal fault
     uint32_t pad;
-    uint64_t reserved[2];
+    uint64_t tmap_done;  // tiles whose tile-map wave has finished (the last one chains them)
+    uint64_t reserved;
 };
 
 // Per-trace descriptor, built by the host for every launch.

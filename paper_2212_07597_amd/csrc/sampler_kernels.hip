@@ -1044,8 +1044,8 @@ __device__ __forceinline__ uint64_t range_mask(int w, int lo, int hi) {
 // ------------------------------------------------------------ tile maps
 //
 // A tile whose segments each move less than T (every SIM map holds at least
-// T - 1 + 1 entries in its no-sample interval) lets an entry sample at most
-// once per segment.  For such a tile the chain map over all entry offsets of
+// T entries in its no-sample interval) lets an entry sample at most once per
+// segment.  For such a tile the chain map over all entry offsets of
 // the whole tile is computed by one wave, segment by segment, before the
 // resolve pass (section 3.2's rule, restated over entries as in the segment
 // analysis):
@@ -1062,25 +1062,27 @@ __device__ __forceinline__ uint64_t range_mask(int w, int lo, int hi) {
 // Source intervals started at maxima lie below U and grow upward in start
 // order; those started at minima lie above it and grow downward.  Runs of
 // consecutive sources that end at the same reference are written as (bound,
-// exit) pairs, so that the tile's exit for any entry is one search.  One
-// workgroup then chains each trace's tile entries through the maps in tile
-// order and publishes every tile's exit, so that the resolve pass no longer
-// waits for the previous tile's walk.  A tile that does not qualify, or whose
-// chains or runs exceed the capacities below, gets no map; the tiles from it
-// on are chained by the resolve pass's walks as before.
+// exit) pairs, so that the tile's exit for any entry is one search.  The
+// last of a trace's tile waves to finish then chains the trace's tile entries
+// through the maps in tile order and publishes every tile's exit, so that the
+// resolve pass no longer waits for the previous tile's walk.  A tile that
+// does not qualify, or whose chains or runs exceed the capacities below, gets
+// no map; the resolve pass chains the tiles from it on, by a map lookup where
+// a tile has one and by its walk where not.
 
 constexpr int TM_CAP = 1024;   // chains followed at once
 constexpr int TM_SRC = 2048;   // source intervals per tile
 constexpr int TM_SIDE = 128;   // runs per side (below and above U)
 constexpr int64_t TM_WORDS = (int64_t)(TILE_MAP_BYTES / 8);
 // Run r of side s (0: below U, 1: above) has its bound at run_word(s, 0, r)
-// and its exit at run_word(s, 1, r): the first 64 runs of both sides and the
-// header (state, runs below, runs above, tile change) lie in words 0-259, the
-// words the map chain copies; runs 64-127 follow at word 512.
+// and its exit at run_word(s, 1, r).  Runs l < 64 of both sides lie in words
+// 4l..4l+3 (bound and exit below U, bound and exit above: one lane's words,
+// two 16-byte loads), followed by the header (state, runs below, runs above,
+// tile change) at word 256; runs 64-127 follow at word 512 the same way.
 constexpr int TM_HDR = 256;
 constexpr int TM_RUN_HI = 512;
 __device__ __forceinline__ int run_word(int side, int which, int r) {
-    return (r < 64 ? 0 : TM_RUN_HI) + side * 128 + which * 64 + (r & 63);
+    return (r < 64 ? 0 : TM_RUN_HI) + 4 * (r & 63) + 2 * side + which;
 }
 constexpr int TM_SB = 1024;    // source bounds (scratch while the map is built)
 constexpr int TM_SD = 3072;    // source sides, one byte each: 1 = below U (scratch)
@@ -1093,6 +1095,11 @@ enum { TMF_QUALIFY = 1, TMF_SOURCES, TMF_CHAINS, TMF_RUNS };
 // per event needed here).
 __device__ __forceinline__ SMP_GLOBAL int64_t* tile_map(const Desc& D, int64_t k) {
     return gp((int64_t*)D.tracked) + k * TM_WORDS;
+}
+// A word of a map that another wave reads in the same launch: stored through
+// to memory, as the look-back words are.
+__device__ __forceinline__ void st_map(SMP_GLOBAL int64_t* p, int64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // First node of a segment (relative prefixes f) whose prefix is >= thr (GE)
@@ -1124,6 +1131,106 @@ __device__ __forceinline__ void first_node2(const int64_t (&f)[NW], int64_t t1, 
         k1 = m1[w] ? w * 64 + ctz64(m1[w]) : k1;
         k2 = m2[w] ? w * 64 + ctz64(m2[w]) : k2;
     }
+}
+
+// The exit of a tile from entry e, from its map's runs (two per lane and
+// side: runs l and 64 + l, bound and exit) and header values.
+static_assert(TM_SIDE == 128, "map_exit takes two runs per lane and side");
+__device__ __forceinline__ int64_t map_exit(int64_t e, int nup, int ndn, int64_t tF, int64_t ub0, int64_t ub1,
+                                            int64_t ue0, int64_t ue1, int64_t db0, int64_t db1, int64_t de0,
+                                            int64_t de1) {
+    const int l = lane_id();
+    // below U: the first run whose (upper) bound is >= e
+    const uint64_t u0 = ballot(l < nup && ub0 >= e), u1 = ballot(64 + l < nup && ub1 >= e);
+    if (u0) return readlane64(ue0, ctz64(u0));
+    if (u1) return readlane64(ue1, ctz64(u1));
+    // above U: the first run whose (lower) bound is <= e
+    const uint64_t d0 = ballot(l < ndn && db0 <= e), d1 = ballot(64 + l < ndn && db1 <= e);
+    if (d0) return readlane64(de0, ctz64(d0));
+    if (d1) return readlane64(de1, ctz64(d1));
+    return e - tF;  // in U: no sample in the tile
+}
+
+// The same for a map of at most 64 runs per side (one per lane; vu, vd:
+// the lanes that hold one), without branches: both searches, then selects.
+__device__ __forceinline__ int64_t map_exit64(int64_t e, uint64_t vu, uint64_t vd, int64_t tF, int64_t ub, int64_t ue,
+                                              int64_t db, int64_t de) {
+    const uint64_t u = vu & ballot(ub >= e), d = vd & ballot(db <= e);
+    const int64_t xu = readlane64(ue, u ? ctz64(u) : 0), xd = readlane64(de, d ? ctz64(d) : 0);
+    return u ? xu : (d ? xd : e - tF);
+}
+
+// The tile entries of a trace, chained through the maps in tile order by one
+// wave (tile 0's entry is 0): each tile's exit is published as the word the
+// resolve pass waits for.  It stops at the first tile without a map.  Tiles
+// are taken TC_CB at a time, the next ones' words loading while these are
+// looked up.
+constexpr int TC_CB = 8;
+__device__ void chain_maps(const Desc& D, unsigned long long* ctl) {
+    const int l = lane_id();
+    const int nt = __builtin_amdgcn_readfirstlane((int)D.ntile);
+    const StatusView ts{D.tstat, (int64_t)nt};
+    // lane l: runs l of both sides (bound, exit below U; bound, exit above);
+    // lanes 0-3: the header
+    auto load = [&](int t0, int64_t (&w)[TC_CB][4], int64_t (&h)[TC_CB]) {
+#pragma unroll
+        for (int b = 0; b < TC_CB; ++b) {
+            const SMP_GLOBAL int64_t* m = tile_map(D, t0 + b < nt ? t0 + b : nt - 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[b][q] = m[4 * l + q];
+            h[b] = m[TM_HDR + (l & 3)];
+        }
+    };
+    int64_t nw[TC_CB][4], nh[TC_CB];
+    load(0, nw, nh);
+    int64_t e = 0;
+    int t = 0;
+    for (; t < nt;) {
+        int64_t cw[TC_CB][4], ch[TC_CB];
+#pragma unroll
+        for (int b = 0; b < TC_CB; ++b) {
+            ch[b] = nh[b];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cw[b][q] = nw[b][q];
+        }
+        if (t + TC_CB < nt) load(t + TC_CB, nw, nh);
+        const int nb = (nt - t) < TC_CB ? (nt - t) : TC_CB;
+        // everything that does not depend on the entry first: the tiles that
+        // can be chained, their runs and tile changes
+        int nm = 0;
+        int64_t nup[TC_CB], ndn[TC_CB], tFs[TC_CB];
+        uint64_t vu[TC_CB], vd[TC_CB];
+#pragma unroll
+        for (int b = 0; b < TC_CB; ++b) {
+            nm += (b == nm && b < nb && readlane64(ch[b], 0) == TM_MAPPED) ? 1 : 0;
+            nup[b] = readlane64(ch[b], 1);
+            ndn[b] = readlane64(ch[b], 2);
+            tFs[b] = readlane64(ch[b], 3);
+            vu[b] = ballot(l < nup[b]);
+            vd[b] = ballot(l < ndn[b]);
+        }
+        int done = 0;
+        int64_t xs = 0;  // lane b: the exit of tile t + b
+#pragma unroll
+        for (int b = 0; b < TC_CB; ++b) {
+            if (b >= nm) break;
+            int64_t x;
+            if (nup[b] <= 64 && ndn[b] <= 64) {
+                x = map_exit64(e, vu[b], vd[b], tFs[b], cw[b][0], cw[b][1], cw[b][2], cw[b][3]);
+            } else {  // more than 64 runs on a side: the rest from the map itself
+                const SMP_GLOBAL int64_t* m = tile_map(D, t + b) + TM_RUN_HI + 4 * l;
+                x = map_exit(e, (int)nup[b], (int)ndn[b], tFs[b], cw[b][0], m[0], cw[b][1], m[1], cw[b][2], m[2],
+                             cw[b][3], m[3]);
+            }
+            xs = l == b ? x : xs;
+            e = x;
+            ++done;
+        }
+        if (l < done) st_status(ts.at(W_XF, t + l), pack(xs, 1));
+        t += done;
+        if (done < nb) break;  // a tile without a map
+    }
+    if (l == 0 && t > 0) g_add((uint64_t*)&ctl[6], (uint64_t)t);
 }
 
 // One wave per tile (grid: every tile of the launch; tiles of traces without
@@ -1159,16 +1266,9 @@ __global__ __launch_bounds__(64) void k_tmap(const Desc* __restrict__ desc, int 
         const int64_t fl_ = v ? sp[SP_FLG * ns + s] : 0;
         if (ballot(v && ((fl_ & 3) != MAP_SIM || hi < lo || hi - lo < T - 1))) ok = false;
     }
-    if (!ok) {
-        if (l == 0) {
-            map[TM_HDR] = TM_NONE;
-            g_add((uint64_t*)&ctl[6 + TMF_QUALIFY], 1ull);
-        }
-        return;
-    }
     for (int i = l; i < SEG; i += 64) claim[i] = 0;
     int nch = 0, nsrc = 0;
-    int fail = 0;  // cause, 0 while the map holds
+    int fail = ok ? 0 : TMF_QUALIFY;  // cause, 0 while the map holds
     int64_t Umax = 0, Umin = 0, carry = 0;  // running extremes (from the tile start), footprint change so far
     // segments g..g+63, one per lane: offset, no-sample bounds and extremes in tile coordinates
     int64_t gR = 0, gL = 0, gH = 0, gX = 0, gN = 0;
@@ -1341,7 +1441,7 @@ __global__ __launch_bounds__(64) void k_tmap(const Desc* __restrict__ desc, int 
     // are the ones the copy needs, issued a whole step earlier)
     const int64_t j0 = k * TILE;
     int64_t fn[NW];
-    load_kept(D, j0, fn);
+    if (!fail) load_kept(D, j0, fn);
     for (int s = 0; s < nval && !fail; ++s) {
         int64_t f[NW];
 #pragma unroll
@@ -1356,7 +1456,8 @@ __global__ __launch_bounds__(64) void k_tmap(const Desc* __restrict__ desc, int 
         for (int i = l; i < nsrc; i += 64) cidx[i] = 0;
         for (int c0 = 0; c0 < nch; c0 += 64)
             if (c0 + l < nch) cidx[cr[c0 + l]] = (uint16_t)(c0 + l);
-        __threadfence();  // the source bounds and sides stored above, before they are read back
+        // the source bounds and sides stored above (by this wave), before they are read back
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         int64_t lastU = 0, lastD = 0;  // exit of the previous source of each side
         for (int s0 = 0; s0 < nsrc; s0 += 64) {
             const int s = s0 + l;
@@ -1392,182 +1493,33 @@ __global__ __launch_bounds__(64) void k_tmap(const Desc* __restrict__ desc, int 
                     fail = TMF_RUNS;
                     break;
                 }
-                if (start) map[run_word(side, 1, run)] = ex;
-                if (ends) map[run_word(side, 0, run)] = bnd;
+                if (start) st_map(map + run_word(side, 1, run), ex);
+                if (ends) st_map(map + run_word(side, 0, run), bnd);
                 cnt = nr;
                 last = readlane64(ex, top64(sm));
             }
             if (fail) break;
         }
         if (!fail && l == 0) {
-            map[TM_HDR + 1] = nup;
-            map[TM_HDR + 2] = ndn;
-            map[TM_HDR + 3] = tF;
+            st_map(map + TM_HDR + 1, nup);
+            st_map(map + TM_HDR + 2, ndn);
+            st_map(map + TM_HDR + 3, tF);
         }
     }
     if (l == 0) {
-        map[TM_HDR] = fail ? TM_NONE : TM_MAPPED;
+        st_map(map + TM_HDR, fail ? TM_NONE : TM_MAPPED);
         g_add((uint64_t*)&ctl[fail ? 6 + fail : 5], 1ull);
     }
-}
-
-// The exit of a tile from entry e, from its map's runs (two per lane and
-// side: runs l and 64 + l, bound and exit) and header values.
-static_assert(TM_SIDE == 128, "map_exit takes two runs per lane and side");
-__device__ __forceinline__ int64_t map_exit(int64_t e, int nup, int ndn, int64_t tF, int64_t ub0, int64_t ub1,
-                                            int64_t ue0, int64_t ue1, int64_t db0, int64_t db1, int64_t de0,
-                                            int64_t de1) {
-    const int l = lane_id();
-    // below U: the first run whose (upper) bound is >= e
-    const uint64_t u0 = ballot(l < nup && ub0 >= e), u1 = ballot(64 + l < nup && ub1 >= e);
-    if (u0) return readlane64(ue0, ctz64(u0));
-    if (u1) return readlane64(ue1, ctz64(u1));
-    // above U: the first run whose (lower) bound is <= e
-    const uint64_t d0 = ballot(l < ndn && db0 <= e), d1 = ballot(64 + l < ndn && db1 <= e);
-    if (d0) return readlane64(de0, ctz64(d0));
-    if (d1) return readlane64(de1, ctz64(d1));
-    return e - tF;  // in U: no sample in the tile
-}
-
-// The same for a map of at most 64 runs per side (one per lane; vu, vd:
-// the lanes that hold one), without branches: both searches, then selects.
-__device__ __forceinline__ int64_t map_exit64(int64_t e, uint64_t vu, uint64_t vd, int64_t tF, int64_t ub, int64_t ue,
-                                              int64_t db, int64_t de) {
-    const uint64_t u = vu & ballot(ub >= e), d = vd & ballot(db <= e);
-    const int64_t xu = readlane64(ue, u ? ctz64(u) : 0), xd = readlane64(de, d ? ctz64(d) : 0);
-    return u ? xu : (d ? xd : e - tF);
-}
-
-// One workgroup per trace with maps: wave 0 chains the entries through the
-// tile maps in tile order and publishes each tile's exit (the word the
-// resolve pass waits for); the other waves copy the maps' first words (the
-// first 64 runs of each side and the header) into an LDS ring ahead of it,
-// a few tiles per trip each.  It stops at the first tile without a map.
-constexpr int TC_RING = 64;  // (a power of two)
-constexpr int TC_WORDS = TM_HDR + 4;
-constexpr int TC_BLOCK = 1024;
-constexpr int TC_BATCH = 3;  // tiles per producer trip (15 producers: 45 tiles ahead at most)
-constexpr int TC_LOADS = (TC_WORDS + 63) / 64;
-constexpr int TC_CB = 8;     // tiles the chaining wave takes at a time
-static_assert((TC_BLOCK / 64 - 1) * TC_BATCH <= TC_RING && (TC_RING & (TC_RING - 1)) == 0 && TC_CB <= TC_RING,
-              "the ring holds every producer's batch");
-__global__ __launch_bounds__(TC_BLOCK) void k_tcompose(const Desc* __restrict__ desc, unsigned long long* ctl) {
-    __shared__ int64_t ring[TC_RING][TC_WORDS];
-    __shared__ int rdy[TC_RING];
-    __shared__ int s_cons, s_stop;
-    const Desc& D = desc[blockIdx.x];
-    if (!D.tmap) return;
-    const int tid = threadIdx.x, wv = tid >> 6, l = lane_id();
-    if (tid < TC_RING) rdy[tid] = -1;
-    if (tid == 0) {
-        s_cons = 0;
-        s_stop = 0;
-    }
-    __syncthreads();
-    const int nt = __builtin_amdgcn_readfirstlane((int)D.ntile);
-    const StatusView ts{D.tstat, (int64_t)nt};
-    if (wv == 0) {
-        // TC_CB tiles at a time: one read of their ready flags, then their
-        // words (lane b < TC_CB: tile b's header words; every lane: run l of
-        // each side, bound and exit), then their lookups one after another
-        int64_t e = 0;
-        int t = 0;
-        bool ok = true;
-        for (; ok && t < nt;) {
-            const int nb = (nt - t) < TC_CB ? (nt - t) : TC_CB;
-            LocalSpin sp_;
-            for (;;) {
-                const int rv = l < nb ? __hip_atomic_load(&rdy[(t + l) & (TC_RING - 1)], __ATOMIC_ACQUIRE,
-                                                          __HIP_MEMORY_SCOPE_WORKGROUP)
-                                      : t + l;
-                if (!ballot(rv != t + l)) break;
-                if (local_spin_abort(ctl, sp_)) {
-                    ok = false;
-                    break;
-                }
-            }
-            if (!ok) break;
-            int64_t h0 = 0, h1 = 0, h2 = 0, h3 = 0;  // lane b: tile t + b's header
-            if (l < nb) {
-                const int64_t* m = ring[(t + l) & (TC_RING - 1)];
-                h0 = m[TM_HDR];
-                h1 = m[TM_HDR + 1];
-                h2 = m[TM_HDR + 2];
-                h3 = m[TM_HDR + 3];
-            }
-            int64_t ub[TC_CB], ue[TC_CB], db[TC_CB], de[TC_CB];
-#pragma unroll
-            for (int b = 0; b < TC_CB; ++b) {
-                const int64_t* m = ring[(t + (b < nb ? b : 0)) & (TC_RING - 1)];
-                ub[b] = m[l];
-                ue[b] = m[64 + l];
-                db[b] = m[128 + l];
-                de[b] = m[192 + l];
-            }
-            int done = 0;
-#pragma unroll
-            for (int b = 0; b < TC_CB; ++b) {
-                if (b >= nb) break;
-                const int64_t st = readlane64(h0, b);
-                if (st != TM_MAPPED) break;
-                const int64_t nup = readlane64(h1, b), ndn = readlane64(h2, b), tF = readlane64(h3, b);
-                int64_t x;
-                if (nup <= 64 && ndn <= 64) {
-                    x = map_exit64(e, ballot(l < nup), ballot(l < ndn), tF, ub[b], ue[b], db[b], de[b]);
-                } else {  // more than 64 runs on a side: the rest from the map itself
-                    const SMP_GLOBAL int64_t* mp = tile_map(D, t + b);
-                    x = map_exit(e, (int)nup, (int)ndn, tF, ub[b], mp[TM_RUN_HI + l], ue[b], mp[TM_RUN_HI + 64 + l],
-                                 db[b], mp[TM_RUN_HI + 128 + l], de[b], mp[TM_RUN_HI + 192 + l]);
-                }
-                st_status(ts.at(W_XF, t + b), pack(x, 1));
-                e = x;
-                ++done;
-            }
-            t += done;
-            // relaxed: the slots' words are in registers, and a release here
-            // would also wait for the stores of the exits to reach memory
-            __hip_atomic_store(&s_cons, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (done < nb) break;  // a tile without a map
-        }
-        __hip_atomic_store(&s_stop, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (l == 0 && t > 0) g_add((uint64_t*)&ctl[6], (uint64_t)t);
-    } else {
-        const int np = TC_BLOCK / 64 - 1;
-        for (int t0 = (wv - 1) * TC_BATCH; t0 < nt; t0 += np * TC_BATCH) {
-            const int nb = (nt - t0) < TC_BATCH ? (nt - t0) : TC_BATCH;
-            // the batch's slots are free once their previous tiles have been consumed
-            LocalSpin sp_;
-            bool ok = true;
-            while (__hip_atomic_load(&s_cons, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= t0 + nb - 1 - TC_RING) {
-                if (__hip_atomic_load(&s_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ||
-                    local_spin_abort(ctl, sp_)) {
-                    ok = false;
-                    break;
-                }
-            }
-            if (!ok || __hip_atomic_load(&s_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
-            int64_t v[TC_BATCH][TC_LOADS];
-#pragma unroll
-            for (int b = 0; b < TC_BATCH; ++b) {
-                const SMP_GLOBAL int64_t* src = tile_map(D, t0 + (b < nb ? b : 0));
-#pragma unroll
-                for (int w = 0; w < TC_LOADS; ++w) {
-                    const int i = w * 64 + l;
-                    v[b][w] = i < TC_WORDS ? src[i] : 0;
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < TC_BATCH; ++b) {
-                if (b >= nb) break;
-                const int slot = (t0 + b) & (TC_RING - 1);
-#pragma unroll
-                for (int w = 0; w < TC_LOADS; ++w) {
-                    const int i = w * 64 + l;
-                    if (i < TC_WORDS) ring[slot][i] = v[b][w];
-                }
-                __hip_atomic_store(&rdy[slot], t0 + b, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-        }
+    // The last of the trace's tile waves chains its tiles.  The map's words
+    // were stored through to memory (agent-scope stores): it is counted once
+    // they are complete, and the last wave drops any stale copies of other
+    // tiles' words from its caches before it reads them.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    uint64_t done = 0;
+    if (l == 0) done = g_add_rtn(&D.scal->tmap_done, 1ull);
+    if (readlaneu64(done, 0) == D.ntile - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        chain_maps(D, ctl);
     }
 }
 
@@ -1861,8 +1813,8 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
             if (l < 4) mh = mp[TM_HDR + l];
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-                mr[w] = mp[w * 64 + l];
-                mr[4 + w] = mp[TM_RUN_HI + w * 64 + l];
+                mr[w] = mp[4 * l + w];
+                mr[4 + w] = mp[TM_RUN_HI + 4 * l + w];
             }
         }
         if (k > 0 && ok) ok = wait_word(ts.at(W_XF, k - 1), e, ctl);
@@ -3010,7 +2962,6 @@ hipError_t launch_clear(const Desc* desc, int ntraces, uint64_t total_bytes, uns
 hipError_t launch_tmap(const Desc* desc, int ntraces, uint64_t ntile_total, unsigned long long* ctl, hipStream_t s) {
     if (ntile_total == 0) return hipSuccess;
     k_tmap<<<dim3((unsigned)ntile_total), dim3(64), 0, s>>>(desc, ntraces, ctl);
-    k_tcompose<<<dim3((unsigned)ntraces), dim3(TC_BLOCK), 0, s>>>(desc, ctl);
     return hipGetLastError();
 }
 

@@ -8,7 +8,8 @@ from paper_2212_07597_amd import autotune
 
 class FakeSampler:
     """Stands in for Sampler: the 'kernel time' of a run is a function of
-    the tuning, smallest at chain_cap 8 and an emit grid of 2x the default."""
+    the tuning, smallest at chain_cap 8, an emit grid of 2x the default and
+    tile maps off."""
 
     DEFAULT_GRID = 1024
 
@@ -16,9 +17,10 @@ class FakeSampler:
         self.t = dict(autotune.DEFAULT)
         self.runs = 0
 
-    def set_tuning(self, chain_cap=16, chain_grid=0, emit_grid=0, graphs=1):
+    def set_tuning(self, chain_cap=16, chain_grid=0, emit_grid=0, graphs=1, tile_map_tiles=0):
         assert 1 <= chain_cap <= 64
-        self.t = dict(chain_cap=chain_cap, chain_grid=chain_grid, emit_grid=emit_grid, graphs=graphs)
+        self.t = dict(chain_cap=chain_cap, chain_grid=chain_grid, emit_grid=emit_grid, graphs=graphs,
+                      tile_map_tiles=tile_map_tiles)
 
     def get_tuning(self):
         t = dict(self.t)
@@ -29,6 +31,7 @@ class FakeSampler:
     def last_timing(self):
         t = self.get_tuning()
         ms = 1.0 + abs(t["chain_cap"] - 8) / 100 + abs(t["emit_grid"] - 2048) / 1e4 + abs(t["chain_grid"] - 1024) / 1e5
+        ms += 0.01 if t["tile_map_tiles"] != autotune.TILE_MAPS_NEVER else 0.0
         return ms, ms + 0.1
 
 
@@ -43,6 +46,7 @@ def test_search_finds_the_fastest_and_caches_it(tmp_path):
     r = autotune.tune(s, workload, "t0-e13", cache_path=path, reps=2, key="gfx950/cu256/t0-e13")
     assert not r["from_cache"]
     assert r["tuning"]["chain_cap"] == 8 and r["tuning"]["emit_grid"] == 2048 and r["tuning"]["chain_grid"] == 0
+    assert r["tuning"]["tile_map_tiles"] == autotune.TILE_MAPS_NEVER
     assert s.t == r["tuning"] and s.t["graphs"] == 1
     assert len(calls) == 3 * len(r["tried"])  # one untimed run and reps timed ones per candidate
     # a second process with the same key: no runs, the same choice
