@@ -2041,7 +2041,8 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
     // flags, the chain after the first forced sample and the entries that
     // take no sample before it, from the summary pass.  Each wave reads them
     // one segment ahead.
-    const int pl_ = l < 5 ? SP_F0 + l : (l == 5 ? SP_FLG : (l < 18 ? SP_FN + (l - 6) : SP_F0));
+    // Lane 18: the segment's copy bytes.
+    const int pl_ = l < 5 ? SP_F0 + l : (l == 5 ? SP_FLG : (l < 18 ? SP_FN + (l - 6) : (l == 18 ? SP_AC : SP_F0)));
     // Segments the resolve pass left to this pass: BFL_CHAIN (follow the
     // chain, and count the copy and timer events if any) or BFL_AUX (count
     // those events only: the chain's results are the resolve pass's).
@@ -2128,6 +2129,11 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
                 aln[w] = *(gu32_t*)(p + 12);
                 afw[w] = *(gu32_t*)(p + 16);
             }
+            // A segment whose cumulative copy bytes cross no multiple of Tc
+            // holds no copy sample: no per-window prefix of the copy bytes.
+            const uint64_t c0u = (uint64_t)C0, c1u = c0u + (uint64_t)readlane64(pv, 18);
+            const bool csmp = D.tc_shift >= 0 ? (c1u >> D.tc_shift) != (c0u >> D.tc_shift)
+                                              : c1u / (uint64_t)D.Tc != c0u / (uint64_t)D.Tc;
             int64_t cc = C0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
@@ -2139,22 +2145,19 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
                 const bool cp = lok && kind == 1 && delta >= 0 && delta < MAX_ABS_DELTA;
                 const bool tm = lok && kind == 2 && delta >= 0 && delta <= (int64_t)0xFFFFFFFFll;
                 const int64_t dc = cp ? delta : 0;
-                const int64_t sc_ = wave_incl_sum(dc) + cc;
-                cc = readlane64(sc_, 63);
-                if (cp || tm) {
-                    int64_t v0 = D.q, v1 = delta;
-                    if (cp) {
-                        const uint64_t cout = (uint64_t)sc_, cin = cout - (uint64_t)dc;
-                        uint64_t nsmp;
-                        if (D.tc_shift >= 0)
-                            nsmp = (cout >> D.tc_shift) - (cin >> D.tc_shift);
-                        else
-                            nsmp = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
-                        v0 = (int64_t)(nsmp * (uint64_t)D.Tc);
-                        v1 = dc;
-                    }
-                    aux_add(ac, D, (uint32_t)t, line, cp, v0, v1);
+                int64_t vcs = 0;  // bytes of the copy samples this event triggers
+                if (csmp) {
+                    const int64_t sc_ = wave_incl_sum(dc) + cc;
+                    cc = readlane64(sc_, 63);
+                    const uint64_t cout = (uint64_t)sc_, cin = cout - (uint64_t)dc;
+                    uint64_t nsmp;
+                    if (D.tc_shift >= 0)
+                        nsmp = (cout >> D.tc_shift) - (cin >> D.tc_shift);
+                    else
+                        nsmp = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
+                    vcs = (int64_t)(nsmp * (uint64_t)D.Tc);
                 }
+                if (cp || tm) aux_add(ac, D, (uint32_t)t, line, cp, cp ? vcs : D.q, cp ? dc : delta);
             }
         }
 
