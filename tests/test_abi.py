@@ -71,6 +71,7 @@ def test_record_layouts_match_header():
     assert smp.SAMPLE_DTYPE.itemsize == 24 + 8  # 32-byte sample
     assert smp.TRACKED_DTYPE.itemsize == 16
     assert ctypes.sizeof(smp.Params) == 32
+    assert ctypes.sizeof(smp.Tuning) == 20  # five uint32 fields, as smp_tuning_t
 
 
 def test_report_lines_matches_oracle():

@@ -247,7 +247,8 @@ def tile_map_cases():
     n = 5 * 512 * 512 + 1234
     ev, kw = tg.config5(seed=51, n=n)
     c5 = dict(copy_threshold=kw["copy_threshold"], num_lines=kw["num_lines"], quantum_us=kw["quantum_us"])
-    out = [(f"c5mix T{T >> 20}M", ev, dict(threshold=T, **c5)) for T in (64 * tg.MiB, 16 * tg.MiB, 4 * tg.MiB)]
+    out = [(f"c5mix T{T >> 20}M", ev, dict(threshold=T, **c5))
+           for T in (64 * tg.MiB, 32 * tg.MiB, 16 * tg.MiB, 4 * tg.MiB)]
     big = ev.copy()
     i = 2 * 512 * 512 + 4321
     big["delta"][i] = 200 * tg.MiB
@@ -260,6 +261,27 @@ def tile_map_cases():
     drift["line"] = rng.integers(0, 5, drift.shape[0])
     for T in (3_000, 30_000):
         out.append((f"drift T{T}", drift, dict(threshold=T, num_lines=5)))
+    # A walk of +-50 steps reflected inside [-1000, 1000]: every segment
+    # moves above and below its start (two or more chains: SIM maps), the
+    # tile's extremes stop growing early (few sources) and stay far apart
+    # from 2T, so every tile's map keeps entries that never sample (U open).
+    # A sawtooth (+50, -50) has one chain per segment (CONST maps): no map.
+    n4 = 4 * 512 * 512 + 333
+    steps = np.where(np.random.default_rng(29).random(n4) < 0.5, 50, -50)
+    f, d = 0, np.empty(n4, dtype=np.int64)
+    for i, st in enumerate(steps.tolist()):
+        if not -1000 <= f + st <= 1000:
+            st = -st
+        d[i] = st
+        f += st
+    band = np.zeros(n4, dtype=tg.EVENT_DTYPE)
+    band["delta"] = d
+    band["ptr"] = np.arange(1, n4 + 1)
+    band["line"] = np.arange(n4) % 3
+    out.append(("band T1000000", band, dict(threshold=10 ** 6, num_lines=3)))
+    saw = band.copy()
+    saw["delta"] = np.where(np.arange(n4) % 2 == 0, 50, -50)
+    out.append(("saw T1000000", saw, dict(threshold=10 ** 6, num_lines=3)))
     mono = np.zeros(2 * 512 * 512 + 9, dtype=tg.EVENT_DTYPE)
     mono["delta"] = 1
     mono["ptr"] = np.arange(1, mono.shape[0] + 1)
@@ -283,6 +305,9 @@ def test_tile_maps(sampler):
         ntile = -(-cases[0][1].shape[0] // (512 * 512))
         assert mapped["c5mix T64M"] == (ntile, ntile)
         assert mapped["c5mix forced"][0] == ntile - 1 and mapped["c5mix forced"][1] == 2
+        nb = -(-(4 * 512 * 512 + 333) // (512 * 512))
+        assert mapped["band T1000000"] == (nb, nb)
+        assert mapped["saw T1000000"] == (0, 0)
         # (its two full tiles get no map; the short last one may)
         assert mapped["mono T1e6"][0] <= 1 and mapped["mono T1e6"][1] == 0
         check_batch(sampler, cases)
