@@ -259,9 +259,7 @@ SMP_API int sampler_last_pass_timing(smp_sampler_t *s, float *pass_ms);
  * exit was chained through tile maps before the resolve pass, words 7-10:
  * tiles of traces with tile maps that got none because a segment moves T or
  * more (or is not followed by chains), or because the tile needs more source
- * intervals, live chains or runs than a map holds, word 12: segments the
- * chain pass visits only to count their copy and timer events; the other
- * words are 0). */
+ * intervals, live chains or runs than a map holds; the other words are 0). */
 SMP_API int sampler_last_counters(smp_sampler_t *s, uint64_t *out32);
 
 /* Launch parameters of later runs.  None changes any result (every

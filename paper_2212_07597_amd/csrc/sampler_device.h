@@ -57,7 +57,6 @@ enum {
     NSPLANE
 };
 constexpr int64_t BFL_CHAIN = 8;
-constexpr int64_t BFL_AUX = 16;  // (with the resolve pass's results) copy and timer events left to the chain pass
 
 // Look-back status words of one tile (each: 2-bit state | 62-bit payload,
 // written once per run; stored plane by plane like the segment values).

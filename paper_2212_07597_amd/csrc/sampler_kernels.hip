@@ -107,56 +107,6 @@ __device__ __forceinline__ void hist_flush(HistCache<NS>& hc, const Desc* desc) 
     }
 }
 
-// Per-workgroup LDS cache of the copy and timer counters of up to
-// AUX_SLOTS (trace, line) keys (copy: sampled and exact bytes; timer: Python
-// and native time), larger than the general cache because these events are
-// many and their lines Zipf-spread; a slot held by another line sends the
-// update to global atomics.
-constexpr int AUX_SLOTS = 512;
-struct AuxCache {
-    unsigned long long key[AUX_SLOTS];
-    unsigned long long cnt[AUX_SLOTS][4];  // copy sampled, copy exact, Python time, native time
-};
-
-__device__ __forceinline__ void aux_init(AuxCache& ac) {
-    for (int i = threadIdx.x; i < AUX_SLOTS; i += blockDim.x) {
-        ac.key[i] = EMPTY_KEY;
-        for (int c = 0; c < 4; ++c) ac.cnt[i][c] = 0;
-    }
-}
-
-__device__ __forceinline__ void aux_add(AuxCache& ac, const Desc& D, uint32_t t, uint32_t line, bool copy, int64_t v0,
-                                        int64_t v1) {
-    const unsigned long long key = ((unsigned long long)t << 32) | line;
-    const uint32_t h = (line * 2654435761u) ^ (t * 0x9E3779B9u);
-    const int slot = (int)(h >> 23) & (AUX_SLOTS - 1);
-    unsigned long long k = ac.key[slot];
-    if (k == EMPTY_KEY) k = atomicCAS(&ac.key[slot], EMPTY_KEY, key);
-    const int c0 = copy ? 0 : 2;
-    if (k == EMPTY_KEY || k == key) {
-        if (v0) atomicAdd(&ac.cnt[slot][c0], (unsigned long long)v0);
-        if (v1) atomicAdd(&ac.cnt[slot][c0 + 1], (unsigned long long)v1);
-    } else {
-        const int h0 = copy ? H_CS : H_PT, h1 = copy ? H_CE : H_NT;
-        if (v0) g_add((uint64_t*)&D.hist[(size_t)h0 * D.L + line], (uint64_t)v0);
-        if (v1) g_add((uint64_t*)&D.hist[(size_t)h1 * D.L + line], (uint64_t)v1);
-    }
-}
-
-__device__ __forceinline__ void aux_flush(AuxCache& ac, const Desc* desc) {
-    static constexpr int planes[4] = {H_CS, H_CE, H_PT, H_NT};
-    for (int i = threadIdx.x; i < AUX_SLOTS; i += blockDim.x) {
-        const unsigned long long key = ac.key[i];
-        if (key == EMPTY_KEY) continue;
-        const Desc& D = desc[(uint32_t)(key >> 32)];
-        const uint32_t line = (uint32_t)key;
-        for (int c = 0; c < 4; ++c) {
-            const unsigned long long v = ac.cnt[i][c];
-            if (v) g_add((uint64_t*)&D.hist[(size_t)planes[c] * D.L + line], v);
-        }
-    }
-}
-
 // last trace whose first segment index is <= x
 __device__ __forceinline__ int find_trace_seg(const Desc* desc, int lo, int ntraces, uint64_t x) {
     int hi = ntraces - 1;
@@ -1543,7 +1493,7 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
     __shared__ int64_t w_sum[3][TWAVES];
     __shared__ int64_t s_pre[3];
     __shared__ int64_t w_peak[TWAVES], w_peakS[TWAVES];
-    __shared__ int w_left[TWAVES], w_aux[TWAVES];
+    __shared__ int w_left[TWAVES];
     __shared__ int64_t m_lo[TILE], m_hi[TILE], m_af[TILE], m_kf[TILE], m_ex[TILE];
     __shared__ int64_t m_R[TILE];  // sparse tiles: the footprint change before each segment
     __shared__ uint64_t w_tot[TWAVES], w_sim[TWAVES];  // valid lanes with TOTAL / SIM maps
@@ -1903,7 +1853,6 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
     uint32_t err = 0;
     int64_t pk = 0, pks = 0;
     bool left = false;  // left to the chain pass
-    bool auxonly = false;  // left to it for its copy and timer events only
     if (valid) {
         const int64_t af = sp[SP_AF * ns], ac = sp[SP_AC * ns];
         const int64_t mxf = sp[SP_MXF * ns], mnf = sp[SP_MNF * ns], mxp = sp[SP_MXP * ns], mnp = sp[SP_MNP * ns];
@@ -1922,11 +1871,9 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
         // sample before its first forced event (the prefix's only sample is
         // that event's, and from it on the chain is the summary pass's) or,
         // without a forced event, no sample at all.  Every other segment is
-        // left to the chain pass, and so are the copy and timer events of
-        // every segment (BFL_AUX: counted by the chain pass without a walk).
+        // left to the chain pass.  (Copy and timer events are counted by the
+        // emit pass.)
         const int fn = (int)sp[SP_FN * ns];
-        const bool aux = (sp[SP_FLG * ns] & 4) != 0;
-        const int64_t xaux = aux ? BFL_AUX : 0;
         if (fn < 0 && ef >= lo && ef <= hi) {
             // no forced event and an entry inside the no-sample interval:
             // the segment takes no sample
@@ -1935,7 +1882,7 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
             o[SP_BGI * ns] = 0;
             o[SP_BGP * ns] = 0;
             o[SP_LSV * ns] = 0;
-            o[SP_BFL * ns] = xaux;
+            o[SP_BFL * ns] = 0;
             SMP_GLOBAL uint64_t* mk = gp(D.mask) + j * NW;
 #pragma unroll
             for (int w = 0; w < NW; ++w) mk[w] = 0;
@@ -1963,7 +1910,7 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
             o[SP_BGI * ns] = hg ? a + gnode : 0;
             o[SP_BGP * ns] = hg ? (int64_t)(uint32_t)record(D, a + gnode)[1] : 0;
             o[SP_LSV * ns] = P0 + lsrel;
-            o[SP_BFL * ns] = (hg ? 1 : 0) | 2 | xaux;
+            o[SP_BFL * ns] = (hg ? 1 : 0) | 2;
             // windows before the forced one hold no sample (as the summary
             // pass wrote); the forced window gains the forced sample
             gp(D.mask)[j * NW + (fn >> 6)] = (1ull << (fn & 63)) | (uint64_t)sp[SP_AMF * ns];
@@ -1971,33 +1918,28 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(4))) void 
             o[SP_BFL * ns] = BFL_CHAIN;
             left = true;
         }
-        auxonly = aux && !left;
     }
     if (ballot(err != 0) && l == 0) g_or32(&D.scal->err, 2u);
     const int nleft = __popcll(ballot(left));
-    const int naux = __popcll(ballot(auxonly));
     pk = wave_max(pk);
     pks = wave_max(pks);
     if (l == 0) {
         w_peak[wv] = pk;
         w_peakS[wv] = pks;
         w_left[wv] = nleft;
-        w_aux[wv] = naux;
     }
     __syncthreads();
     if (tid == 0) {
         int64_t p = 0, q = 0;
-        uint64_t c = 0, ca = 0;
+        uint64_t c = 0;
         for (int w = 0; w < TWAVES; ++w) {
             p = w_peak[w] > p ? w_peak[w] : p;
             q = w_peakS[w] > q ? w_peakS[w] : q;
             c += (uint64_t)w_left[w];
-            ca += (uint64_t)w_aux[w];
         }
         if (p > 0) g_max(&D.scal->peak_F, (int64_t)p);
         if (q > 0) g_max(&D.scal->peak_S, (int64_t)q);
         if (c) g_add((uint64_t*)&ctl[4], c);
-        if (ca) g_add((uint64_t*)&ctl[12], ca);
     }
 }
 
@@ -2029,9 +1971,6 @@ __device__ __forceinline__ void load_head(const Desc& D, int64_t j, ChainHead& h
 // entry offset; record its samples, count, best growth sample and the Python
 // footprint at its last sample.  Copy and timer events are counted here.
 __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, int ntraces, uint64_t nseg_total) {
-    __shared__ AuxCache ac;
-    aux_init(ac);
-    __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int l = lane_id();
     int cur_t = 0;
@@ -2041,53 +1980,42 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
     // flags, the chain after the first forced sample and the entries that
     // take no sample before it, from the summary pass.  Each wave reads them
     // one segment ahead.
-    // Lane 18: the segment's copy bytes.
-    const int pl_ = l < 5 ? SP_F0 + l : (l == 5 ? SP_FLG : (l < 18 ? SP_FN + (l - 6) : (l == 18 ? SP_AC : SP_F0)));
-    // Segments the resolve pass left to this pass: BFL_CHAIN (follow the
-    // chain, and count the copy and timer events if any) or BFL_AUX (count
-    // those events only: the chain's results are the resolve pass's).
+    const int pl_ = l < 5 ? SP_F0 + l : (l == 5 ? SP_FLG : (l < 18 ? SP_FN + (l - 6) : SP_F0));
     // Only the segments the resolve pass left to this pass, grid-stride:
     // each wave reads the flags of its next 64 segments in one load (lane i:
     // the i-th) and visits the marked ones.
     const uint64_t stride = (uint64_t)gridDim.x * WAVES;
     uint64_t gb = (uint64_t)blockIdx.x * WAVES + wv, cur_gb = 0;
-    uint64_t pend = 0;   // marked segments among the last 64 read, not yet taken
-    uint64_t pwalk = 0;  // those of them whose chain is followed
-    int hint = 0;        // a trace at or before the wave's next segment
-    bool nwalk = false;  // (next_marked's segment is followed)
+    uint64_t pend = 0;  // marked segments among the last 64 read, not yet taken
+    int hint = 0;       // a trace at or before the wave's next segment
     auto next_marked = [&]() -> uint64_t {
         while (!pend) {
             if (gb >= nseg_total) return nseg_total;
             hint = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, hint, ntraces, gb));
             const uint64_t x = gb + (uint64_t)l * stride;
-            int64_t bf = 0;
+            bool mk = false;
             if (x < nseg_total) {
                 const Desc& Dx = desc[find_trace_seg(desc, hint, ntraces, x)];
-                bf = seg_val(Dx, SP_BFL, (int64_t)(x - Dx.seg_begin));
+                mk = seg_val(Dx, SP_BFL, (int64_t)(x - Dx.seg_begin)) == BFL_CHAIN;
             }
-            pend = ballot((bf & (BFL_CHAIN | BFL_AUX)) != 0);
-            pwalk = ballot((bf & BFL_CHAIN) != 0);
+            pend = ballot(mk);
             cur_gb = gb;
             gb += 64 * stride;
         }
         const int i = ctz64(pend);
         pend &= pend - 1;
-        nwalk = (pwalk >> i) & 1;
         return cur_gb + (uint64_t)i * stride;
     };
     uint64_t g = next_marked();
-    bool walk_next = nwalk;
     int64_t pv_next = 0;
-    ChainHead hd;  // the head of the wave's next followed segment
+    ChainHead hd;  // the head of the wave's next segment
     if (g < nseg_total) {
         const Desc& D0 = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, 0, ntraces, g))];
         pv_next = seg_val(D0, pl_, (int64_t)(g - D0.seg_begin));
-        if (walk_next) load_head(D0, (int64_t)(g - D0.seg_begin), hd);
+        load_head(D0, (int64_t)(g - D0.seg_begin), hd);
     }
     for (uint64_t gn; g < nseg_total; g = gn) {
         gn = next_marked();
-        const bool walk = walk_next;
-        walk_next = nwalk;
         const int t = __builtin_amdgcn_readfirstlane(find_trace_seg(desc, cur_t, ntraces, g));
         if (t != cur_t && have_t && l == 0 && peakS > 0)
             g_max(&desc[cur_t].scal->peak_S, (int64_t)peakS);
@@ -2107,62 +2035,11 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
             const uint64_t gq = gn < nseg_total ? gn : g;
             const Desc& Dn = desc[__builtin_amdgcn_readfirstlane(find_trace_seg(desc, t, ntraces, gq))];
             pv_next = seg_val(Dn, pl_, (int64_t)(gq - Dn.seg_begin));
-            if (walk_next) load_head(Dn, (int64_t)(gq - Dn.seg_begin), hd);
+            load_head(Dn, (int64_t)(gq - Dn.seg_begin), hd);
         }
-        const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), C0 = readlane64(pv, 2);
+        const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1);
         const int64_t eF = readlane64(pv, 3), xF = readlane64(pv, 4);
-        const int64_t flg = readlane64(pv, 5);
         const int fn = (int)readlane64(pv, 6);
-        // Copy volume (section 3.5: one Tc sample per multiple of Tc crossed by
-        // the cumulative copy bytes) and the timer split (section 2.1: Python
-        // time += quantum, native time += delay).  Only segments that hold such
-        // events re-read their records here.
-        if (flg & 4) {
-            // every window's words loaded before the first use
-            gu8_t* base = (gu8_t*)(D.ev + (size_t)a * 24);  // wave-uniform
-            uint64_t ad[NW];
-            uint32_t aln[NW], afw[NW];
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                gu8_t* p = record_addr(base, nv, w);
-                ad[w] = *(gu64_t*)p;
-                aln[w] = *(gu32_t*)(p + 12);
-                afw[w] = *(gu32_t*)(p + 16);
-            }
-            // A segment whose cumulative copy bytes cross no multiple of Tc
-            // holds no copy sample: no per-window prefix of the copy bytes.
-            const uint64_t c0u = (uint64_t)C0, c1u = c0u + (uint64_t)readlane64(pv, 18);
-            const bool csmp = D.tc_shift >= 0 ? (c1u >> D.tc_shift) != (c0u >> D.tc_shift)
-                                              : c1u / (uint64_t)D.Tc != c0u / (uint64_t)D.Tc;
-            int64_t cc = C0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const int k = w * 64 + l;
-                const int64_t delta = (int64_t)ad[w];
-                const uint32_t line = aln[w];
-                const uint32_t kind = (afw[w] >> 1) & 3;
-                const bool lok = k < nv && line < D.L;
-                const bool cp = lok && kind == 1 && delta >= 0 && delta < MAX_ABS_DELTA;
-                const bool tm = lok && kind == 2 && delta >= 0 && delta <= (int64_t)0xFFFFFFFFll;
-                const int64_t dc = cp ? delta : 0;
-                int64_t vcs = 0;  // bytes of the copy samples this event triggers
-                if (csmp) {
-                    const int64_t sc_ = wave_incl_sum(dc) + cc;
-                    cc = readlane64(sc_, 63);
-                    const uint64_t cout = (uint64_t)sc_, cin = cout - (uint64_t)dc;
-                    uint64_t nsmp;
-                    if (D.tc_shift >= 0)
-                        nsmp = (cout >> D.tc_shift) - (cin >> D.tc_shift);
-                    else
-                        nsmp = cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
-                    vcs = (int64_t)(nsmp * (uint64_t)D.Tc);
-                }
-                if (cp || tm) aux_add(ac, D, (uint32_t)t, line, cp, cp ? vcs : D.q, cp ? dc : delta);
-            }
-        }
-
-        if (!walk) continue;  // (the chain's results are the resolve pass's)
-
         // The pointer of the summary pass's best growth sample after the forced
         // event, loaded now (it is the segment's best unless the walk below
         // finds a larger one before the forced event).
@@ -2277,8 +2154,6 @@ __global__ __launch_bounds__(BLOCK) void k_chain(const Desc* __restrict__ desc, 
         if (err && l == 0) g_or32(&D.scal->err, err);
     }
     if (have_t && l == 0 && peakS > 0) g_max(&desc[cur_t].scal->peak_S, (int64_t)peakS);
-    __syncthreads();
-    aux_flush(ac, desc);
 }
 
 // --------------------------------------------------------------- scan pass
@@ -2439,14 +2314,16 @@ __device__ __forceinline__ void flush_stage(const Desc& D, uint32_t t, const Sam
 }
 
 // What the emit pass loads for a segment: its records, its plane values
-// (lanes 0-3: F0, P0, C0 (unused), entry offset; lanes 4-9: the scan state
-// before the segment) and its sample masks (lane w: window w).
+// (lanes 0-3: F0, P0, C0, entry offset; lanes 4-9: the scan state before
+// the segment; lane 18: its copy bytes; lane 19: its summary flags) and its
+// sample masks (lane w: window w).
 // The emit pass carries each window's records from one segment to the next
 // as one 16-byte vector (delta, pointer, line) and the flags word: the
 // registers a refill load writes are then the ones the next segment reads,
 // with no copy (a copy would wait for the load).  pv holds, on lanes 0-3,
-// F0, P0, C0 (unused) and the entry offset, on lanes 4-9 the scan state
-// before the segment, and on lanes 10-17 the sample masks of windows 0-7.
+// F0, P0, C0 and the entry offset, on lanes 4-9 the scan state before the
+// segment, on lanes 10-17 the sample masks of windows 0-7, on lane 18 the
+// segment's copy bytes and on lane 19 its summary flags.
 typedef uint32_t v4u32 __attribute__((ext_vector_type(4), aligned(8)));
 typedef const __attribute__((address_space(1))) v4u32 gv4u32_t;
 
@@ -2470,9 +2347,9 @@ struct EmitSeg {
 
 __device__ __forceinline__ void emit_fetch_meta(const Desc& D, int64_t j, EmitIn& in) {
     const int l = lane_id();
-    const int pl = l < 4 ? SP_F0 + (l == 3 ? SP_EF - SP_F0 : l) : SP_XCNT + (l - 4);
-    gi64_t* src = l < 10 ? (gi64_t*)D.seg + (int64_t)pl * (int64_t)D.nseg + j
-                         : (gi64_t*)D.mask + j * NW + ((l - 10) & (NW - 1));
+    const int pl = l < 4 ? SP_F0 + (l == 3 ? SP_EF - SP_F0 : l) : (l == 18 ? SP_AC : (l == 19 ? SP_FLG : SP_XCNT + (l - 4)));
+    gi64_t* src = (l < 10 || l == 18 || l == 19) ? (gi64_t*)D.seg + (int64_t)pl * (int64_t)D.nseg + j
+                                                 : (gi64_t*)D.mask + j * NW + ((l - 10) & (NW - 1));
     in.pv = *src;
 }
 
@@ -2492,6 +2369,21 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, cons
     const Desc& Dn = desc[sn.t];
     gu8_t* nbase = (gu8_t*)(Dn.ev + (size_t)(sn.j * SEG) * 24);  // wave-uniform
     const int64_t F0 = readlane64(pv, 0), P0 = readlane64(pv, 1), eF = readlane64(pv, 3);
+    // Copy volume (section 3.5: one Tc sample per multiple of Tc crossed by
+    // the cumulative copy bytes) and the timer split (section 2.1: Python
+    // time += quantum, native time += delay) go to the lines' counters here.
+    // Only a segment that holds such events (summary flag bit 2) looks for
+    // them, and only one whose copy bytes cross a multiple of Tc holds a copy
+    // sample and scans its copy bytes.
+    const bool has_aux = (readlane64(pv, 19) & 4) != 0;
+    int64_t cc = 0;
+    bool csmp = false;
+    if (has_aux) {
+        cc = readlane64(pv, 2);
+        const uint64_t c0u = (uint64_t)cc, c1u = c0u + (uint64_t)readlane64(pv, 18);
+        csmp = D.tc_shift >= 0 ? (c1u >> D.tc_shift) != (c0u >> D.tc_shift)
+                               : c1u / (uint64_t)D.Tc != c0u / (uint64_t)D.Tc;
+    }
     int64_t base = readlane64(pv, 4);
     const int64_t hv = readlane64(pv, 5);
     const uint32_t hidx = (uint32_t)readlane64(pv, 6), hptr = (uint32_t)readlane64(pv, 7);
@@ -2600,6 +2492,30 @@ __device__ __forceinline__ void emit_segment(const Desc* __restrict__ desc, cons
             }
             cnt += __popcll(m);
             staged += __popcll(m);
+        }
+        // the window's copy and timer events (validated as in the summary pass)
+        if (has_aux) {
+            const uint32_t kind = (fl >> 1) & 3u;
+            const uint64_t r0 = ((uint64_t)in.q[w].y << 32) | in.q[w].x;
+            const uint32_t line = in.q[w].w;
+            const bool lok = k < nv && line < D.L;
+            const bool cp = lok && kind == 1u && r0 < (uint64_t)MAX_ABS_DELTA;
+            const bool tm = lok && kind == 2u && (r0 >> 32) == 0;
+            if (ballot(cp || tm)) {
+                int64_t vcs = 0;  // bytes of the copy samples this event triggers
+                if (csmp) {
+                    const int64_t dc = cp ? (int64_t)r0 : 0;
+                    const int64_t sc_ = wave_incl_sum(dc) + cc;
+                    cc = readlane64(sc_, 63);
+                    const uint64_t cout = (uint64_t)sc_, cin = cout - (uint64_t)dc;
+                    const uint64_t nsmp = D.tc_shift >= 0 ? (cout >> D.tc_shift) - (cin >> D.tc_shift)
+                                                          : cout / (uint64_t)D.Tc - cin / (uint64_t)D.Tc;
+                    vcs = (int64_t)(nsmp * (uint64_t)D.Tc);
+                }
+                if (cp || tm)
+                    hist_add(hc, D, (uint32_t)t, line, cp ? C_CS : C_PT, cp ? vcs : D.q, cp ? C_CE : C_NT, (int64_t)r0,
+                             -1, 0, -1, 0);
+            }
         }
         // this window's registers take the next segment's window w (after
         // their last use here, so no copies and no early wait)
