@@ -35,6 +35,12 @@ namespace {
 
 constexpr uint64_t ALIGN = 256;
 constexpr int RUN_SLOTS = 8;
+// Launches alternate between two streams created together, so that two
+// launches in flight sit on two hardware queues and overlap on the device.
+// The runtime spreads streams over a small pool of hardware queues (four by
+// default); with a stream per run slot, two slots' streams could share a
+// queue, and launches on one queue never overlap.
+constexpr int LAUNCH_STREAMS = 2;
 constexpr int MAX_TRACES_PER_RUN = 4096;
 constexpr uint64_t CBLK_WORDS = 256;
 constexpr int NPASS = 5;  // summarize, resolve, chain, scan, emit
@@ -178,7 +184,7 @@ struct RunSlot {
     Scalars* host_scal_dev = nullptr;  // its device address
     std::vector<uint64_t> ids;     // the launch's traces, in descriptor order
     unsigned long long* dev_ticket = nullptr;
-    hipStream_t stream = nullptr;  // launches of this slot; ordered after the caller's stream
+    hipStream_t stream = nullptr;  // the slot's current launch (one of the sampler's launch streams)
     hipEvent_t e_ready = nullptr;  // recorded on the caller's stream at run()
     hipEvent_t e_start = nullptr, e_end = nullptr;
     hipEvent_t e_pass[NPASS + 1] = {};  // around each pass of the sampling kernels
@@ -205,6 +211,8 @@ struct smp_sampler {
     std::map<uint64_t, uint64_t> free_list;  // offset -> size
     std::map<uint64_t, TraceRec> traces;
     RunSlot slots[RUN_SLOTS];
+    hipStream_t streams[LAUNCH_STREAMS] = {};  // launches, ordered after the caller's stream
+    int next_stream = 0;
     uint64_t next_id = 1;
     uint64_t run_seq = 0;
     int grid_chain = 0, grid_emit = 0, grid_track = 0;
@@ -351,6 +359,13 @@ int sampler_create(int device, void* hip_stream, uint64_t mem_budget, void* work
         delete s;
         return SMP_EDEVICE;
     }
+    for (auto& st : s->streams) {
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            st = nullptr;
+            sampler_destroy(s);
+            return SMP_EDEVICE;
+        }
+    }
     for (int i = 0; i < RUN_SLOTS; ++i) {
         RunSlot& r = s->slots[i];
         uint8_t* base = s->ws + i * slot_bytes();
@@ -360,7 +375,6 @@ int sampler_create(int device, void* hip_stream, uint64_t mem_budget, void* work
             hipHostMalloc((void**)&r.host_scal, sizeof(Scalars) * MAX_TRACES_PER_RUN, hipHostMallocCoherent) !=
                 hipSuccess ||
             hipHostGetDevicePointer((void**)&r.host_scal_dev, r.host_scal, 0) != hipSuccess ||
-            hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&r.e_ready, hipEventDisableTiming) != hipSuccess ||
             hipEventCreate(&r.e_start) != hipSuccess || hipEventCreate(&r.e_end) != hipSuccess ||
             !(r.last_desc = new (std::nothrow) Desc[MAX_TRACES_PER_RUN])) {
@@ -396,7 +410,6 @@ void sampler_destroy(smp_sampler_t* s) {
         delete[] r.last_desc;
         r.last_desc = nullptr;
         if (r.host_scal) (void)hipHostFree(r.host_scal);
-        if (r.stream) (void)hipStreamDestroy(r.stream);
         if (r.e_ready) (void)hipEventDestroy(r.e_ready);
         if (r.e_start) (void)hipEventDestroy(r.e_start);
         for (auto& e : r.e_pass)
@@ -404,6 +417,8 @@ void sampler_destroy(smp_sampler_t* s) {
         if (r.e_end) (void)hipEventDestroy(r.e_end);
         if (r.gexec) (void)hipGraphExecDestroy(r.gexec);
     }
+    for (auto& st : s->streams)
+        if (st) (void)hipStreamDestroy(st);
     delete s;
 }
 
@@ -561,6 +576,8 @@ int run(smp_sampler_t* s, int blocking) {
         }
         RunSlot& r = s->slots[si];
         if (int rc = retire_slot(s, r)) return rc;
+        r.stream = s->streams[s->next_stream];
+        s->next_stream = (s->next_stream + 1) % LAUNCH_STREAMS;
         uint64_t seg = 0, tile = 0, blk = 0, zero = 0, lines = 0;
         r.ids.clear();
         for (size_t k = 0; k < cnt; ++k) {
