@@ -197,9 +197,10 @@ SMP_API int submit_traces(smp_sampler_t *s, uint32_t count, const smp_event_t *c
                           const smp_params_t *params, int ev_on_device, uint64_t *trace_ids, uint32_t *submitted);
 
 /* Launch every submitted, not yet launched trace as one batch (each pass of
- * the launch sequence covers the segments of all of them).  The launch runs on one of the
- * sampler's internal streams, ordered after all work queued so far on the
- * caller's stream, so consecutive batches may overlap on the device.
+ * the launch sequence covers the segments of all of them).  Launches
+ * alternate between the sampler's two internal streams, each ordered after
+ * all work queued so far on the caller's stream, so two consecutive batches
+ * may overlap on the device (a third queues behind the first). 
  * blocking = 1 waits for completion. */
 SMP_API int run(smp_sampler_t *s, int blocking);
 

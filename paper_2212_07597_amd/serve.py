@@ -7,8 +7,9 @@ The loop:
   (``submit_trace`` returns SMP_EBUDGET otherwise; the request waits, and it is
   rejected for good on SMP_ETOOBIG);
 * launches every admitted, not yet launched request as one batch whenever
-  fewer than ``max_inflight`` batches are on the GPU.  Each batch runs on its
-  own stream, so a batch that arrives while others run overlaps with them;
+  fewer than ``max_inflight`` batches are on the GPU.  Consecutive launches
+  go to the library's two launch streams, so a batch that arrives while
+  another runs overlaps with it;
 * fetches finished requests, which frees their workspace and admits waiting
   ones.
 
