@@ -200,7 +200,7 @@ SMP_API int submit_traces(smp_sampler_t *s, uint32_t count, const smp_event_t *c
  * the launch sequence covers the segments of all of them).  Launches
  * alternate between the sampler's two internal streams, each ordered after
  * all work queued so far on the caller's stream, so two consecutive batches
- * may overlap on the device (a third queues behind the first). 
+ * may overlap on the device (a third queues behind the first).
  * blocking = 1 waits for completion. */
 SMP_API int run(smp_sampler_t *s, int blocking);
 
