@@ -360,9 +360,10 @@ def main():
 
 def bench_e2e(smp, torch, np, s, ev, params, K, reps=3):
     """End to end on the headline trace: events in pinned host memory copied
-    to HBM (submit_trace), the launch, and the whole profile copied back
-    (fetch_profile: samples, tracked list, per-line arrays).  Phases are
-    timed one after another with a wait between them; median of reps."""
+    to HBM (submit_trace), the launch, and the whole profile copied back into
+    pinned host arrays (fetch_profile: samples, tracked list, per-line
+    arrays).  Phases are timed one after another with a wait between them;
+    median of reps."""
     log("end to end (pinned host events, full profile fetch)")
     host = torch.from_numpy(ev.view(np.uint8)).pin_memory()
     rows = []
@@ -374,7 +375,7 @@ def bench_e2e(smp, torch, np, s, ev, params, K, reps=3):
         t1 = time.perf_counter()
         s.run(blocking=True)
         t2 = time.perf_counter()
-        prof = s.fetch_profile(tid)
+        prof = s.fetch_profile(tid, pinned=True)
         t3 = time.perf_counter()
         if prof["status"] != smp.SMP_OK or prof["K"] != K:
             raise RuntimeError("end-to-end profile differs from the device-resident one")
@@ -382,7 +383,7 @@ def bench_e2e(smp, torch, np, s, ev, params, K, reps=3):
     rows = rows[1:]  # the first pass warms the pinned pages and the copy engines
     med = [statistics.median(r[i] for r in rows) * 1e3 for i in range(4)]
     n = len(ev)
-    return {"workload": "config2, events in pinned host memory; H2D + run + fetch of the whole profile",
+    return {"workload": "config2, events in pinned host memory; H2D + run + fetch of the whole profile into pinned host arrays",
             "h2d_ms": round(med[0], 3), "run_ms": round(med[1], 3), "fetch_ms": round(med[2], 3),
             "ms": round(med[3], 3), "events_per_s": round(n / (med[3] * 1e-3), 1),
             "h2d_gbs": round(BYTES_PER_EVENT * n / (med[0] * 1e-3) / 1e9, 1), "reps": reps}

@@ -86,6 +86,18 @@ class Tuning(ctypes.Structure):
     ]
 
 
+def _host_array(shape, dtype, pinned):
+    """An uninitialised host array; with ``pinned``, a view of a page-locked
+    torch buffer (the array keeps the buffer alive)."""
+    dtype = np.dtype(dtype)
+    if not pinned:
+        return np.empty(shape, dtype)
+    import torch
+    count = int(np.prod(shape, dtype=np.int64))
+    buf = torch.empty(max(count * dtype.itemsize, 1), dtype=torch.uint8, pin_memory=True)
+    return buf.numpy()[: count * dtype.itemsize].view(dtype).reshape(shape)
+
+
 class SamplerError(RuntimeError):
     def __init__(self, fn, code):
         super().__init__(f"{fn} failed: {code} ({error_string(code)})")
@@ -391,15 +403,19 @@ class Sampler:
         _check("poll", rc)
         return True
 
-    def fetch_profile(self, trace_id) -> dict:
+    def fetch_profile(self, trace_id, pinned=False) -> dict:
+        """The trace's whole profile as numpy arrays (and release of the trace).
+        With ``pinned`` the arrays live in page-locked host memory from torch's
+        pinned allocator, which the device copies into directly instead of
+        through staging buffers (for large profiles fetched repeatedly)."""
         sizes = ProfileSizes()
         _check("fetch_profile", lib().fetch_profile(self.h, int(trace_id), ctypes.byref(sizes), None))
         K, H, L = int(sizes.n_samples), int(sizes.n_tracked), int(sizes.num_lines)
-        samples = np.empty(K, SAMPLE_DTYPE)
-        tracked = np.empty(H, TRACKED_DTYPE)
-        hist = np.empty((len(HIST_NAMES), L), np.int64)
-        leak = np.empty((len(LEAK_NAMES), L), np.int64)
-        gates = np.empty((len(GATE_NAMES), L), np.uint8)
+        samples = _host_array(K, SAMPLE_DTYPE, pinned)
+        tracked = _host_array(H, TRACKED_DTYPE, pinned)
+        hist = _host_array((len(HIST_NAMES), L), np.int64, pinned)
+        leak = _host_array((len(LEAK_NAMES), L), np.int64, pinned)
+        gates = _host_array((len(GATE_NAMES), L), np.uint8, pinned)
         out = Profile(samples.ctypes.data if K else None, tracked.ctypes.data if H else None, hist.ctypes.data,
                       leak.ctypes.data, gates.ctypes.data)
         _check("fetch_profile", lib().fetch_profile(self.h, int(trace_id), ctypes.byref(sizes), ctypes.byref(out)))

@@ -555,6 +555,21 @@ def test_device_resident_events(sampler):
     compare(sampler.fetch_profile(tid), oracle.run(ev, threshold=tg.MiB, num_lines=64))
 
 
+def test_pinned_fetch(sampler):
+    """A profile fetched into page-locked arrays equals the oracle (and so
+    the pageable fetch), including a trace with no samples."""
+    say("pinned fetch")
+    ev, _ = tg.config1(seed=9)
+    flat = np.zeros(1000, dtype=tg.EVENT_DTYPE)
+    flat["ptr"] = np.arange(1, 1001)
+    cases = [("c1 s9", ev, dict(threshold=tg.MiB, num_lines=64)), ("flat", flat, dict(threshold=tg.MiB, num_lines=4))]
+    ids = [sampler.submit_trace(e, smp.make_params(kw["threshold"], kw["num_lines"])) for _, e, kw in cases]
+    sampler.run(blocking=True)
+    for (label, e, kw), tid in zip(cases, ids):
+        g = sampler.fetch_profile(tid, pinned=True)
+        compare(g, oracle.run(e, **kw), label + " pinned")
+
+
 def test_config3_batch(sampler):
     say("config 3: 1024 traces in one launch")
     plan = tg.config3_plan()
